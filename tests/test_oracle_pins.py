@@ -1,0 +1,286 @@
+"""Pins for the CPU oracle of Eq. (1): each fixes it against something other
+than itself (exact arithmetic, textbook special cases, closed forms and
+invariances), so that a dropped term, a wrong sign or index or a transposed
+operand in the oracle fails at least one of them.  CPU only."""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import GLSOracle, gls_literal
+from oracle import gls as oracle_gls
+from paper_1304_2272_amd import synth
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def _spd(n, rng, cond=30.0):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.geomspace(1.0, cond, n)
+    return (Q * ev) @ Q.T
+
+
+def _problem(n, p, m, seed):
+    rng = np.random.default_rng(seed)
+    M = _spd(n, rng)
+    XL = np.column_stack([np.ones(n), rng.standard_normal((n, p - 2))])
+    y = rng.standard_normal(n)
+    XR = rng.integers(0, 3, size=(m, n)).astype(np.float64)
+    return M, XL, y, XR
+
+
+# -- P1: exact rational arithmetic -------------------------------------------
+
+def _frac_solve(A, B):
+    """Gauss-Jordan over Fractions: A^-1 B exactly (A square, nonsingular)."""
+    n = len(A)
+    k = len(B[0])
+    aug = [list(A[i]) + list(B[i]) for i in range(n)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if aug[r][c] != 0)
+        aug[c], aug[piv] = aug[piv], aug[c]
+        pv = aug[c][c]
+        aug[c] = [v / pv for v in aug[c]]
+        for r in range(n):
+            if r != c and aug[r][c] != 0:
+                f = aug[r][c]
+                aug[r] = [vr - f * vc for vr, vc in zip(aug[r], aug[c])]
+    return [row[n:n + k] for row in aug]
+
+
+def _frac_T(A):
+    return [list(r) for r in zip(*A)]
+
+
+def _frac_mm(A, B):
+    return [[sum(a * b for a, b in zip(row, col)) for col in zip(*B)] for row in A]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p1_exact_rationals(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, p, m = 7, 3, 4
+    A = rng.integers(-3, 4, size=(n, n))
+    M = A.T @ A + np.eye(n, dtype=np.int64)          # integer SPD
+    XL = np.column_stack([np.ones(n, dtype=np.int64), rng.integers(-4, 5, size=n)])
+    y = rng.integers(-9, 10, size=n)
+    XR = rng.integers(0, 3, size=(m, n))
+    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    Mf = [[Fraction(int(v)) for v in row] for row in M]
+    for i in range(m):
+        Xi = [[Fraction(int(XL[r, 0])), Fraction(int(XL[r, 1])), Fraction(int(XR[i, r]))] for r in range(n)]
+        Af = _frac_solve(Mf, Xi)                      # M^-1 X_i
+        N = _frac_mm(_frac_T(Xi), Af)                 # X_i^T M^-1 X_i
+        yc = [[Fraction(int(v))] for v in y]
+        rhs = _frac_mm(_frac_T(Af), yc)               # X_i^T M^-1 y
+        bex = [row[0] for row in _frac_solve(N, rhs)]
+        Ninv = _frac_solve(N, [[Fraction(int(r == c)) for c in range(p)] for r in range(p)])
+        assert info[i] == 0
+        assert _rel(b[i, 0], [float(v) for v in bex]) < 1e-13
+        assert abs(var[i] - float(Ninv[p - 1][p - 1])) <= 1e-13 * abs(float(Ninv[p - 1][p - 1]))
+
+
+# -- P2: explicit inverse by Gauss-Jordan (no factorisation reuse) -----------
+
+def _gauss_jordan_inverse(M):
+    n = M.shape[0]
+    aug = np.hstack([M.astype(np.float64), np.eye(n)])
+    for c in range(n):
+        piv = c + int(np.argmax(np.abs(aug[c:, c])))
+        aug[[c, piv]] = aug[[piv, c]]
+        aug[c] /= aug[c, c]
+        for r in range(n):
+            if r != c:
+                aug[r] -= aug[r, c] * aug[c]
+    return aug[:, n:]
+
+
+def test_p2_explicit_inverse():
+    M, XL, y, XR = _problem(40, 4, 25, seed=3)
+    Minv = _gauss_jordan_inverse(M)
+    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    for i in range(XR.shape[0]):
+        Xi = np.column_stack([XL, XR[i]])
+        N = Xi.T @ Minv @ Xi
+        ref = np.linalg.solve(N, Xi.T @ Minv @ y)
+        assert _rel(b[i, 0], ref) < 1e-11
+        assert abs(var[i] - np.linalg.inv(N)[-1, -1]) < 1e-11 * abs(var[i])
+
+
+# -- P3: QR-based GLS through symmetric whitening (Section 2's alternative) --
+
+def test_p3_qr_whitening():
+    M, XL, y, XR = _problem(60, 5, 20, seed=4)
+    w, V = np.linalg.eigh(M)
+    Wh = (V / np.sqrt(w)) @ V.T                        # M^{-1/2}, symmetric
+    b, _, _ = GLSOracle(M, XL, y).solve(XR)
+    for i in range(XR.shape[0]):
+        Xi = np.column_stack([XL, XR[i]])
+        Q, R = np.linalg.qr(Wh @ Xi)
+        ref = np.linalg.solve(R, Q.T @ (Wh @ y))
+        assert _rel(b[i, 0], ref) < 1e-10
+
+
+# -- P4: planted coefficients, noise-free (fixes bbar_T = X_L^T ybar) -------
+
+@pytest.mark.parametrize("p", [2, 4, 8])
+def test_p4_planted_b(p):
+    prob = synth.make_problem(300, p, seed=11, noise=False)
+    XR = synth.snp_block(300, 11, 0, 50)
+    beta = prob["beta"][:, 0]
+    b, _, info = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert (info == 0).all()
+    want = np.concatenate([beta, [0.0]])
+    assert np.max(np.abs(b[:, 0, :] - want)) < 1e-10 * max(1.0, np.max(np.abs(beta)))
+    # plant a SNP effect on SNP k
+    k, gamma = 17, 0.75
+    y2 = prob["Y"][:, 0] + gamma * XR[k]
+    b2, _, _ = GLSOracle(prob["M"], prob["XL"], y2).solve(XR[k:k + 1])
+    assert np.max(np.abs(b2[0, 0] - np.concatenate([beta, [gamma]]))) < 1e-10
+
+
+# -- P5: M = I gives OLS; M = diag(1/w) gives weighted least squares --------
+
+def test_p5_ols_and_wls():
+    rng = np.random.default_rng(5)
+    n, p, m = 80, 4, 12
+    XL = np.column_stack([np.ones(n), rng.standard_normal((n, p - 2))])
+    y = rng.standard_normal(n)
+    XR = rng.integers(0, 3, size=(m, n)).astype(np.float64)
+    b, _, _ = GLSOracle(np.eye(n), XL, y).solve(XR)
+    w = rng.uniform(0.2, 5.0, n)
+    bw, _, _ = GLSOracle(np.diag(1.0 / w), XL, y).solve(XR)
+    for i in range(m):
+        Xi = np.column_stack([XL, XR[i]])
+        ref = np.linalg.lstsq(Xi, y, rcond=None)[0]
+        assert _rel(b[i, 0], ref) < 1e-12
+        sw = np.sqrt(w)
+        refw = np.linalg.lstsq(Xi * sw[:, None], y * sw, rcond=None)[0]
+        assert _rel(bw[i, 0], refw) < 1e-12
+
+
+# -- P6: n = p, square invertible X_i: b_i = X_i^-1 y whatever M ------------
+
+def test_p6_square_design():
+    rng = np.random.default_rng(6)
+    n = p = 4
+    M = _spd(n, rng, cond=10.0)
+    XL = np.column_stack([np.ones(n), rng.standard_normal((n, p - 2))])
+    y = rng.standard_normal(n)
+    XR = rng.integers(0, 3, size=(6, n)).astype(np.float64)
+    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    for i in range(6):
+        Xi = np.column_stack([XL, XR[i]])
+        if abs(np.linalg.det(Xi)) < 1e-8:
+            continue
+        Xinv = np.linalg.inv(Xi)
+        assert _rel(b[i, 0], Xinv @ y) < 1e-11
+        assert abs(var[i] - (Xinv @ M @ Xinv.T)[-1, -1]) < 1e-10 * abs(var[i])
+
+
+# -- P7: invariances ----------------------------------------------------------
+
+def test_p7_invariances():
+    M, XL, y, XR = _problem(50, 4, 10, seed=7)
+    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    # scaling M leaves b unchanged (variance scales)
+    bs, vs, _ = GLSOracle(3.5 * M, XL, y).solve(XR)
+    assert _rel(bs, b) < 1e-12
+    assert _rel(vs, 3.5 * var) < 1e-12
+    # consistent permutation of individuals
+    perm = np.random.default_rng(8).permutation(50)
+    bp, _, _ = GLSOracle(M[np.ix_(perm, perm)], XL[perm], y[perm]).solve(XR[:, perm])
+    assert _rel(bp, b) < 1e-11
+    # x -> x + c 1 leaves the SNP coefficient unchanged (intercept absorbs it)
+    bc, vc, _ = GLSOracle(M, XL, y).solve(XR + 2.5)
+    assert _rel(bc[:, 0, -1], b[:, 0, -1]) < 1e-10
+    assert _rel(vc, var) < 1e-10
+    # x -> a x divides it by a
+    ba, _, _ = GLSOracle(M, XL, y).solve(-1.7 * XR)
+    assert _rel(ba[:, 0, -1], b[:, 0, -1] / -1.7) < 1e-11
+    # duplicate SNP columns give identical results
+    bd, _, _ = GLSOracle(M, XL, y).solve(np.vstack([XR[3], XR[3]]))
+    assert np.array_equal(bd[0], bd[1])
+
+
+# -- P8: Frisch-Waugh-Lovell closed form for the SNP coefficient -------------
+
+def test_p8_fwl_closed_form():
+    M, XL, y, XR = _problem(70, 6, 15, seed=9)
+    Minv = _gauss_jordan_inverse(M)
+    P = Minv - Minv @ XL @ np.linalg.inv(XL.T @ Minv @ XL) @ XL.T @ Minv
+    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    for i in range(XR.shape[0]):
+        x = XR[i]
+        s = x @ P @ x
+        assert abs(b[i, 0, -1] - (x @ P @ y) / s) < 1e-10 * max(1.0, abs(b[i, 0, -1]))
+        assert abs(var[i] - 1.0 / s) < 1e-10 * var[i]
+
+
+# -- literal per-SNP form, multiple traits, rank deficiency -------------------
+
+def test_literal_and_traits():
+    M, XL, _, XR = _problem(30, 3, 8, seed=10)
+    Y = np.random.default_rng(12).standard_normal((30, 5))
+    b, _, _ = GLSOracle(M, XL, Y).solve(XR)
+    assert b.shape == (8, 5, 3)
+    assert _rel(b, gls_literal(M, XL, Y, XR)) < 1e-11
+    for j in range(5):
+        bj, _, _ = GLSOracle(M, XL, Y[:, j]).solve(XR)
+        assert _rel(b[:, j], bj[:, 0]) < 1e-13
+
+
+def test_rank_deficient_snp_flagged():
+    M, XL, y, XR = _problem(40, 4, 5, seed=13)
+    XR[2] = 2.0                     # monomorphic: collinear with the intercept
+    XR[4] = 0.0                     # all-zero column
+    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    assert list(info) == [0, 0, 4, 0, 4]
+    assert np.isnan(b[2]).all() and np.isnan(b[4]).all() and np.isnan(var[2])
+    assert np.isfinite(b[[0, 1, 3]]).all()
+
+
+# -- planted mistakes: the pins above must catch them -------------------------
+
+class _YNotWhitened(GLSOracle):
+    """Mistake S3 of the printed listing read literally: bbar_T from y, not M^-1 y."""
+    def normal_equations(self, XR):
+        N, r = super().normal_equations(XR)
+        r[:, :self.p - 1, :] = self.XL.T @ self.Y
+        return N, r
+
+
+class _DroppedCross(GLSOracle):
+    """A dropped off-diagonal block of X_i^T M^-1 X_i."""
+    def normal_equations(self, XR):
+        N, r = super().normal_equations(XR)
+        N[:, self.p - 1, :self.p - 1] = 0.0
+        N[:, :self.p - 1, self.p - 1] = 0.0
+        return N, r
+
+
+class _WrongSign(GLSOracle):
+    def normal_equations(self, XR):
+        N, r = super().normal_equations(XR)
+        r[:, self.p - 1, :] *= -1.0
+        return N, r
+
+
+@pytest.mark.parametrize("bad", [_YNotWhitened, _DroppedCross, _WrongSign])
+def test_planted_mistakes_are_caught(bad):
+    prob = synth.make_problem(200, 4, seed=21, noise=False)
+    XR = synth.snp_block(200, 21, 0, 20)
+    beta = prob["beta"][:, 0]
+    k, gamma = 5, 0.9
+    y = prob["Y"][:, 0] + gamma * XR[k]
+    want = np.concatenate([beta, [gamma]])
+    good, _, _ = GLSOracle(prob["M"], prob["XL"], y).solve(XR[k:k + 1])
+    assert np.max(np.abs(good[0, 0] - want)) < 1e-10
+    wrong, _, _ = bad(prob["M"], prob["XL"], y).solve(XR[k:k + 1])
+    assert np.max(np.abs(wrong[0, 0] - want)) > 1e-3
+
