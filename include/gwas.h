@@ -1,0 +1,177 @@
+/*
+ * gwas.h - C ABI of the MI355X library for the generalized least-squares
+ * solves of a mixed-model genome-wide association study.
+ *
+ * For every SNP i the library computes (Eq. 1, Section 1)
+ *
+ *     b_i = (X_i^T M^-1 X_i)^-1 X_i^T M^-1 y,     X_i = [X_L | x_i],
+ *
+ * with M (n x n) symmetric positive definite, X_L (n x (p-1)) the covariates
+ * shared by all SNPs, x_i (n) the dosages of SNP i and y (n) the phenotype
+ * (t phenotype columns may share M and X_i).  It follows the restructured
+ * algorithm of Section 2.1 (Algorithm 1) and its streamed form of Section 3
+ * (Algorithm 2):
+ *
+ *   gwas_init          L L^T = M; Xbar_L = L^-1 X_L, ybar = L^-1 y;
+ *                      S_TL = Xbar_L^T Xbar_L, bbar_T = Xbar_L^T ybar.
+ *   gwas_stream_block  for a block of SNP columns X_blk:
+ *                      Xbar_blk = L^-1 X_blk; per SNP S_BL = xbar^T Xbar_L,
+ *                      S_BR = xbar^T xbar, bbar_B = xbar^T ybar; then the
+ *                      p x p system S_i b_i = bbar_i by Cholesky.
+ *   gwas_free          releases the context.
+ *
+ * Conventions
+ *   - All matrices are column-major with an explicit leading dimension
+ *     (ld >= rows).  SNP i of a block is the contiguous n-vector at
+ *     XR + i*ldx.  b_i is the contiguous p-vector at b + i*ldb (for t > 1
+ *     traits: t consecutive p-vectors, trait-major), with the SNP coefficient
+ *     last (index p-1) and the X_L coefficients first, in X_L's column order.
+ *   - Device memory means memory of the context's HIP device; host memory
+ *     may be pageable or pinned (pinned host memory is used in place).
+ *   - Functions return GWAS_OK (0) or a positive GWAS_E_* code; no C++
+ *     exception crosses this interface.  Every call that takes a context
+ *     returns GWAS_E_STATE for a NULL, freed or poisoned context.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef GWAS_H
+#define GWAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GWAS_OK            0
+#define GWAS_E_INVALID     1   /* bad argument; nothing was touched          */
+#define GWAS_E_NOT_SPD     2   /* M is not positive definite (gwas_info)     */
+#define GWAS_E_RANK_XL     3   /* X_L^T M^-1 X_L not numerically positive
+                                  definite (a Cholesky pivot <= 1e-10 times
+                                  its diagonal entry): X_L rank deficient   */
+#define GWAS_E_NO_DEVICE   4   /* no usable gfx950 device                    */
+#define GWAS_E_HIP         5   /* HIP runtime error (gwas_last_error)        */
+#define GWAS_E_OOM         6   /* device allocation failed                   */
+#define GWAS_E_STATE       7   /* NULL, freed or poisoned context            */
+#define GWAS_E_WORKSPACE   8   /* caller workspace smaller than required     */
+
+/* ---- arithmetic of the per-block triangular solve ----------------------- */
+#define GWAS_FP64          0   /* everything in float64                     */
+#define GWAS_FP32_REFINE   1   /* L^-1 x_i on float32 matrix cores, float64
+                                  accumulation between K panels; the SNP
+                                  cross products and the p x p solve in
+                                  float64 with two refinement steps          */
+#define GWAS_BF16_REFINE   2   /* as above with bfloat16 operands           */
+
+/* ---- element type of the SNP dosages handed to gwas_stream_block -------- */
+#define GWAS_X_F64         0   /* float64                                   */
+#define GWAS_X_I8          1   /* int8 dosages (0, 1, 2), expanded on device */
+
+typedef struct gwas_ctx gwas_ctx;
+
+typedef struct gwas_desc {
+    int64_t n;               /* individuals, n >= p                          */
+    int32_t p;               /* columns of X_i, 2 <= p <= 20                 */
+    int32_t t;               /* phenotype columns sharing M, 1 <= t <= 256   */
+    const double* M;         /* n x n, lower triangle read (Section 2)       */
+    int64_t ldm;             /* >= n                                         */
+    const double* XL;        /* n x (p-1) covariates                         */
+    int64_t ldxl;            /* >= n                                         */
+    const double* Y;         /* n x t phenotypes                             */
+    int64_t ldy;             /* >= n                                         */
+    int32_t inputs_on_device;/* nonzero: M, XL and Y are device pointers     */
+    int32_t precision;       /* GWAS_FP64 | GWAS_FP32_REFINE | GWAS_BF16_REFINE */
+    int32_t x_dtype;         /* GWAS_X_F64 | GWAS_X_I8                       */
+    int32_t device;          /* HIP device ordinal                           */
+    int64_t dev_block;       /* SNP columns per device sub-block, 0 = auto   */
+    void*   workspace;       /* caller device memory, or NULL: library allocates */
+    size_t  workspace_bytes; /* size of workspace when given                 */
+    void*   stream;          /* hipStream_t for compute, NULL: library stream */
+} gwas_desc;
+
+/*
+ * Device bytes a context needs for these sizes (pure function, no device
+ * call).  Returns 0 if the sizes are invalid.  A caller that passes its own
+ * workspace must pass at least this many bytes, 256-byte aligned.
+ */
+size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block,
+                            int32_t precision, int32_t x_dtype);
+
+/*
+ * Create a context: copies M, X_L and y to the device, factors M = L L^T
+ * (Algorithm 1, first line; FP64), forms the explicit triangular inverse
+ * L^-1 used by every block, whitens X_L and y (Algorithm 1, second line) and
+ * forms S_TL, bbar_T and the Cholesky factor of S_TL (Algorithm 1, third
+ * line).  For the GWAS_*_REFINE precisions it also forms
+ * W = M^-1 [X_L | y] in float64 and the reduced-precision copy of L^-1.
+ *
+ * The desc's host pointers are only read during the call.  On success *out
+ * owns all library memory (the caller's workspace, if given, must outlive
+ * it).  Errors: GWAS_E_INVALID (n < p, p outside 2..20, t outside 1..256,
+ * ld < n, NULL pointer, unknown precision or x_dtype; checked before any
+ * device call), GWAS_E_NO_DEVICE, GWAS_E_WORKSPACE, GWAS_E_OOM, GWAS_E_HIP,
+ * GWAS_E_NOT_SPD (gwas_info gives the 1-based order of the first leading
+ * minor of M that is not positive, as LAPACK's potrf does) and
+ * GWAS_E_RANK_XL.  On GWAS_E_NOT_SPD and GWAS_E_RANK_XL *out is set so that
+ * gwas_info can be read, and must then be released with gwas_free; on every
+ * other error *out is NULL.
+ */
+int gwas_init(gwas_ctx** out, const gwas_desc* d);
+
+/*
+ * Solve the GLS problems of a block of mblk SNPs (Algorithm 2, one pass of
+ * its loop; the block is split into device sub-blocks of dev_block columns,
+ * double-buffered between host-to-device copies and compute).
+ *
+ *   XR       n x mblk dosages (x_dtype), column i = SNP i, host or device.
+ *   ldx      >= n, elements between consecutive SNP columns.
+ *   b        output, p*t doubles per SNP at b + i*ldb (host or device).
+ *   ldb      >= p*t.
+ *   var_snp  optional (NULL): [S_i^-1]_{pp}, the variance of the SNP
+ *            coefficient in units of M, per SNP (host or device).
+ *   info     optional (NULL): per-SNP status, 0 = solved, p = X_i
+ *            numerically rank deficient (then b_i and var_i are NaN).
+ *
+ * Returns after every output has been written (synchronous for the caller,
+ * pipelined inside).  mblk = 0 is a no-op.  Results for a SNP do not depend
+ * on the block it arrives in.  On a device error the context is poisoned and
+ * later calls return GWAS_E_STATE.
+ */
+int gwas_stream_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
+                      double* b, int64_t ldb, double* var_snp, int32_t* info);
+
+/* Release a context (NULL is accepted).  Later use returns GWAS_E_STATE. */
+int gwas_free(gwas_ctx* ctx);
+
+/* Static text for a status code. */
+const char* gwas_strerror(int code);
+
+/* After GWAS_E_NOT_SPD: 1-based failing pivot of M; after GWAS_E_RANK_XL:
+ * 1-based failing pivot of X_L^T M^-1 X_L; otherwise 0.  -1 for a bad ctx. */
+int64_t gwas_info(const gwas_ctx* ctx);
+
+/* Text of the last error recorded on the context ("" if none). */
+const char* gwas_last_error(const gwas_ctx* ctx);
+
+/*
+ * Kernel timing for measurement: when enabled, HIP events bracket every
+ * launch of the per-block triangular-product kernel on the compute stream.
+ * gwas_kernel_time returns the number of timed launches and their summed
+ * duration in milliseconds since timing was last enabled, and the sum of
+ * the SNP columns those launches processed.
+ */
+int gwas_set_timing(gwas_ctx* ctx, int32_t enable);
+int gwas_kernel_time(gwas_ctx* ctx, int64_t* launches, double* total_ms,
+                     int64_t* columns);
+
+/* Sizes the context was built with: n_pad (padded order of the device
+ * factors), the sub-block width and the device ordinal. */
+int gwas_query(const gwas_ctx* ctx, int64_t* n_pad, int64_t* dev_block,
+               int32_t* device);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWAS_H */

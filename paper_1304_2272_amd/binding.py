@@ -1,0 +1,251 @@
+"""Thin ctypes binding over the C ABI declared in ``include/gwas.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Loading fails loudly when ``libgwas.so`` has not been built; there
+is no fallback path.
+
+Array conventions on the Python side (all float64 unless stated):
+  M   (n, n) symmetric.  The library reads the triangle that is lower in
+      column-major order, i.e. the upper triangle of a C-ordered array.
+  XL  (n, p-1) covariates, Y (n,) or (n, t) phenotypes.
+  XR  (m, n) C-ordered, one row per SNP (the column-major n x m matrix whose
+      column i is SNP i); float64 or int8 per ``x_dtype``.
+  b   (m, t, p) output, SNP coefficient last; var (m,); info (m,) int32.
+numpy arrays are host memory; torch tensors may live on the GPU.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgwas.so")
+
+GWAS_OK = 0
+ERRORS = {1: "GWAS_E_INVALID", 2: "GWAS_E_NOT_SPD", 3: "GWAS_E_RANK_XL", 4: "GWAS_E_NO_DEVICE",
+          5: "GWAS_E_HIP", 6: "GWAS_E_OOM", 7: "GWAS_E_STATE", 8: "GWAS_E_WORKSPACE"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+X_DTYPES = {"f64": 0, "i8": 1}
+
+FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
+             "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
+             "gwas_kernel_time", "gwas_query")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("t", ctypes.c_int32),
+        ("M", ctypes.c_void_p), ("ldm", ctypes.c_int64),
+        ("XL", ctypes.c_void_p), ("ldxl", ctypes.c_int64),
+        ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64),
+        ("inputs_on_device", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("x_dtype", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("dev_block", ctypes.c_int64),
+        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class GwasError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+
+
+_lib = None
+
+
+def load():
+    """Load ``libgwas.so`` and declare its signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own libamdhip64 with the
+    # same soname, so loading torch first makes the library bind to it and
+    # device pointers and streams from torch stay valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.gwas_workspace_bytes.restype = ctypes.c_size_t
+    L.gwas_workspace_bytes.argtypes = [i64, i32, i32, i64, i32, i32]
+    L.gwas_init.restype = ctypes.c_int
+    L.gwas_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Desc)]
+    L.gwas_stream_block.restype = ctypes.c_int
+    L.gwas_stream_block.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
+    L.gwas_free.restype = ctypes.c_int
+    L.gwas_free.argtypes = [vp]
+    L.gwas_strerror.restype = ctypes.c_char_p
+    L.gwas_strerror.argtypes = [ctypes.c_int]
+    L.gwas_info.restype = i64
+    L.gwas_info.argtypes = [vp]
+    L.gwas_last_error.restype = ctypes.c_char_p
+    L.gwas_last_error.argtypes = [vp]
+    L.gwas_set_timing.restype = ctypes.c_int
+    L.gwas_set_timing.argtypes = [vp, i32]
+    L.gwas_kernel_time.restype = ctypes.c_int
+    L.gwas_kernel_time.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(i64)]
+    L.gwas_query.restype = ctypes.c_int
+    L.gwas_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    _lib = L
+    return L
+
+
+def workspace_bytes(n, p, t=1, dev_block=0, precision="fp64", x_dtype="f64"):
+    return load().gwas_workspace_bytes(n, p, t, dev_block, PRECISIONS[precision], X_DTYPES[x_dtype])
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr_ld(a, want_dtype, what):
+    """(pointer, leading dimension, keepalive, on_device) of a column-major view.
+
+    ``a`` is given row-major as (cols, rows): rows of ``a`` are columns of the
+    column-major matrix handed to the library.
+    """
+    if _is_torch(a):
+        import torch
+        tdt = {np.float64: torch.float64, np.int8: torch.int8}[want_dtype]
+        if a.dtype != tdt:
+            raise TypeError(f"{what}: expected {tdt}, got {a.dtype}")
+        if a.dim() == 1:
+            a = a.reshape(1, -1)
+        if a.stride(-1) != 1:
+            a = a.contiguous()
+        return a.data_ptr(), a.stride(0) if a.shape[0] > 1 else a.shape[1], a, a.is_cuda
+    a = np.asarray(a)
+    if a.dtype != want_dtype:
+        raise TypeError(f"{what}: expected {np.dtype(want_dtype)}, got {a.dtype}")
+    if a.ndim == 1:
+        a = a.reshape(1, -1)
+    if a.strides[-1] != a.itemsize:
+        a = np.ascontiguousarray(a)
+    ld = a.strides[0] // a.itemsize if a.shape[0] > 1 else a.shape[1]
+    return a.ctypes.data, ld, a, False
+
+
+class GwasContext:
+    """One factorisation of M and its derived constants, reused for every block."""
+
+    def __init__(self, M, XL, Y, precision="fp64", x_dtype="f64", dev_block=0, device=0,
+                 stream=None):
+        L = load()
+        self._lib = L
+        self.precision = precision
+        self.x_dtype = x_dtype
+        dev = _is_torch(M) and M.is_cuda
+        if dev:
+            import torch
+            n = M.shape[0]
+            XLt = XL.reshape(n, -1).t().contiguous()
+            Yt = (Y.reshape(n, 1) if Y.dim() == 1 else Y).t().contiguous()
+            Mk = M.contiguous()
+            if stream is None:
+                stream = torch.cuda.current_stream(M.device).cuda_stream
+            keep = (Mk, XLt, Yt)
+            mp, xlp, yp = Mk.data_ptr(), XLt.data_ptr(), Yt.data_ptr()
+            p = XLt.shape[0] + 1
+            t = Yt.shape[0]
+        else:
+            M = np.ascontiguousarray(np.asarray(M, dtype=np.float64))
+            n = M.shape[0]
+            XLt = np.ascontiguousarray(np.asarray(XL, dtype=np.float64).reshape(n, -1).T)
+            Yv = np.asarray(Y, dtype=np.float64)
+            Yt = np.ascontiguousarray((Yv.reshape(n, 1) if Yv.ndim == 1 else Yv).T)
+            keep = (M, XLt, Yt)
+            mp, xlp, yp = M.ctypes.data, XLt.ctypes.data, Yt.ctypes.data
+            p = XLt.shape[0] + 1
+            t = Yt.shape[0]
+        self.n, self.p, self.t = n, p, t
+        d = Desc(n=n, p=p, t=t, M=mp, ldm=n, XL=xlp, ldxl=n, Y=yp, ldy=n,
+                 inputs_on_device=1 if dev else 0, precision=PRECISIONS[precision],
+                 x_dtype=X_DTYPES[x_dtype], device=device, dev_block=dev_block,
+                 workspace=None, workspace_bytes=0, stream=stream)
+        h = ctypes.c_void_p()
+        rc = L.gwas_init(ctypes.byref(h), ctypes.byref(d))
+        del keep
+        self._h = h
+        if rc != GWAS_OK:
+            info = L.gwas_info(h) if h.value else 0
+            msg = L.gwas_last_error(h).decode() if h.value else L.gwas_strerror(rc).decode()
+            if h.value:
+                L.gwas_free(h)
+                self._h = ctypes.c_void_p()
+            err = GwasError(rc, msg)
+            err.info = info
+            raise err
+
+    def _check(self, rc):
+        if rc != GWAS_OK:
+            msg = self._lib.gwas_last_error(self._h).decode() if self._h.value else ""
+            raise GwasError(rc, msg or self._lib.gwas_strerror(rc).decode())
+
+    def stream_block(self, XR, out=None):
+        """Solve Eq. (1) for every SNP row of XR; returns (b, var, info)."""
+        xdt = np.int8 if self.x_dtype == "i8" else np.float64
+        xp, ldx, keep, xdev = _ptr_ld(XR, xdt, "XR")
+        m = XR.shape[0] if XR.ndim == 2 else 1
+        pt = self.p * self.t
+        if out is not None:
+            b, var, info = out
+        elif xdev:
+            import torch
+            b = torch.empty((m, self.t, self.p), dtype=torch.float64, device=XR.device)
+            var = torch.empty(m, dtype=torch.float64, device=XR.device)
+            info = torch.empty(m, dtype=torch.int32, device=XR.device)
+        else:
+            b = np.empty((m, self.t, self.p))
+            var = np.empty(m)
+            info = np.empty(m, dtype=np.int32)
+        ptr = (lambda a: a.data_ptr()) if _is_torch(b) else (lambda a: a.ctypes.data)
+        rc = self._lib.gwas_stream_block(self._h, xp, ldx, m, ptr(b), pt,
+                                         ptr(var) if var is not None else None,
+                                         ptr(info) if info is not None else None)
+        del keep
+        self._check(rc)
+        return b, var, info
+
+    def set_timing(self, on=True):
+        self._check(self._lib.gwas_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        cols = ctypes.c_int64()
+        self._check(self._lib.gwas_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms),
+                                               ctypes.byref(cols)))
+        return n.value, ms.value, cols.value
+
+    def query(self):
+        npad = ctypes.c_int64()
+        blk = ctypes.c_int64()
+        dev = ctypes.c_int32()
+        self._check(self._lib.gwas_query(self._h, ctypes.byref(npad), ctypes.byref(blk),
+                                         ctypes.byref(dev)))
+        return {"n_pad": npad.value, "dev_block": blk.value, "device": dev.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gwas_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,613 @@
+// C ABI of the library: context lifetime, workspace layout, the one-time
+// set-up of Algorithm 1 (first three lines) and the per-block loop of
+// Algorithm 2 with double-buffered host-to-device copies on side streams.
+#include "gwas.h"
+#include "internal.h"
+
+#include <string.h>
+
+#include <algorithm>
+#include <climits>
+#include <string>
+#include <vector>
+
+using namespace gwas;
+
+namespace {
+
+constexpr uint64_t CTX_MAGIC = 0x67776173c7c70001ull;
+constexpr uint64_t CTX_DEAD = 0xdeadc7c7deadc7c7ull;
+constexpr int64_t DEFAULT_DEV_BLOCK = 16384;
+constexpr int MAX_T = 256;
+constexpr double RANK_TOL_F64 = 1e-10;
+constexpr double RANK_TOL_F32 = 1e-6;
+constexpr double RANK_TOL_BF16 = 1e-2;
+constexpr int REFINE_STEPS = 2;
+
+struct Layout {
+    int64_t n, n_pad, ld, dev_block, npb, Q;
+    int p, t, q1, Qc, precision, x_dtype;
+    size_t off_L, off_U, off_Ulow, off_XY, off_C, off_W, off_S, off_consts, off_flags,
+        off_sched, off_sched_tail, off_region;
+    size_t off_xbuf[2], off_part, off_xw, off_b[2], off_v[2], off_i[2];
+    size_t off_tmp;
+    size_t sched_len;
+    size_t total;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
+                 int32_t x_dtype) {
+    if (p < 2 || p > 20 || n < p || t < 1 || t > MAX_T) return false;
+    if (n > (int64_t)1 << 24) return false;
+    if (dev_block < 0 || dev_block > ((int64_t)1 << 22)) return false;
+    if (precision != GWAS_FP64 && precision != GWAS_FP32_REFINE && precision != GWAS_BF16_REFINE)
+        return false;
+    if (x_dtype != GWAS_X_F64 && x_dtype != GWAS_X_I8) return false;
+    return true;
+}
+
+Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, int x_dtype) {
+    Layout L{};
+    L.n = n;
+    L.p = p;
+    L.t = t;
+    L.q1 = p - 1;
+    L.Qc = p - 1 + t;
+    L.precision = precision;
+    L.x_dtype = x_dtype;
+    L.n_pad = (n + NPAD_ALIGN - 1) / NPAD_ALIGN * NPAD_ALIGN;
+    L.ld = L.n_pad;
+    L.dev_block = dev_block > 0 ? (dev_block + TILE_N - 1) / TILE_N * TILE_N : DEFAULT_DEV_BLOCK;
+    L.npb = L.n_pad / PART_ROWS;
+    L.Q = (precision == GWAS_FP64) ? L.Qc + 1 : 1;
+    const size_t nn = (size_t)L.ld * (size_t)L.n_pad;
+    const size_t A = 256;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, A); return r; };
+    L.off_L = take(nn * 8);
+    L.off_U = take(nn * 8);
+    L.off_Ulow = (precision == GWAS_FP32_REFINE) ? take(nn * 4)
+               : (precision == GWAS_BF16_REFINE) ? take(nn * 2) : 0;
+    L.off_XY = take((size_t)L.n_pad * L.Qc * 8);
+    L.off_C = take((size_t)L.n_pad * L.Qc * 8);
+    L.off_W = (precision != GWAS_FP64) ? take((size_t)L.n_pad * L.Qc * 8) : 0;
+    L.off_S = take((size_t)L.q1 * L.Qc * 8);
+    L.off_consts = take((size_t)consts_len(L.q1, t) * 8);
+    L.off_flags = take(256);
+    L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block);
+    L.off_sched = take(L.sched_len * 2 * 4);
+    L.off_sched_tail = take(L.sched_len * 2 * 4);
+    // region shared by the set-up temporary and the streaming buffers
+    L.off_region = o;
+    const size_t elem = (x_dtype == GWAS_X_I8) ? 1 : 8;
+    size_t r = 0;
+    auto rtake = [&](size_t bytes) { size_t q = r; r = align_up(r + bytes, A); return L.off_region + q; };
+    L.off_xbuf[0] = rtake((size_t)L.n_pad * L.dev_block * elem);
+    L.off_xbuf[1] = rtake((size_t)L.n_pad * L.dev_block * elem);
+    L.off_part = rtake((size_t)L.npb * L.Q * L.dev_block * 8);
+    L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
+    for (int s = 0; s < 2; ++s) {
+        L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
+        L.off_v[s] = rtake((size_t)L.dev_block * 8);
+        L.off_i[s] = rtake((size_t)L.dev_block * 4);
+    }
+    const int64_t n1 = (L.n_pad / 2 + LEAF - 1) / LEAF * LEAF;
+    const size_t tmp = (size_t)n1 * (size_t)(L.n_pad - n1) * 8;
+    L.off_tmp = L.off_region;
+    L.total = L.off_region + std::max(r, align_up(tmp, A));
+    return L;
+}
+
+}  // namespace
+
+struct gwas_ctx {
+    uint64_t magic = CTX_MAGIC;
+    bool poisoned = false;
+    int device = 0;
+    Layout lay{};
+    char* ws = nullptr;
+    bool own_ws = false;
+    double *L = nullptr, *U = nullptr, *XY = nullptr, *C = nullptr, *W = nullptr, *S = nullptr,
+           *consts = nullptr;
+    void* Ulow = nullptr;
+    int* flags = nullptr;
+    int* sched = nullptr;
+    int* sched_tail = nullptr;
+    int64_t tail_cols = -1;
+    char* xbuf[2] = {nullptr, nullptr};
+    double* part = nullptr;
+    double* xw = nullptr;
+    double* bbuf[2] = {nullptr, nullptr};
+    double* vbuf[2] = {nullptr, nullptr};
+    int* ibuf[2] = {nullptr, nullptr};
+    double* tmp = nullptr;
+    hipStream_t s_comp = nullptr, s_h2d = nullptr, s_d2h = nullptr;
+    bool own_comp = false;
+    hipEvent_t ev_loaded[2] = {}, ev_done[2] = {}, ev_out[2] = {};
+    std::vector<int> host_sched, host_tail;
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    int64_t t_launches = 0, t_cols = 0;
+    double t_ms = 0.0;
+    int64_t info = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail_hip(gwas_ctx* c, hipError_t e, const char* what) {
+    if (c) {
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        c->poisoned = true;
+    }
+    return (e == hipErrorOutOfMemory) ? GWAS_E_OOM : GWAS_E_HIP;
+}
+
+#define HIPCHK(ctx, expr)                                                         \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) return fail_hip((ctx), e_, #expr);                  \
+    } while (0)
+
+bool live(const gwas_ctx* c) { return c && c->magic == CTX_MAGIC && !c->poisoned; }
+
+bool on_device(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+// Recursive Cholesky and triangular inverse of the diagonal block [o, o+sz):
+//   [A11 .; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T,
+//   L21 = A21 L11^-T, A22 <- A22 - L21 L21^T, and
+//   U = L^-T with U12 = -U11 L21^T U22.
+int chol_inv(gwas_ctx* c, int64_t o, int64_t sz) {
+    const int64_t ld = c->lay.ld;
+    hipStream_t s = c->s_comp;
+    if (sz == LEAF) {
+        HIPCHK(c, chol_leaf(c->L + o + o * ld, c->U + o + o * ld, ld, o, c->lay.n, c->flags, s));
+        return GWAS_OK;
+    }
+    const int64_t n1 = (sz / 2 + LEAF - 1) / LEAF * LEAF;
+    const int64_t n2 = sz - n1;
+    int rc = chol_inv(c, o, n1);
+    if (rc) return rc;
+    double* L21 = c->L + (o + n1) + o * ld;
+    double* L22 = c->L + (o + n1) + (o + n1) * ld;
+    double* U11 = c->U + o + o * ld;
+    double* U12 = c->U + o + (o + n1) * ld;
+    double* U22 = c->U + (o + n1) + (o + n1) * ld;
+    // T = A21 U11 (= L21), copied into place
+    GemmArgs g{};
+    g = GemmArgs{n2, n1, n1, L21, ld, 'N', U11, ld, 'N', c->tmp, n2, 1.0, 0.0, KR_B_UPPER, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    HIPCHK(c, hipMemcpy2DAsync(L21, ld * 8, c->tmp, n2 * 8, n2 * 8, n1, hipMemcpyDeviceToDevice, s));
+    // A22 -= L21 L21^T (lower tiles)
+    g = GemmArgs{n2, n2, n1, c->tmp, n2, 'N', c->tmp, n2, 'T', L22, ld, -1.0, 1.0, 0, 1};
+    HIPCHK(c, gemm_f64(g, s));
+    rc = chol_inv(c, o + n1, n2);
+    if (rc) return rc;
+    // T = U11 L21^T (n1 x n2), U12 = -T U22
+    g = GemmArgs{n1, n2, n1, U11, ld, 'N', L21, ld, 'T', c->tmp, n1, 1.0, 0.0, KR_A_UPPER, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    g = GemmArgs{n1, n2, n2, c->tmp, n1, 'N', U22, ld, 'N', U12, ld, -1.0, 0.0, KR_B_UPPER, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    return GWAS_OK;
+}
+
+int check_device(int dev, std::string& why) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        why = "no HIP device";
+        return GWAS_E_NO_DEVICE;
+    }
+    if (dev < 0 || dev >= count) {
+        why = "device ordinal out of range";
+        return GWAS_E_NO_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        why = "hipGetDeviceProperties failed";
+        return GWAS_E_NO_DEVICE;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        why = std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950";
+        return GWAS_E_NO_DEVICE;
+    }
+    return GWAS_OK;
+}
+
+void release(gwas_ctx* c) {
+    if (!c) return;
+    if (c->s_comp) (void)hipStreamSynchronize(c->s_comp);
+    if (c->s_h2d) (void)hipStreamSynchronize(c->s_h2d);
+    if (c->s_d2h) (void)hipStreamSynchronize(c->s_d2h);
+    for (int s = 0; s < 2; ++s) {
+        if (c->ev_loaded[s]) (void)hipEventDestroy(c->ev_loaded[s]);
+        if (c->ev_done[s]) (void)hipEventDestroy(c->ev_done[s]);
+        if (c->ev_out[s]) (void)hipEventDestroy(c->ev_out[s]);
+    }
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    if (c->s_h2d) (void)hipStreamDestroy(c->s_h2d);
+    if (c->s_d2h) (void)hipStreamDestroy(c->s_d2h);
+    if (c->own_comp && c->s_comp) (void)hipStreamDestroy(c->s_comp);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    (void)hipGetLastError();
+}
+
+int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host) {
+    const int64_t len = trmm_schedule_len(c->lay.n_pad, cols);
+    host.assign((size_t)(2 * len), 0);
+    if (trmm_schedule(c->lay.n_pad, cols, host.data(), len) != len) {
+        c->err = "tile schedule does not fit";
+        return GWAS_E_INVALID;
+    }
+    HIPCHK(c, hipMemcpyAsync(dst, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice,
+                             c->s_comp));
+    return GWAS_OK;
+}
+
+int init_body(gwas_ctx* c, const gwas_desc* d) {
+    const Layout& Y = c->lay;
+    const int64_t ld = Y.ld, n = Y.n, n_pad = Y.n_pad;
+    hipStream_t s = c->s_comp;
+    const hipMemcpyKind kin = d->inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+
+    HIPCHK(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->flags), INT_MAX, 1, s));
+    HIPCHK(c, hipMemsetAsync(c->flags + 1, 0, 4, s));
+    // M -> L (the lower triangle is what the factorisation reads), identity padding
+    HIPCHK(c, hipMemcpy2DAsync(c->L, ld * 8, d->M, d->ldm * 8, n * 8, n, kin, s));
+    HIPCHK(c, pad_identity(c->L, ld, n, n_pad, s));
+    HIPCHK(c, hipMemsetAsync(c->U, 0, (size_t)ld * n_pad * 8, s));
+    int rc = chol_inv(c, 0, n_pad);
+    if (rc) return rc;
+    // [X_L | Y] with zero padding rows, then C = L^-1 [X_L | Y]
+    HIPCHK(c, hipMemsetAsync(c->XY, 0, (size_t)n_pad * Y.Qc * 8, s));
+    HIPCHK(c, hipMemcpy2DAsync(c->XY, n_pad * 8, d->XL, d->ldxl * 8, n * 8, Y.q1, kin, s));
+    HIPCHK(c, hipMemcpy2DAsync(c->XY + (size_t)n_pad * Y.q1, n_pad * 8, d->Y, d->ldy * 8, n * 8,
+                               Y.t, kin, s));
+    GemmArgs g{n_pad, Y.Qc, n_pad, c->U, ld, 'T', c->XY, n_pad, 'N', c->C, n_pad, 1.0, 0.0,
+               KR_A_LOWER, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    // [S_TL | bbar_T] = Xbar_L^T [Xbar_L | Ybar]
+    g = GemmArgs{Y.q1, Y.Qc, n_pad, c->C, n_pad, 'T', c->C, n_pad, 'N', c->S, Y.q1, 1.0, 0.0, 0, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    HIPCHK(c, snp_constants(c->S, Y.q1, Y.q1, Y.t, c->consts, c->flags + 1, s));
+    if (Y.precision != GWAS_FP64) {
+        // W = L^-T [Xbar_L | Ybar] = M^-1 [X_L | Y]
+        g = GemmArgs{n_pad, Y.Qc, n_pad, c->U, ld, 'N', c->C, n_pad, 'N', c->W, n_pad, 1.0, 0.0,
+                     KR_A_UPPER, 0};
+        HIPCHK(c, gemm_f64(g, s));
+        if (Y.precision == GWAS_FP32_REFINE)
+            HIPCHK(c, convert_f32(c->U, (float*)c->Ulow, ld, n_pad, n_pad, s));
+        else
+            HIPCHK(c, convert_bf16(c->U, (__bf16*)c->Ulow, ld, n_pad, n_pad, s));
+    }
+    rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));
+    int flags[2] = {0, 0};
+    HIPCHK(c, hipMemcpy(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[0] != INT_MAX) {
+        c->info = flags[0];
+        c->err = "M is not positive definite";
+        return GWAS_E_NOT_SPD;
+    }
+    if (flags[1] != 0) {
+        c->info = flags[1];
+        c->err = "X_L^T M^-1 X_L is not positive definite";
+        return GWAS_E_RANK_XL;
+    }
+    return GWAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
+                            int32_t x_dtype) {
+    if (!sizes_valid(n, p, t, dev_block, precision, x_dtype)) return 0;
+    return make_layout(n, p, t, dev_block, precision, x_dtype).total;
+}
+
+int gwas_init(gwas_ctx** out, const gwas_desc* d) {
+    if (!out) return GWAS_E_INVALID;
+    *out = nullptr;
+    if (!d || !d->M || !d->XL || !d->Y) return GWAS_E_INVALID;
+    if (!sizes_valid(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype)) return GWAS_E_INVALID;
+    if (d->ldm < d->n || d->ldxl < d->n || d->ldy < d->n) return GWAS_E_INVALID;
+    if (d->workspace && (reinterpret_cast<uintptr_t>(d->workspace) % 256)) return GWAS_E_INVALID;
+
+    gwas_ctx* c = new (std::nothrow) gwas_ctx();
+    if (!c) return GWAS_E_OOM;
+    c->device = d->device;
+    std::string why;
+    int rc = check_device(d->device, why);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype);
+    const Layout& Y = c->lay;
+    auto bail = [&](int code) {
+        release(c);
+        c->magic = CTX_DEAD;
+        delete c;
+        return code;
+    };
+    if (hipSetDevice(d->device) != hipSuccess) return bail(GWAS_E_NO_DEVICE);
+    if (d->workspace) {
+        if (d->workspace_bytes < Y.total) return bail(GWAS_E_WORKSPACE);
+        c->ws = static_cast<char*>(d->workspace);
+    } else {
+        if (hipMalloc(&c->ws, Y.total) != hipSuccess) {
+            (void)hipGetLastError();
+            c->ws = nullptr;
+            return bail(GWAS_E_OOM);
+        }
+        c->own_ws = true;
+    }
+    char* w = c->ws;
+    c->L = (double*)(w + Y.off_L);
+    c->U = (double*)(w + Y.off_U);
+    c->Ulow = Y.off_Ulow ? (void*)(w + Y.off_Ulow) : nullptr;
+    c->XY = (double*)(w + Y.off_XY);
+    c->C = (double*)(w + Y.off_C);
+    c->W = Y.off_W ? (double*)(w + Y.off_W) : nullptr;
+    c->S = (double*)(w + Y.off_S);
+    c->consts = (double*)(w + Y.off_consts);
+    c->flags = (int*)(w + Y.off_flags);
+    c->sched = (int*)(w + Y.off_sched);
+    c->sched_tail = (int*)(w + Y.off_sched_tail);
+    for (int s = 0; s < 2; ++s) {
+        c->xbuf[s] = w + Y.off_xbuf[s];
+        c->bbuf[s] = (double*)(w + Y.off_b[s]);
+        c->vbuf[s] = (double*)(w + Y.off_v[s]);
+        c->ibuf[s] = (int*)(w + Y.off_i[s]);
+    }
+    c->part = (double*)(w + Y.off_part);
+    c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
+    c->tmp = (double*)(w + Y.off_tmp);
+
+    hipError_t e = hipSuccess;
+    if (d->stream) {
+        c->s_comp = static_cast<hipStream_t>(d->stream);
+    } else {
+        e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking);
+        c->own_comp = true;
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_h2d, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_d2h, hipStreamNonBlocking);
+    for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+        e = hipEventCreateWithFlags(&c->ev_loaded[s], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_done[s], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out[s], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(GWAS_E_HIP);
+    }
+    rc = init_body(c, d);
+    if (rc == GWAS_E_NOT_SPD || rc == GWAS_E_RANK_XL) {
+        c->poisoned = true;   // info stays readable; streaming is refused
+        *out = c;
+        return rc;
+    }
+    if (rc) return bail(rc);
+    *out = c;
+    return GWAS_OK;
+}
+
+int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
+                      int64_t ldb, double* var_snp, int32_t* info) {
+    if (!live(c)) return GWAS_E_STATE;
+    const Layout& Y = c->lay;
+    if (mblk < 0) return GWAS_E_INVALID;
+    if (mblk == 0) return GWAS_OK;
+    if (!XR || !b || ldx < Y.n || ldb < (int64_t)Y.p * Y.t) return GWAS_E_INVALID;
+    HIPCHK(c, hipSetDevice(c->device));
+
+    const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
+    const char* xr = static_cast<const char*>(XR);
+    const bool x_dev = on_device(XR);
+    const bool direct_x = x_dev && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
+                          ((ldx * (int64_t)elem) % 16 == 0);
+    const bool direct_out = on_device(b) && (!var_snp || on_device(var_snp)) &&
+                            (!info || on_device(info));
+    const int pt = Y.p * Y.t;
+    const int at = (Y.precision == GWAS_FP64) ? A_F64 : (Y.precision == GWAS_FP32_REFINE) ? A_F32 : A_BF16;
+    const void* Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
+    const double tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
+                     : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32 : RANK_TOL_BF16;
+    const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
+    if (c->timing && (int64_t)c->tev.size() < 2 * nsub) {
+        while ((int64_t)c->tev.size() < 2 * nsub) {
+            hipEvent_t ev;
+            HIPCHK(c, hipEventCreate(&ev));
+            c->tev.push_back(ev);
+        }
+    }
+
+    for (int64_t k = 0; k < nsub; ++k) {
+        const int64_t col0 = k * Y.dev_block;
+        const int64_t cols = std::min<int64_t>(Y.dev_block, mblk - col0);
+        const int slot = (int)(k & 1);
+        const void* xptr;
+        int64_t xld;
+        if (direct_x) {
+            xptr = xr + (size_t)col0 * ldx * elem;
+            xld = ldx;
+        } else {
+            if (k >= 2) HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_done[slot], 0));
+            HIPCHK(c, hipMemcpy2DAsync(c->xbuf[slot], Y.n_pad * elem, xr + (size_t)col0 * ldx * elem,
+                                       ldx * elem, Y.n * elem, cols, hipMemcpyDefault, c->s_h2d));
+            HIPCHK(c, hipEventRecord(c->ev_loaded[slot], c->s_h2d));
+            HIPCHK(c, hipStreamWaitEvent(c->s_comp, c->ev_loaded[slot], 0));
+            xptr = c->xbuf[slot];
+            xld = Y.n_pad;
+        }
+        double* bo;
+        double* vo;
+        int* io;
+        int64_t ldbo;
+        if (direct_out) {
+            bo = b + (size_t)col0 * ldb;
+            vo = var_snp ? var_snp + col0 : nullptr;
+            io = info ? info + col0 : nullptr;
+            ldbo = ldb;
+        } else {
+            if (k >= 2) HIPCHK(c, hipStreamWaitEvent(c->s_comp, c->ev_out[slot], 0));
+            bo = c->bbuf[slot];
+            vo = c->vbuf[slot];
+            io = c->ibuf[slot];
+            ldbo = pt;
+        }
+        const int* sched = c->sched;
+        if (cols != Y.dev_block) {
+            if (cols != c->tail_cols) {
+                int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
+                if (rc) return rc;
+                c->tail_cols = cols;
+            }
+            sched = c->sched_tail;
+        }
+        TrmmArgs ta{};
+        ta.at = at;
+        ta.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+        ta.Ut = Ut;
+        ta.ldu = Y.ld;
+        ta.n_pad = Y.n_pad;
+        ta.X = xptr;
+        ta.ldx = xld;
+        ta.n = Y.n;
+        ta.cols = cols;
+        ta.C = c->C;
+        ta.ldc = Y.n_pad;
+        ta.Qc = Y.Qc;
+        ta.with_cross = (Y.precision == GWAS_FP64);
+        ta.part = c->part;
+        ta.ldp = Y.dev_block;
+        ta.sched = sched;
+        ta.n_sched = trmm_schedule_len(Y.n_pad, cols);
+        if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
+        HIPCHK(c, trmm_stream(ta, c->s_comp));
+        if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
+        if (Y.precision != GWAS_FP64)
+            HIPCHK(c, snp_cross_w(ta.xt, xptr, xld, Y.n, cols, c->W, Y.n_pad, Y.Qc, c->xw,
+                                  Y.dev_block, c->s_comp));
+        SolveArgs sa{};
+        sa.p = Y.p;
+        sa.t = Y.t;
+        sa.cols = cols;
+        sa.part = c->part;
+        sa.ldp = Y.dev_block;
+        sa.npb = Y.npb;
+        sa.Q = Y.Q;
+        sa.xw = c->xw;
+        sa.ldxw = Y.dev_block;
+        sa.consts = c->consts;
+        sa.refine = (Y.precision == GWAS_FP64) ? 0 : REFINE_STEPS;
+        sa.rank_tol = tol;
+        sa.b = bo;
+        sa.ldb = ldbo;
+        sa.var = vo;
+        sa.info = io;
+        HIPCHK(c, snp_solve(sa, c->s_comp));
+        HIPCHK(c, hipEventRecord(c->ev_done[slot], c->s_comp));
+        if (!direct_out) {
+            HIPCHK(c, hipStreamWaitEvent(c->s_d2h, c->ev_done[slot], 0));
+            HIPCHK(c, hipMemcpy2DAsync(b + (size_t)col0 * ldb, ldb * 8, bo, pt * 8, pt * 8, cols,
+                                       hipMemcpyDefault, c->s_d2h));
+            if (var_snp)
+                HIPCHK(c, hipMemcpyAsync(var_snp + col0, vo, cols * 8, hipMemcpyDefault, c->s_d2h));
+            if (info)
+                HIPCHK(c, hipMemcpyAsync(info + col0, io, cols * 4, hipMemcpyDefault, c->s_d2h));
+            HIPCHK(c, hipEventRecord(c->ev_out[slot], c->s_d2h));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->s_h2d));
+    HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    HIPCHK(c, hipStreamSynchronize(c->s_d2h));
+    if (c->timing) {
+        for (int64_t k = 0; k < nsub; ++k) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]));
+            c->t_ms += ms;
+            c->t_launches += 1;
+            c->t_cols += std::min<int64_t>(Y.dev_block, mblk - k * Y.dev_block);
+        }
+    }
+    return GWAS_OK;
+}
+
+int gwas_free(gwas_ctx* c) {
+    if (!c) return GWAS_OK;
+    if (c->magic != CTX_MAGIC) return GWAS_E_STATE;
+    (void)hipSetDevice(c->device);
+    release(c);
+    c->magic = CTX_DEAD;
+    delete c;
+    return GWAS_OK;
+}
+
+const char* gwas_strerror(int code) {
+    switch (code) {
+        case GWAS_OK: return "ok";
+        case GWAS_E_INVALID: return "invalid argument";
+        case GWAS_E_NOT_SPD: return "M is not positive definite";
+        case GWAS_E_RANK_XL: return "X_L^T M^-1 X_L is not positive definite (X_L rank deficient)";
+        case GWAS_E_NO_DEVICE: return "no usable gfx950 device";
+        case GWAS_E_HIP: return "HIP runtime error";
+        case GWAS_E_OOM: return "device memory exhausted";
+        case GWAS_E_STATE: return "context is NULL, freed or poisoned";
+        case GWAS_E_WORKSPACE: return "workspace smaller than gwas_workspace_bytes";
+        default: return "unknown status";
+    }
+}
+
+int64_t gwas_info(const gwas_ctx* c) {
+    if (!c || c->magic != CTX_MAGIC) return -1;
+    return c->info;
+}
+
+const char* gwas_last_error(const gwas_ctx* c) {
+    if (!c || c->magic != CTX_MAGIC) return "invalid context";
+    return c->err.c_str();
+}
+
+int gwas_set_timing(gwas_ctx* c, int32_t enable) {
+    if (!live(c)) return GWAS_E_STATE;
+    c->timing = enable != 0;
+    c->t_launches = 0;
+    c->t_cols = 0;
+    c->t_ms = 0.0;
+    return GWAS_OK;
+}
+
+int gwas_kernel_time(gwas_ctx* c, int64_t* launches, double* total_ms, int64_t* columns) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (launches) *launches = c->t_launches;
+    if (total_ms) *total_ms = c->t_ms;
+    if (columns) *columns = c->t_cols;
+    return GWAS_OK;
+}
+
+int gwas_query(const gwas_ctx* c, int64_t* n_pad, int64_t* dev_block, int32_t* device) {
+    if (!c || c->magic != CTX_MAGIC) return GWAS_E_STATE;
+    if (n_pad) *n_pad = c->lay.n_pad;
+    if (dev_block) *dev_block = c->lay.dev_block;
+    if (device) *device = c->device;
+    return GWAS_OK;
+}
+
+}  // extern "C"

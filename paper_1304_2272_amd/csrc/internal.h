@@ -1,0 +1,121 @@
+// Internal declarations shared by the library's translation units.
+// Launchers take raw device pointers and a stream; every launcher checks the
+// shapes it is given against what its kernel assumes before launching.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gwas {
+
+// ---- tiles of the matrix-core kernels ----------------------------------
+constexpr int TILE_M = 128;        // rows of a tile (rows of L^-1 / of C)
+constexpr int TILE_N = 128;        // columns of a tile (SNPs / columns of C)
+constexpr int PART_ROWS = 64;      // rows summed into one partial dot product
+constexpr int NPAD_ALIGN = 256;    // n is padded to a multiple of this
+constexpr int LEAF = 64;           // order of the diagonal blocks factored in LDS
+
+// K-range restrictions of the generic FP64 product, from operand structure.
+enum : int {
+    KR_A_LOWER = 1,   // A(m,k) = 0 for k > m
+    KR_A_UPPER = 2,   // A(m,k) = 0 for k < m
+    KR_B_UPPER = 4,   // B(k,n) = 0 for k > n
+    KR_B_LOWER = 8,   // B(k,n) = 0 for k < n
+};
+
+// C(MxN) = alpha * op(A) op(B) + beta * C in float64 on matrix cores.
+//   opA 'N': A(m,k) = A[m + k*lda]      opA 'T': A(m,k) = A[k + m*lda]
+//   opB 'N': B(k,n) = B[k + n*ldb]      opB 'T': B(k,n) = B[n + k*ldb]
+// beta == 0 never reads C.  lower_only skips tiles strictly above the
+// diagonal (for a symmetric update of a diagonal block).
+struct GemmArgs {
+    int64_t M, N, K;
+    const double* A; int64_t lda; char opA;
+    const double* B; int64_t ldb; char opB;
+    double* C; int64_t ldc;
+    double alpha, beta;
+    int kflags;
+    int lower_only;
+};
+hipError_t gemm_f64(const GemmArgs& g, hipStream_t s);
+
+// Cholesky of the LEAF x LEAF diagonal block at L (lower triangle read),
+// written back as L's block (zero above the diagonal) and the block of
+// U = L^-T (zero below the diagonal).  Pivot failures of rows < n_valid
+// record the smallest 1-based global row in *fail (atomic min).
+hipError_t chol_leaf(double* L, double* U, int64_t ld, int64_t row0,
+                     int64_t n_valid, int* fail, hipStream_t s);
+
+// rows r >= n or columns c >= n of the n_pad x n_pad matrix A become identity
+hipError_t pad_identity(double* A, int64_t ld, int64_t n, int64_t n_pad, hipStream_t s);
+
+// out = (T)in over an n_pad x n_pad column-major block (same ld)
+hipError_t convert_f32(const double* in, float* out, int64_t ld, int64_t rows,
+                       int64_t cols, hipStream_t s);
+hipError_t convert_bf16(const double* in, __bf16* out, int64_t ld, int64_t rows,
+                        int64_t cols, hipStream_t s);
+
+// Constant p x p blocks: S (q1 x Qc, ld lds) holds [S_TL | bbar_T] with
+// q1 = p-1 rows.  Writes R = chol(S_TL) (lower, ld q1), v = R^-1 bbar_T
+// (q1 x t), copies of S_TL and bbar_T, and the 1-based failing pivot of
+// S_TL (0 if none) into *fail.
+hipError_t snp_constants(const double* S, int64_t lds, int q1, int t,
+                         double* consts, int* fail, hipStream_t s);
+
+// Offsets into the constants buffer.
+__host__ __device__ inline int64_t consts_R(int) { return 0; }
+__host__ __device__ inline int64_t consts_v(int q1) { return (int64_t)q1 * q1; }
+__host__ __device__ inline int64_t consts_STL(int q1, int t) { return (int64_t)q1 * q1 + (int64_t)q1 * t; }
+__host__ __device__ inline int64_t consts_bT(int q1, int t) { return 2 * (int64_t)q1 * q1 + (int64_t)q1 * t; }
+__host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64_t)q1 * q1 + 2 * (int64_t)q1 * t; }
+
+// ---- streaming kernels ---------------------------------------------------
+enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2 };
+enum XType : int { X_F64 = 0, X_I8 = 1 };
+
+// Z = L^-1 X for one sub-block, never stored: for every 64-row slice of Z
+// and SNP column j the kernel writes partial sums into
+//   part[(pb * Q + q) * ldp + j]
+// with q < Qc: z^T C[:,q] (only when with_cross) and q = Q-1: z^T z.
+//   Ut    row-major L^-1 (Ut[k + r*ldu] = L^-1(r,k)), n_pad x n_pad, zero
+//         above the diagonal and in the padding; element type per `at`.
+//   X     n x cols dosages, column j at X + j*ldx (element type per `xt`).
+//   C     n_pad x Qc whitened [Xbar_L | Ybar] (zero padding rows).
+//   sched two int32 per workgroup: (row tile, column tile), -1 = idle.
+struct TrmmArgs {
+    int at, xt;
+    const void* Ut; int64_t ldu; int64_t n_pad;
+    const void* X; int64_t ldx; int64_t n; int64_t cols;
+    const double* C; int64_t ldc; int Qc;
+    int with_cross;
+    double* part; int64_t ldp;
+    const int* sched; int64_t n_sched;
+};
+hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
+
+// Host side: tile schedule for n_pad rows and `cols` SNP columns.  Returns
+// the number of workgroups and fills `out` (2 ints per workgroup).
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap);
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols);
+
+// xw[q * ldxw + j] = x_j^T W[:, q] for q < Qc (float64 accumulation).
+hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
+                       const double* W, int64_t ldw, int Qc, double* xw,
+                       int64_t ldxw, hipStream_t s);
+
+// Per-SNP reduction of the partials and the p x p Cholesky solve.
+struct SolveArgs {
+    int p, t;
+    int64_t cols;
+    const double* part; int64_t ldp; int64_t npb; int Q;  // partials
+    const double* xw; int64_t ldxw;                       // NULL: cross terms from part
+    const double* consts;
+    int refine;                                           // FP64 refinement steps
+    double rank_tol;
+    double* b; int64_t ldb;
+    double* var;
+    int* info;
+};
+hipError_t snp_solve(const SolveArgs& a, hipStream_t s);
+
+}  // namespace gwas

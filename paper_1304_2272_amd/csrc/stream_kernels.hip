@@ -1,0 +1,577 @@
+// Kernels of the per-block hot path (Algorithm 2, loop body):
+//   trmm_stream   Xbar_blk = L^-1 X_blk on matrix cores with the cross
+//                 products of Algorithm 2 fused into its epilogue
+//                 (S_BL = xbar^T Xbar_L, bbar_B = xbar^T ybar, S_BR = xbar^T xbar),
+//                 reduced per 64-row slice;
+//   snp_cross_w   x^T W with W = M^-1 [X_L | y] for the reduced-precision paths;
+//   snp_solve     per-SNP reduction of the partial sums and the p x p
+//                 Cholesky solve (Algorithm 1, last two lines of the loop).
+#include "internal.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace gwas {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
+
+// Each LDS row of a stage holds 128 bytes of K (BK elements) plus 16 bytes of
+// padding, so the 16 rows read together by one instruction fall on
+// distinct banks and every row stays 16-byte aligned.
+constexpr int ROW_BYTES = 128;
+constexpr int ROW_STRIDE = ROW_BYTES + 16;
+constexpr int FLUSH_STAGES = 4;   // reduced-precision sums move to float64 every 4 stages
+
+// Accumulator layout of the 16x16 instructions: element v of a lane holds
+// column lane%16 and row ROW_G*(lane/16) + ROW_V*v.
+template <typename AT> struct MM;
+template <> struct MM<double> {
+    static constexpr int BK = 16, KPL = 1;
+    static constexpr int ROW_G = 1, ROW_V = 4;
+    typedef d4_t acc_t;
+    typedef double frag_t;
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MM<float> {
+    static constexpr int BK = 32, KPL = 1;
+    static constexpr int ROW_G = 4, ROW_V = 1;
+    typedef f4_t acc_t;
+    typedef float frag_t;
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MM<__bf16> {
+    static constexpr int BK = 64, KPL = 8;
+    static constexpr int ROW_G = 4, ROW_V = 1;
+    typedef f4_t acc_t;
+    typedef bf8_t frag_t;
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename AT> __device__ __forceinline__ AT from_i8(int8_t x) { return (AT)(int)x; }
+template <typename AT> __device__ __forceinline__ AT from_f64(double x) { return (AT)x; }
+template <> __device__ __forceinline__ __bf16 from_f64<__bf16>(double x) { return (__bf16)(float)x; }
+
+// B slab: 128 SNP columns x BK values; thread t owns column t/2, half t%2,
+// i.e. E = BK/2 consecutive k of one column.
+template <typename AT, typename XT> struct BSlab {
+    static constexpr int E = MM<AT>::BK / 2;
+    static constexpr int BYTES = E * (int)sizeof(XT);
+    static constexpr int NV = BYTES >= 16 ? BYTES / 16 : 1;   // 16-byte loads (or one 8-byte)
+    u4_t v[NV];
+};
+
+template <typename AT, typename XT>
+__device__ __forceinline__ void load_b(BSlab<AT, XT>& r, const XT* __restrict__ X, int64_t ldx,
+                                       int64_t col0, int64_t cols, int64_t k0, int64_t n, int tid) {
+    constexpr int E = BSlab<AT, XT>::E;
+    constexpr int BYTES = BSlab<AT, XT>::BYTES;
+    const int c = tid >> 1;
+    const int64_t col = col0 + c;
+    const int64_t kb = k0 + (tid & 1) * E;
+    const XT* src = X + col * ldx + kb;
+    if (col < cols && kb + E <= n) {
+        if constexpr (BYTES >= 16) {
+            const u4_t* p = reinterpret_cast<const u4_t*>(src);
+#pragma unroll
+            for (int i = 0; i < BSlab<AT, XT>::NV; ++i) r.v[i] = p[i];
+        } else {
+            const u2_t w = *reinterpret_cast<const u2_t*>(src);
+            r.v[0] = u4_t{w[0], w[1], 0u, 0u};
+        }
+    } else {
+        XT tmp[E] __attribute__((aligned(16)));
+#pragma unroll
+        for (int e = 0; e < E; ++e) tmp[e] = (col < cols && kb + e < n) ? src[e] : (XT)0;
+        if constexpr (BYTES >= 16) {
+#pragma unroll
+            for (int i = 0; i < BSlab<AT, XT>::NV; ++i) r.v[i] = reinterpret_cast<const u4_t*>(tmp)[i];
+        } else {
+            const u2_t w = *reinterpret_cast<const u2_t*>(tmp);
+            r.v[0] = u4_t{w[0], w[1], 0u, 0u};
+        }
+    }
+}
+
+template <typename AT, typename XT>
+__device__ __forceinline__ void store_b(const BSlab<AT, XT>& r, char* Bs, int tid) {
+    constexpr int E = BSlab<AT, XT>::E;
+    const XT* x = reinterpret_cast<const XT*>(r.v);
+    AT* dst = reinterpret_cast<AT*>(Bs + (tid >> 1) * ROW_STRIDE) + (tid & 1) * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if constexpr (sizeof(XT) == 1) dst[e] = from_i8<AT>((int8_t)x[e]);
+        else dst[e] = from_f64<AT>((double)x[e]);
+    }
+}
+
+// A slab: 128 rows of L^-1 x 128 bytes of K; thread t owns row t/2, 64 bytes.
+struct ASlab { u4_t v[4]; };
+
+__device__ __forceinline__ void load_a(ASlab& r, const char* __restrict__ Ut, int64_t row_bytes,
+                                       int64_t r0, int64_t kbyte0, int tid) {
+    const u4_t* p = reinterpret_cast<const u4_t*>(Ut + (r0 + (tid >> 1)) * row_bytes + kbyte0 +
+                                                  (tid & 1) * 64);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.v[i] = p[i];
+}
+
+__device__ __forceinline__ void store_a(const ASlab& r, char* As, int tid) {
+    u4_t* dst = reinterpret_cast<u4_t*>(As + (tid >> 1) * ROW_STRIDE + (tid & 1) * 64);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[i] = r.v[i];
+}
+
+template <typename AT>
+__device__ __forceinline__ typename MM<AT>::frag_t frag(const u4_t (&f)[2], int s) {
+    if constexpr (sizeof(AT) == 8) {
+        return reinterpret_cast<const double*>(f)[s];
+    } else if constexpr (sizeof(AT) == 4) {
+        return reinterpret_cast<const float*>(f)[s];
+    } else {
+        return reinterpret_cast<const bf8_t*>(f)[s];
+    }
+}
+
+__device__ __forceinline__ double wave_sum16(double v) {
+    // sum over the four lane groups (lanes l, l+16, l+32, l+48)
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// One 128 x 128 tile (rows of Z, SNP columns) per workgroup, four waves of
+// 64 x 64.  Tile coordinates come from the schedule so that all tiles of a
+// row block run on one XCD (shared L^-1 panel in its L2) and the longest
+// (bottom) row blocks start first.  Within a stage, lane group g supplies the
+// contiguous K slice [g*BK/4, (g+1)*BK/4) to A and B alike.
+template <typename AT, typename XT>
+__global__ __launch_bounds__(256, (sizeof(AT) == 8 ? 2 : 1)) void trmm_stream_kernel(TrmmArgs a) {
+    typedef MM<AT> T;
+    constexpr int BK = T::BK;
+    constexpr bool LOWP = sizeof(AT) < 8;
+    const int I = a.sched[2 * (int64_t)blockIdx.x];
+    const int J = a.sched[2 * (int64_t)blockIdx.x + 1];
+    if (I < 0) return;
+
+    __shared__ __attribute__((aligned(16))) char As[2][TILE_M * ROW_STRIDE];
+    __shared__ __attribute__((aligned(16))) char Bs[2][TILE_N * ROW_STRIDE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    const int64_t r0 = (int64_t)I * TILE_M;
+    const int64_t c0 = (int64_t)J * TILE_N;
+    const int64_t kend = std::min<int64_t>(r0 + TILE_M, a.n_pad);   // L^-1 is lower triangular
+    const int64_t nk = kend / BK;
+    const char* Ut = reinterpret_cast<const char*>(a.Ut);
+    const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
+    const XT* X = reinterpret_cast<const XT*>(a.X);
+
+    typename T::acc_t acc[4][4];
+    d4_t acc64[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+            acc64[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        }
+
+    ASlab ra;
+    BSlab<AT, XT> rb;
+    load_a(ra, Ut, row_bytes, r0, 0, tid);
+    load_b<AT, XT>(rb, X, a.ldx, c0, a.cols, 0, a.n, tid);
+    store_a(ra, As[0], tid);
+    store_b<AT, XT>(rb, Bs[0], tid);
+    __syncthreads();
+
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            load_a(ra, Ut, row_bytes, r0, (kt + 1) * ROW_BYTES, tid);
+            load_b<AT, XT>(rb, X, a.ldx, c0, a.cols, (kt + 1) * BK, a.n, tid);
+        }
+        u4_t af[4][2], bf[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const u4_t* pa = reinterpret_cast<const u4_t*>(As[buf] + (wr * 64 + i * 16 + li) * ROW_STRIDE + lg * 32);
+            af[i][0] = pa[0];
+            af[i][1] = pa[1];
+            const u4_t* pb = reinterpret_cast<const u4_t*>(Bs[buf] + (wc * 64 + i * 16 + li) * ROW_STRIDE + lg * 32);
+            bf[i][0] = pb[0];
+            bf[i][1] = pb[1];
+        }
+#pragma unroll
+        for (int s = 0; s < BK / 4 / T::KPL; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = T::mma(frag<AT>(af[i], s), frag<AT>(bf[j], s), acc[i][j]);
+        if constexpr (LOWP) {
+            if ((kt + 1) % FLUSH_STAGES == 0 || !more) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+                        acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+                    }
+            }
+        }
+        if (more) {
+            store_a(ra, As[buf ^ 1], tid);
+            store_b<AT, XT>(rb, Bs[buf ^ 1], tid);
+        }
+        __syncthreads();
+    }
+    if constexpr (!LOWP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc64[i][j] = acc[i][j];
+    }
+
+    // Epilogue: per column, sums over this wave's 64 rows.  Rows of lane
+    // (i, v): r0 + wr*64 + i*16 + ROW_G*lg + ROW_V*v; columns: c0 + wc*64 + j*16 + li.
+    const int Q = a.with_cross ? a.Qc + 1 : 1;
+    const int64_t pb = (r0 + wr * 64) / PART_ROWS;
+    const int64_t cbase = c0 + wc * 64 + li;
+    if (a.with_cross) {
+        for (int q = 0; q < a.Qc; ++q) {
+            const double* Cq = a.C + q * a.ldc + r0 + wr * 64 + T::ROW_G * lg;
+            double cv[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + T::ROW_V * v];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) s += acc64[i][j][v] * cv[i][v];
+                s = wave_sum16(s);
+                const int64_t col = cbase + j * 16;
+                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s += acc64[i][j][v] * acc64[i][j][v];
+        s = wave_sum16(s);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = s;
+    }
+}
+
+// x_j^T W[:, q]: each wave takes 8 SNP columns, lanes stride over k.
+constexpr int XW_COLS = 8;
+constexpr int XW_Q = 8;
+template <typename XT>
+__global__ __launch_bounds__(256) void snp_cross_w_kernel(const XT* __restrict__ X, int64_t ldx,
+                                                          int64_t n, int64_t cols,
+                                                          const double* __restrict__ W, int64_t ldw,
+                                                          int Qc, double* __restrict__ xw,
+                                                          int64_t ldxw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t colbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * XW_COLS;
+    if (colbase >= cols) return;
+    for (int q0 = 0; q0 < Qc; q0 += XW_Q) {
+        double s[XW_COLS][XW_Q];
+#pragma unroll
+        for (int c = 0; c < XW_COLS; ++c)
+#pragma unroll
+            for (int q = 0; q < XW_Q; ++q) s[c][q] = 0.0;
+        for (int64_t k = lane; k < n; k += 64) {
+            double w[XW_Q];
+#pragma unroll
+            for (int q = 0; q < XW_Q; ++q) w[q] = (q0 + q < Qc) ? W[k + (q0 + q) * ldw] : 0.0;
+#pragma unroll
+            for (int c = 0; c < XW_COLS; ++c) {
+                const int64_t col = colbase + c;
+                const double x = (col < cols) ? (double)X[col * ldx + k] : 0.0;
+#pragma unroll
+                for (int q = 0; q < XW_Q; ++q) s[c][q] += x * w[q];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < XW_COLS; ++c)
+#pragma unroll
+            for (int q = 0; q < XW_Q; ++q) {
+                double v = s[c][q];
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+                const int64_t col = colbase + c;
+                if (lane == 0 && col < cols && q0 + q < Qc) xw[(q0 + q) * ldxw + col] = v;
+            }
+    }
+}
+
+// One thread per SNP.  With R = chol(S_TL) fixed, the Cholesky factor of
+// S_i = [[S_TL, S_BL^T], [S_BL, S_BR]] is [[R, 0], [u^T, sqrt(s)]] with
+// u = R^-1 S_BL^T and s = S_BR - u^T u, so b_i follows from two triangular
+// solves with R and one division by s.  Optional float64 refinement steps
+// b <- b + S_i^-1 (bbar_i - S_i b) reuse the same factor.
+template <int Q1>
+__global__ __launch_bounds__(128) void snp_solve_kernel(SolveArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.cols) return;
+    const int t = a.t;
+    const double* R = a.consts + consts_R(Q1);
+    const double* V = a.consts + consts_v(Q1);
+    const double* STL = a.consts + consts_STL(Q1, t);
+    const double* BT = a.consts + consts_bT(Q1, t);
+
+    double sbl[Q1];
+    double sbr = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q1; ++q) sbl[q] = 0.0;
+    for (int64_t pb = 0; pb < a.npb; ++pb) {
+        const double* P = a.part + pb * a.Q * a.ldp + j;
+        if (!a.xw) {
+#pragma unroll
+            for (int q = 0; q < Q1; ++q) sbl[q] += P[q * a.ldp];
+        }
+        sbr += P[(a.Q - 1) * a.ldp];
+    }
+    if (a.xw) {
+#pragma unroll
+        for (int q = 0; q < Q1; ++q) sbl[q] = a.xw[q * a.ldxw + j];
+    }
+    double u[Q1];
+#pragma unroll
+    for (int r = 0; r < Q1; ++r) {
+        double s = sbl[r];
+#pragma unroll
+        for (int k = 0; k < r; ++k) s -= R[r + k * Q1] * u[k];
+        u[r] = s / R[r + r * Q1];
+    }
+    double s = sbr;
+#pragma unroll
+    for (int r = 0; r < Q1; ++r) s -= u[r] * u[r];
+    const bool ok = (s > a.rank_tol * sbr) && isfinite(s) && isfinite(sbr);
+    const double nan = __builtin_nan("");
+    if (a.var) a.var[j] = ok ? 1.0 / s : nan;
+    if (a.info) a.info[j] = ok ? 0 : Q1 + 1;
+    double* bj = a.b + j * a.ldb;
+    for (int jt = 0; jt < t; ++jt) {
+        double bB;
+        if (a.xw) {
+            bB = a.xw[(Q1 + jt) * a.ldxw + j];
+        } else {
+            bB = 0.0;
+            for (int64_t pb = 0; pb < a.npb; ++pb) bB += a.part[(pb * a.Q + Q1 + jt) * a.ldp + j];
+        }
+        if (!ok) {
+            for (int r = 0; r <= Q1; ++r) bj[jt * (Q1 + 1) + r] = nan;
+            continue;
+        }
+        const double* v = V + jt * Q1;
+        double c = bB;
+#pragma unroll
+        for (int r = 0; r < Q1; ++r) c -= u[r] * v[r];
+        double bs = c / s;
+        double bl[Q1];
+        // R^T bl = v - u bs
+#pragma unroll
+        for (int r = Q1 - 1; r >= 0; --r) {
+            double w = v[r] - u[r] * bs;
+#pragma unroll
+            for (int k = r + 1; k < Q1; ++k) w -= R[k + r * Q1] * bl[k];
+            bl[r] = w / R[r + r * Q1];
+        }
+        for (int it = 0; it < a.refine; ++it) {
+            // residual of S_i b = bbar_i in float64
+            double rt[Q1];
+#pragma unroll
+            for (int r = 0; r < Q1; ++r) {
+                double acc = BT[r + jt * Q1] - sbl[r] * bs;
+#pragma unroll
+                for (int k = 0; k < Q1; ++k) acc -= STL[r + k * Q1] * bl[k];
+                rt[r] = acc;
+            }
+            double rb = bB - sbr * bs;
+#pragma unroll
+            for (int k = 0; k < Q1; ++k) rb -= sbl[k] * bl[k];
+            // solve with the factor: y = R^-1 rt, dB = (rb - u.y)/s, dT = R^-T (y - u dB)
+            double y[Q1];
+#pragma unroll
+            for (int r = 0; r < Q1; ++r) {
+                double w = rt[r];
+#pragma unroll
+                for (int k = 0; k < r; ++k) w -= R[r + k * Q1] * y[k];
+                y[r] = w / R[r + r * Q1];
+            }
+            double dB = rb;
+#pragma unroll
+            for (int r = 0; r < Q1; ++r) dB -= u[r] * y[r];
+            dB /= s;
+            double dT[Q1];
+#pragma unroll
+            for (int r = Q1 - 1; r >= 0; --r) {
+                double w = y[r] - u[r] * dB;
+#pragma unroll
+                for (int k = r + 1; k < Q1; ++k) w -= R[k + r * Q1] * dT[k];
+                dT[r] = w / R[r + r * Q1];
+            }
+#pragma unroll
+            for (int r = 0; r < Q1; ++r) bl[r] += dT[r];
+            bs += dB;
+        }
+#pragma unroll
+        for (int r = 0; r < Q1; ++r) bj[jt * (Q1 + 1) + r] = bl[r];
+        bj[jt * (Q1 + 1) + Q1] = bs;
+    }
+}
+
+template <typename AT, typename XT>
+hipError_t launch_trmm(const TrmmArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((trmm_stream_kernel<AT, XT>), dim3((unsigned)a.n_sched), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols) {
+    const int64_t nrb = n_pad / TILE_M;
+    const int64_t ncb = (cols + TILE_N - 1) / TILE_N;
+    if (nrb < 16) return nrb * ncb;
+    // row blocks dealt to 8 XCD lists; the longest list sets the grid
+    int64_t longest = 0;
+    for (int x = 0; x < 8; ++x) {
+        int64_t len = 0;
+        for (int64_t r = 0; r < nrb; ++r) {
+            const int64_t grp = r / 8, pos = r % 8;
+            const int xcd = (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
+            if (xcd == x) len += ncb;
+        }
+        longest = std::max(longest, len);
+    }
+    return 8 * longest;
+}
+
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap) {
+    const int64_t nrb = n_pad / TILE_M;
+    const int64_t ncb = (cols + TILE_N - 1) / TILE_N;
+    const int64_t total = trmm_schedule_len(n_pad, cols);
+    if (total > cap) return -1;
+    if (nrb < 16) {
+        int64_t b = 0;
+        for (int64_t I = nrb - 1; I >= 0; --I)
+            for (int64_t J = 0; J < ncb; ++J, ++b) {
+                out[2 * b] = (int)I;
+                out[2 * b + 1] = (int)J;
+            }
+        return total;
+    }
+    // Workgroup b runs on XCD b % 8.  Row blocks, longest (largest I) first,
+    // are dealt to the XCDs in snake order (0..7, 7..0, ...), which balances
+    // the triangular work; each XCD runs its row blocks in descending order
+    // with all column tiles of one row block together.
+    std::vector<std::vector<int64_t>> rows(8);
+    for (int64_t r = 0; r < nrb; ++r) {
+        const int64_t grp = r / 8, pos = r % 8;
+        const int xcd = (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
+        rows[xcd].push_back(nrb - 1 - r);
+    }
+    const int64_t per = total / 8;
+    for (int x = 0; x < 8; ++x) {
+        int64_t q = 0;
+        for (int64_t I : rows[x])
+            for (int64_t J = 0; J < ncb; ++J, ++q) {
+                out[2 * (8 * q + x)] = (int)I;
+                out[2 * (8 * q + x) + 1] = (int)J;
+            }
+        for (; q < per; ++q) {
+            out[2 * (8 * q + x)] = -1;
+            out[2 * (8 * q + x) + 1] = -1;
+        }
+    }
+    return total;
+}
+
+hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
+    if (a.cols <= 0) return hipSuccess;
+    if (!a.Ut || !a.X || !a.part || !a.sched) return hipErrorInvalidValue;
+    if (a.n_pad % TILE_M || a.n_pad % PART_ROWS || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1)
+        return hipErrorInvalidValue;
+    if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
+    if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
+    if (a.n_sched != trmm_schedule_len(a.n_pad, a.cols) || a.n_sched > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const size_t xs = a.xt == X_I8 ? 1 : 8;
+    if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
+    if (a.xt == X_F64) {
+        if (a.at == A_F64) return launch_trmm<double, double>(a, s);
+        if (a.at == A_F32) return launch_trmm<float, double>(a, s);
+        if (a.at == A_BF16) return launch_trmm<__bf16, double>(a, s);
+    } else if (a.xt == X_I8) {
+        if (a.at == A_F64) return launch_trmm<double, int8_t>(a, s);
+        if (a.at == A_F32) return launch_trmm<float, int8_t>(a, s);
+        if (a.at == A_BF16) return launch_trmm<__bf16, int8_t>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
+                       const double* W, int64_t ldw, int Qc, double* xw, int64_t ldxw,
+                       hipStream_t s) {
+    if (cols <= 0) return hipSuccess;
+    if (!X || !W || !xw || ldx < n || ldw < n || ldxw < cols || Qc < 1) return hipErrorInvalidValue;
+    const int64_t waves = (cols + XW_COLS - 1) / XW_COLS;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    if (xt == X_I8)
+        hipLaunchKernelGGL(snp_cross_w_kernel<int8_t>, dim3(grid), dim3(256), 0, s,
+                           (const int8_t*)X, ldx, n, cols, W, ldw, Qc, xw, ldxw);
+    else
+        hipLaunchKernelGGL(snp_cross_w_kernel<double>, dim3(grid), dim3(256), 0, s,
+                           (const double*)X, ldx, n, cols, W, ldw, Qc, xw, ldxw);
+    return hipGetLastError();
+}
+
+hipError_t snp_solve(const SolveArgs& a, hipStream_t s) {
+    if (a.cols <= 0) return hipSuccess;
+    if (a.p < 2 || a.p > 20 || a.t < 1 || !a.part || !a.consts || !a.b || a.ldb < a.p * a.t)
+        return hipErrorInvalidValue;
+    if (!a.xw && a.Q != a.p + a.t) return hipErrorInvalidValue;
+    if (a.xw && a.Q != 1) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((a.cols + 127) / 128);
+    switch (a.p - 1) {
+#define GWAS_SOLVE_CASE(q) \
+    case q: hipLaunchKernelGGL(snp_solve_kernel<q>, dim3(grid), dim3(128), 0, s, a); break;
+        GWAS_SOLVE_CASE(1) GWAS_SOLVE_CASE(2) GWAS_SOLVE_CASE(3) GWAS_SOLVE_CASE(4)
+        GWAS_SOLVE_CASE(5) GWAS_SOLVE_CASE(6) GWAS_SOLVE_CASE(7) GWAS_SOLVE_CASE(8)
+        GWAS_SOLVE_CASE(9) GWAS_SOLVE_CASE(10) GWAS_SOLVE_CASE(11) GWAS_SOLVE_CASE(12)
+        GWAS_SOLVE_CASE(13) GWAS_SOLVE_CASE(14) GWAS_SOLVE_CASE(15) GWAS_SOLVE_CASE(16)
+        GWAS_SOLVE_CASE(17) GWAS_SOLVE_CASE(18) GWAS_SOLVE_CASE(19)
+#undef GWAS_SOLVE_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gwas
