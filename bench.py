@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the GLS-GWAS hot path on one MI355X.
+
+A step is one gwas_stream_block call over one batch of SNPs already resident
+in HBM (int8 dosages, the n = 50,000, p = 8 workload by default): the
+triangular product L^-1 X_blk, the SNP cross products, the p x p solves and
+the FP64 refinement, with b, var and info written to device memory.  The
+context (Cholesky of M, inverse factor, whitened X_L and y) is built before
+the timed region and its time is reported as ``init_s``.
+
+Legs: ``fp32`` (reduced-precision product with FP64 accumulation and
+refinement; this is ``value``), ``fp64`` (plain float64 path) and ``bf16``.
+Errors of the reduced-precision legs are measured against the fp64 leg on the
+same SNPs.  One JSON line goes to stdout.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SNP GLS solves/sec at n=50k,p=8 (mixed vs FP64); TRSM % of MFMA peak"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense matrix-core peaks
+WORKLOADS = {
+    "n50000_p8": dict(n=50_000, p=8, m=1_000_000, step=50_000, x_dtype="i8"),
+    "n20000_p4": dict(n=20_000, p=4, m=500_000, step=50_000, x_dtype="f64"),
+    "n10000_p4": dict(n=10_000, p=4, m=100_000, step=50_000, x_dtype="f64"),
+    "n1000_p4": dict(n=1_000, p=4, m=10_000, step=10_000, x_dtype="f64"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def normwise(b, bref):
+    import torch
+    d = (b - bref).reshape(b.shape[0], -1).norm(dim=1)
+    r = bref.reshape(b.shape[0], -1).norm(dim=1)
+    return float((d / r).max())
+
+
+def cpu_baseline(workload, seed, n_s, m_s, threads):
+    """The oracle on a bounded sample of the workload: its first n_s
+    individuals and m_s SNPs.  Its per-SNP cost is two triangular solves with
+    the LU factors of M (2 n^2 flops each), so SNPs/s is scaled by (n_s/n)^2."""
+    from threadpoolctl import threadpool_limits
+    from oracle import GLSOracle
+    from paper_1304_2272_amd import synth
+    n, p = workload["n"], workload["p"]
+    prob = synth.make_problem(n_s, p, seed)
+    XR = synth.snp_block(n_s, seed, 0, m_s, dtype=np.float64)
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
+        t1 = time.perf_counter()
+        orc.solve(XR)
+        t2 = time.perf_counter()
+    rate_s = m_s / (t2 - t1)
+    scale = (n_s / n) ** 2
+    return {
+        "value": rate_s * scale, "unit": "SNP/s", "cores": threads, "kind": "oracle",
+        "sample": (f"oracle on the same recipe restricted to the first {n_s} individuals and "
+                   f"{m_s} SNPs ({rate_s:.1f} SNP/s measured there), scaled by (n_s/n)^2 = "
+                   f"{scale:.4g} for its O(n^2) per-SNP solves; the one-off LU of M "
+                   f"({t1 - t0:.2f} s at n_s) is excluded"),
+        "measured_snps_per_s_at_sample": rate_s, "factor_s_at_sample": t1 - t0,
+    }
+
+
+def run_leg(name, prob_dev, blocks, steps, warmup, workload):
+    import torch
+    from paper_1304_2272_amd import binding
+    n = workload["n"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = binding.GwasContext(prob_dev["M"], prob_dev["XL"], prob_dev["Y"], precision=name,
+                              x_dtype=workload["x_dtype"])
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    outs = []
+    for s in range(warmup):
+        ctx.stream_block(blocks[s % len(blocks)])
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        b, var, info = ctx.stream_block(blocks[(warmup + s) % len(blocks)])
+        outs.append(b)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, kms, kcols = ctx.kernel_time()
+    info_bad = int((info != 0).sum())
+    ctx.close()
+    snps = sum(blocks[(warmup + s) % len(blocks)].shape[0] for s in range(steps))
+    flops = float(n) * float(n) * kcols           # L^-1 x: n^2 flops per SNP
+    achieved = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    peak = PEAK_TFLOPS[name]
+    log(f"[{name}] init {init_s:.2f} s, {snps} SNPs in {elapsed:.3f} s = {snps / elapsed:.1f} SNP/s, "
+        f"TRMM {launches} launches {kms:.1f} ms -> {achieved:.2f} TFLOP/s ({achieved / peak:.3f} of peak)")
+    return {
+        "snps_per_s": snps / elapsed, "elapsed_s": elapsed, "init_s": init_s, "snps": snps,
+        "ms_per_step": 1e3 * elapsed / max(steps, 1),
+        "kernel": {"launches": launches, "total_ms": kms, "avg_ms": kms / max(launches, 1),
+                   "columns": kcols},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak},
+        "rank_flags_last_step": info_bad,
+    }, outs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n50000_p8", choices=sorted(WORKLOADS))
+    ap.add_argument("--legs", default="fp32,fp64,bf16")
+    ap.add_argument("--fp64-steps", type=int, default=4)
+    ap.add_argument("--bf16-steps", type=int, default=2)
+    ap.add_argument("--step-snps", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=1306)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=8192)
+    ap.add_argument("--cpu-snps", type=int, default=8192)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1304_2272_amd import binding, synth
+    binding.load()
+    w = dict(WORKLOADS[args.workload])
+    if args.step_snps:
+        w["step"] = args.step_snps
+    n, p, step = w["n"], w["p"], w["step"]
+    dev = torch.device("cuda:0")
+    legs = [x for x in args.legs.split(",") if x]
+    main_leg = legs[0]
+
+    t0 = time.perf_counter()
+    log(f"generating n={n} p={p} on {dev} ...")
+    prob = synth.make_problem(n, p, args.seed, device="cuda:0")
+    prob_dev = {"M": prob["M"], "XL": torch.from_numpy(prob["XL"]).to(dev),
+                "Y": torch.from_numpy(prob["Y"]).to(dev)}
+    nblk = args.warmup + max(args.steps, args.fp64_steps, args.bf16_steps)
+    xdt = torch.int8 if w["x_dtype"] == "i8" else torch.float64
+    blocks = [synth.snp_block_device(n, args.seed, i * step, step, dev, dtype=xdt) for i in range(nblk)]
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s ({nblk} blocks of {step} SNPs)")
+
+    steps_of = {"fp32": args.steps, "fp64": args.fp64_steps, "bf16": args.bf16_steps}
+    steps_of[main_leg] = args.steps
+    res, outs = {}, {}
+    for leg in legs:
+        res[leg], outs[leg] = run_leg(leg, prob_dev, blocks, steps_of[leg], args.warmup, w)
+    errs = {}
+    if "fp64" in outs:
+        for leg in legs:
+            if leg == "fp64":
+                continue
+            k = min(len(outs[leg]), len(outs["fp64"]))
+            if k:
+                errs[leg] = max(normwise(outs[leg][i], outs["fp64"][i]) for i in range(k))
+                log(f"[{leg}] max normwise error vs fp64 over {k} steps: {errs[leg]:.3e}")
+    del outs, blocks
+    torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            threads = min(16, os.cpu_count() or 1)
+        cn = min(args.cpu_n, n)
+        log(f"cpu baseline: oracle at n_s={cn}, {args.cpu_snps} SNPs, {threads} threads ...")
+        cpu = cpu_baseline(w, args.seed, cn, args.cpu_snps, threads)
+        log(f"cpu baseline {cpu['value']:.3f} SNP/s (scaled)")
+
+    r = res[main_leg]
+    end_to_end = w["m"] / (r["init_s"] + w["m"] / r["snps_per_s"])
+    line = {
+        "metric": METRIC,
+        "value": r["snps_per_s"],
+        "unit": "SNP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[main_leg],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "p": p, "snps_per_step": step,
+                   "x_dtype": "int8" if w["x_dtype"] == "i8" else "f64",
+                   "precision": main_leg, "inputs": "device-resident", "parallelism": "single GPU"},
+        "roofline": dict(r["roofline"], traffic=None),
+        "cpu_baseline": cpu,
+        "init_s": {k: v["init_s"] for k, v in res.items()},
+        "legs": {k: {"snps_per_s": v["snps_per_s"], "ms_per_step": v["ms_per_step"],
+                     "roofline": v["roofline"], "kernel": v["kernel"], "snps": v["snps"]}
+                 for k, v in res.items()},
+        "err_vs_fp64": errs,
+        "end_to_end_snps_per_s": end_to_end,
+        "end_to_end_m": w["m"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
