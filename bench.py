@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--cpu-snps", type=int, default=8192)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -160,6 +162,15 @@ def main():
     blocks = [synth.snp_block_device(n, args.seed, i * step, step, dev, dtype=xdt) for i in range(nblk)]
     torch.cuda.synchronize()
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s ({nblk} blocks of {step} SNPs)")
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read and written")
+        del src, dst
 
     steps_of = {"fp32": args.steps, "fp64": args.fp64_steps, "bf16": args.bf16_steps}
     steps_of[main_leg] = args.steps

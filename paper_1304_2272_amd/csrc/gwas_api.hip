@@ -4,6 +4,7 @@
 #include "gwas.h"
 #include "internal.h"
 
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -25,7 +26,7 @@ constexpr double RANK_TOL_BF16 = 1e-2;
 constexpr int REFINE_STEPS = 2;
 
 struct Layout {
-    int64_t n, n_pad, ld, dev_block, npb, Q;
+    int64_t n, n_pad, ld, dev_block, npb_max, Q;
     int p, t, q1, Qc, precision, x_dtype;
     size_t off_L, off_U, off_Ulow, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
@@ -60,7 +61,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.n_pad = (n + NPAD_ALIGN - 1) / NPAD_ALIGN * NPAD_ALIGN;
     L.ld = L.n_pad;
     L.dev_block = dev_block > 0 ? (dev_block + TILE_N - 1) / TILE_N * TILE_N : DEFAULT_DEV_BLOCK;
-    L.npb = L.n_pad / PART_ROWS;
+    L.npb_max = L.n_pad / MIN_PART_ROWS;
     L.Q = (precision == GWAS_FP64) ? L.Qc + 1 : 1;
     const size_t nn = (size_t)L.ld * (size_t)L.n_pad;
     const size_t A = 256;
@@ -76,7 +77,14 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_S = take((size_t)L.q1 * L.Qc * 8);
     L.off_consts = take((size_t)consts_len(L.q1, t) * 8);
     L.off_flags = take(256);
-    L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block);
+    // room for the schedule and partial sums of every tile shape
+    const int at = precision == GWAS_FP64 ? A_F64 : precision == GWAS_FP32_REFINE ? A_F32 : A_BF16;
+    L.sched_len = 0;
+    for (int c = 0; c < trmm_num_cfgs(); ++c) {
+        if (!trmm_cfg_valid(at, x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c)) continue;
+        const TrmmShape sh = trmm_shape(c);
+        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh.tm, sh.tn));
+    }
     L.off_sched = take(L.sched_len * 2 * 4);
     L.off_sched_tail = take(L.sched_len * 2 * 4);
     // region shared by the set-up temporary and the streaming buffers
@@ -86,7 +94,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     auto rtake = [&](size_t bytes) { size_t q = r; r = align_up(r + bytes, A); return L.off_region + q; };
     L.off_xbuf[0] = rtake((size_t)L.n_pad * L.dev_block * elem);
     L.off_xbuf[1] = rtake((size_t)L.n_pad * L.dev_block * elem);
-    L.off_part = rtake((size_t)L.npb * L.Q * L.dev_block * 8);
+    L.off_part = rtake((size_t)L.npb_max * L.Q * L.dev_block * 8);
     L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
     for (int s = 0; s < 2; ++s) {
         L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
@@ -116,6 +124,8 @@ struct gwas_ctx {
     int* sched = nullptr;
     int* sched_tail = nullptr;
     int64_t tail_cols = -1;
+    int at = A_F64;
+    int cfg = 0;
     char* xbuf[2] = {nullptr, nullptr};
     double* part = nullptr;
     double* xw = nullptr;
@@ -245,9 +255,11 @@ void release(gwas_ctx* c) {
 }
 
 int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host) {
-    const int64_t len = trmm_schedule_len(c->lay.n_pad, cols);
+    const TrmmShape sh = trmm_shape(c->cfg);
+    const int64_t len = trmm_schedule_len(c->lay.n_pad, cols, sh.tm, sh.tn);
     host.assign((size_t)(2 * len), 0);
-    if (trmm_schedule(c->lay.n_pad, cols, host.data(), len) != len) {
+    if (len > (int64_t)c->lay.sched_len ||
+        trmm_schedule(c->lay.n_pad, cols, sh.tm, sh.tn, host.data(), len) != len) {
         c->err = "tile schedule does not fit";
         return GWAS_E_INVALID;
     }
@@ -339,6 +351,13 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     }
     c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype);
     const Layout& Y = c->lay;
+    c->at = d->precision == GWAS_FP64 ? A_F64 : d->precision == GWAS_FP32_REFINE ? A_F32 : A_BF16;
+    c->cfg = trmm_default_cfg(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64);
+    if (const char* e = getenv("GWAS_TRMM_CFG")) {
+        // tile-shape override for measurement; ignored when not valid here
+        const int v = atoi(e);
+        if (trmm_cfg_valid(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, v)) c->cfg = v;
+    }
     auto bail = [&](int code) {
         release(c);
         c->magic = CTX_DEAD;
@@ -425,7 +444,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     const bool direct_out = on_device(b) && (!var_snp || on_device(var_snp)) &&
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
-    const int at = (Y.precision == GWAS_FP64) ? A_F64 : (Y.precision == GWAS_FP32_REFINE) ? A_F32 : A_BF16;
+    const int at = c->at;
     const void* Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
     const double tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
                      : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32 : RANK_TOL_BF16;
@@ -498,7 +517,8 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         ta.part = c->part;
         ta.ldp = Y.dev_block;
         ta.sched = sched;
-        ta.n_sched = trmm_schedule_len(Y.n_pad, cols);
+        ta.cfg = c->cfg;
+        ta.n_sched = trmm_schedule_len(Y.n_pad, cols, trmm_shape(c->cfg).tm, trmm_shape(c->cfg).tn);
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
         HIPCHK(c, trmm_stream(ta, c->s_comp));
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
@@ -511,7 +531,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         sa.cols = cols;
         sa.part = c->part;
         sa.ldp = Y.dev_block;
-        sa.npb = Y.npb;
+        sa.npb = Y.n_pad / trmm_shape(c->cfg).part_rows;
         sa.Q = Y.Q;
         sa.xw = c->xw;
         sa.ldxw = Y.dev_block;

@@ -11,7 +11,6 @@ namespace gwas {
 // ---- tiles of the matrix-core kernels ----------------------------------
 constexpr int TILE_M = 128;        // rows of a tile (rows of L^-1 / of C)
 constexpr int TILE_N = 128;        // columns of a tile (SNPs / columns of C)
-constexpr int PART_ROWS = 64;      // rows summed into one partial dot product
 constexpr int NPAD_ALIGN = 256;    // n is padded to a multiple of this
 constexpr int LEAF = 64;           // order of the diagonal blocks factored in LDS
 
@@ -73,8 +72,9 @@ __host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64
 enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2 };
 enum XType : int { X_F64 = 0, X_I8 = 1 };
 
-// Z = L^-1 X for one sub-block, never stored: for every 64-row slice of Z
-// and SNP column j the kernel writes partial sums into
+// Z = L^-1 X for one sub-block, never stored: for every slice of part_rows
+// rows of Z (one wave's rows) and SNP column j the kernel writes partial
+// sums into
 //   part[(pb * Q + q) * ldp + j]
 // with q < Qc: z^T C[:,q] (only when with_cross) and q = Q-1: z^T z.
 //   Ut    row-major L^-1 (Ut[k + r*ldu] = L^-1(r,k)), n_pad x n_pad, zero
@@ -82,8 +82,9 @@ enum XType : int { X_F64 = 0, X_I8 = 1 };
 //   X     n x cols dosages, column j at X + j*ldx (element type per `xt`).
 //   C     n_pad x Qc whitened [Xbar_L | Ybar] (zero padding rows).
 //   sched two int32 per workgroup: (row tile, column tile), -1 = idle.
+//   cfg   tile shape (trmm_shape).
 struct TrmmArgs {
-    int at, xt;
+    int at, xt, cfg;
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const double* C; int64_t ldc; int Qc;
@@ -93,10 +94,17 @@ struct TrmmArgs {
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 
-// Host side: tile schedule for n_pad rows and `cols` SNP columns.  Returns
-// the number of workgroups and fills `out` (2 ints per workgroup).
-int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap);
-int64_t trmm_schedule_len(int64_t n_pad, int64_t cols);
+struct TrmmShape { int tm, tn, part_rows, threads; };
+int trmm_num_cfgs();
+TrmmShape trmm_shape(int cfg);
+bool trmm_cfg_valid(int at, int xt, int cfg);
+int trmm_default_cfg(int at, int xt);
+constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of any shape
+
+// Host side: tile schedule for n_pad rows and `cols` SNP columns with tm x tn
+// tiles.  Returns the number of workgroups and fills `out` (2 ints each).
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, int tm, int tn, int* out, int64_t cap);
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, int tm, int tn);
 
 // xw[q * ldxw + j] = x_j^T W[:, q] for q < Qc (float64 accumulation).
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,

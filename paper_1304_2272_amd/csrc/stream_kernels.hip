@@ -64,76 +64,6 @@ template <typename AT> __device__ __forceinline__ AT from_i8(int8_t x) { return 
 template <typename AT> __device__ __forceinline__ AT from_f64(double x) { return (AT)x; }
 template <> __device__ __forceinline__ __bf16 from_f64<__bf16>(double x) { return (__bf16)(float)x; }
 
-// B slab: 128 SNP columns x BK values; thread t owns column t/2, half t%2,
-// i.e. E = BK/2 consecutive k of one column.
-template <typename AT, typename XT> struct BSlab {
-    static constexpr int E = MM<AT>::BK / 2;
-    static constexpr int BYTES = E * (int)sizeof(XT);
-    static constexpr int NV = BYTES >= 16 ? BYTES / 16 : 1;   // 16-byte loads (or one 8-byte)
-    u4_t v[NV];
-};
-
-template <typename AT, typename XT>
-__device__ __forceinline__ void load_b(BSlab<AT, XT>& r, const XT* __restrict__ X, int64_t ldx,
-                                       int64_t col0, int64_t cols, int64_t k0, int64_t n, int tid) {
-    constexpr int E = BSlab<AT, XT>::E;
-    constexpr int BYTES = BSlab<AT, XT>::BYTES;
-    const int c = tid >> 1;
-    const int64_t col = col0 + c;
-    const int64_t kb = k0 + (tid & 1) * E;
-    const XT* src = X + col * ldx + kb;
-    if (col < cols && kb + E <= n) {
-        if constexpr (BYTES >= 16) {
-            const u4_t* p = reinterpret_cast<const u4_t*>(src);
-#pragma unroll
-            for (int i = 0; i < BSlab<AT, XT>::NV; ++i) r.v[i] = p[i];
-        } else {
-            const u2_t w = *reinterpret_cast<const u2_t*>(src);
-            r.v[0] = u4_t{w[0], w[1], 0u, 0u};
-        }
-    } else {
-        XT tmp[E] __attribute__((aligned(16)));
-#pragma unroll
-        for (int e = 0; e < E; ++e) tmp[e] = (col < cols && kb + e < n) ? src[e] : (XT)0;
-        if constexpr (BYTES >= 16) {
-#pragma unroll
-            for (int i = 0; i < BSlab<AT, XT>::NV; ++i) r.v[i] = reinterpret_cast<const u4_t*>(tmp)[i];
-        } else {
-            const u2_t w = *reinterpret_cast<const u2_t*>(tmp);
-            r.v[0] = u4_t{w[0], w[1], 0u, 0u};
-        }
-    }
-}
-
-template <typename AT, typename XT>
-__device__ __forceinline__ void store_b(const BSlab<AT, XT>& r, char* Bs, int tid) {
-    constexpr int E = BSlab<AT, XT>::E;
-    const XT* x = reinterpret_cast<const XT*>(r.v);
-    AT* dst = reinterpret_cast<AT*>(Bs + (tid >> 1) * ROW_STRIDE) + (tid & 1) * E;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        if constexpr (sizeof(XT) == 1) dst[e] = from_i8<AT>((int8_t)x[e]);
-        else dst[e] = from_f64<AT>((double)x[e]);
-    }
-}
-
-// A slab: 128 rows of L^-1 x 128 bytes of K; thread t owns row t/2, 64 bytes.
-struct ASlab { u4_t v[4]; };
-
-__device__ __forceinline__ void load_a(ASlab& r, const char* __restrict__ Ut, int64_t row_bytes,
-                                       int64_t r0, int64_t kbyte0, int tid) {
-    const u4_t* p = reinterpret_cast<const u4_t*>(Ut + (r0 + (tid >> 1)) * row_bytes + kbyte0 +
-                                                  (tid & 1) * 64);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r.v[i] = p[i];
-}
-
-__device__ __forceinline__ void store_a(const ASlab& r, char* As, int tid) {
-    u4_t* dst = reinterpret_cast<u4_t*>(As + (tid >> 1) * ROW_STRIDE + (tid & 1) * 64);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[i] = r.v[i];
-}
-
 template <typename AT>
 __device__ __forceinline__ typename MM<AT>::frag_t frag(const u4_t (&f)[2], int s) {
     if constexpr (sizeof(AT) == 8) {
@@ -152,139 +82,203 @@ __device__ __forceinline__ double wave_sum16(double v) {
     return v;
 }
 
-// One 128 x 128 tile (rows of Z, SNP columns) per workgroup, four waves of
-// 64 x 64.  Tile coordinates come from the schedule so that all tiles of a
-// row block run on one XCD (shared L^-1 panel in its L2) and the longest
-// (bottom) row blocks start first.  Within a stage, lane group g supplies the
-// contiguous K slice [g*BK/4, (g+1)*BK/4) to A and B alike.
-template <typename AT, typename XT>
-__global__ __launch_bounds__(256, (sizeof(AT) == 8 ? 2 : 1)) void trmm_stream_kernel(TrmmArgs a) {
+// Workgroup shape: WGM x WGN waves, each wave WTM x WTN blocks of 16 x 16.
+template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_> struct Shape {
+    static constexpr int WGM = WGM_, WGN = WGN_, WTM = WTM_, WTN = WTN_, MINB = MINB_;
+    static constexpr int TM = WGM * WTM * 16;     // rows of L^-1 / Z per tile
+    static constexpr int TN = WGN * WTN * 16;     // SNP columns per tile
+    static constexpr int NT = 64 * WGM * WGN;     // threads
+};
+
+// One TM x TN tile of Z = L^-1 X per workgroup.  The tile's K range is
+// [0, r0 + TM) because L^-1 is lower triangular.  Stages of 128 bytes of K
+// per row go global -> registers -> LDS (double buffered); within a stage
+// lane group g = lane/16 supplies the contiguous K slice [g*BK/4, (g+1)*BK/4)
+// to A and B alike.  Tile coordinates come from the schedule.
+template <typename AT, typename XT, typename S>
+__global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs a) {
     typedef MM<AT> T;
     constexpr int BK = T::BK;
     constexpr bool LOWP = sizeof(AT) < 8;
+    constexpr int TM = S::TM, TN = S::TN, NT = S::NT, WTM = S::WTM, WTN = S::WTN;
+    constexpr int A_CHUNKS = TM * (ROW_BYTES / 16);              // 16-byte chunks per stage
+    constexpr int CA = (A_CHUNKS + NT - 1) / NT;
+    constexpr int XB = BK * (int)sizeof(XT);                     // bytes of one column per stage
+    constexpr int CPC = XB / 16;                                 // 16-byte chunks per column
+    constexpr int EPC = 16 / (int)sizeof(XT);                    // elements per chunk
+    constexpr int B_CHUNKS = TN * CPC;
+    constexpr int CB = (B_CHUNKS + NT - 1) / NT;
+    static_assert(XB % 16 == 0, "a column stage must be whole 16-byte chunks");
+
     const int I = a.sched[2 * (int64_t)blockIdx.x];
     const int J = a.sched[2 * (int64_t)blockIdx.x + 1];
     if (I < 0) return;
 
-    __shared__ __attribute__((aligned(16))) char As[2][TILE_M * ROW_STRIDE];
-    __shared__ __attribute__((aligned(16))) char Bs[2][TILE_N * ROW_STRIDE];
+    __shared__ __attribute__((aligned(16))) char As[2][TM * ROW_STRIDE];
+    __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / S::WGN, wc = wave % S::WGN;
     const int li = lane & 15, lg = lane >> 4;
 
-    const int64_t r0 = (int64_t)I * TILE_M;
-    const int64_t c0 = (int64_t)J * TILE_N;
-    const int64_t kend = std::min<int64_t>(r0 + TILE_M, a.n_pad);   // L^-1 is lower triangular
+    const int64_t r0 = (int64_t)I * TM;
+    const int64_t c0 = (int64_t)J * TN;
+    const int64_t kend = std::min<int64_t>(r0 + TM, a.n_pad);
     const int64_t nk = kend / BK;
     const char* Ut = reinterpret_cast<const char*>(a.Ut);
     const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
     const XT* X = reinterpret_cast<const XT*>(a.X);
 
-    typename T::acc_t acc[4][4];
-    d4_t acc64[4][4];
+    typename T::acc_t acc[WTM][WTN];
+    d4_t acc64[WTM][WTN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < WTN; ++j) {
             acc[i][j] = typename T::acc_t{0, 0, 0, 0};
             acc64[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
         }
 
-    ASlab ra;
-    BSlab<AT, XT> rb;
-    load_a(ra, Ut, row_bytes, r0, 0, tid);
-    load_b<AT, XT>(rb, X, a.ldx, c0, a.cols, 0, a.n, tid);
-    store_a(ra, As[0], tid);
-    store_b<AT, XT>(rb, Bs[0], tid);
-    __syncthreads();
+    u4_t ra[CA], rb[CB];
+    auto load = [&](int64_t kt) {
+#pragma unroll
+        for (int c = 0; c < CA; ++c) {
+            const int idx = tid + c * NT;
+            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS) {
+                const int row = idx >> 3, ch = idx & 7;
+                ra[c] = *reinterpret_cast<const u4_t*>(Ut + (r0 + row) * row_bytes + kt * ROW_BYTES + ch * 16);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int idx = tid + c * NT;
+            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
+                const int col = idx / CPC, ch = idx % CPC;
+                const int64_t gcol = c0 + col;
+                const int64_t k0 = kt * BK + ch * EPC;
+                const XT* src = X + gcol * a.ldx + k0;
+                if (gcol < a.cols && k0 + EPC <= a.n) {
+                    rb[c] = *reinterpret_cast<const u4_t*>(src);
+                } else {
+                    XT tmp[EPC] __attribute__((aligned(16)));
+#pragma unroll
+                    for (int e = 0; e < EPC; ++e) tmp[e] = (gcol < a.cols && k0 + e < a.n) ? src[e] : (XT)0;
+                    rb[c] = *reinterpret_cast<const u4_t*>(tmp);
+                }
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < CA; ++c) {
+            const int idx = tid + c * NT;
+            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
+                *reinterpret_cast<u4_t*>(As[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int idx = tid + c * NT;
+            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
+                const int col = idx / CPC, ch = idx % CPC;
+                AT* dst = reinterpret_cast<AT*>(Bs[buf] + col * ROW_STRIDE) + ch * EPC;
+                const XT* x = reinterpret_cast<const XT*>(&rb[c]);
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) {
+                    if constexpr (sizeof(XT) == 1) dst[e] = from_i8<AT>((int8_t)x[e]);
+                    else dst[e] = from_f64<AT>((double)x[e]);
+                }
+            }
+        }
+    };
 
+    load(0);
+    store(0);
+    __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) {
-            load_a(ra, Ut, row_bytes, r0, (kt + 1) * ROW_BYTES, tid);
-            load_b<AT, XT>(rb, X, a.ldx, c0, a.cols, (kt + 1) * BK, a.n, tid);
-        }
-        u4_t af[4][2], bf[4][2];
+        if (more) load(kt + 1);
+        u4_t af[WTM][2], bf[WTN][2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const u4_t* pa = reinterpret_cast<const u4_t*>(As[buf] + (wr * 64 + i * 16 + li) * ROW_STRIDE + lg * 32);
+        for (int i = 0; i < WTM; ++i) {
+            const u4_t* pa = reinterpret_cast<const u4_t*>(As[buf] + (wr * WTM * 16 + i * 16 + li) * ROW_STRIDE + lg * 32);
             af[i][0] = pa[0];
             af[i][1] = pa[1];
-            const u4_t* pb = reinterpret_cast<const u4_t*>(Bs[buf] + (wc * 64 + i * 16 + li) * ROW_STRIDE + lg * 32);
-            bf[i][0] = pb[0];
-            bf[i][1] = pb[1];
+        }
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            const u4_t* pb = reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32);
+            bf[j][0] = pb[0];
+            bf[j][1] = pb[1];
         }
 #pragma unroll
         for (int s = 0; s < BK / 4 / T::KPL; ++s)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WTM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < WTN; ++j)
                     acc[i][j] = T::mma(frag<AT>(af[i], s), frag<AT>(bf[j], s), acc[i][j]);
         if constexpr (LOWP) {
             if ((kt + 1) % FLUSH_STAGES == 0 || !more) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WTM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < WTN; ++j) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
                         acc[i][j] = typename T::acc_t{0, 0, 0, 0};
                     }
             }
         }
-        if (more) {
-            store_a(ra, As[buf ^ 1], tid);
-            store_b<AT, XT>(rb, Bs[buf ^ 1], tid);
-        }
+        if (more) store(buf ^ 1);
         __syncthreads();
     }
     if constexpr (!LOWP) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc64[i][j] = acc[i][j];
+            for (int j = 0; j < WTN; ++j) acc64[i][j] = acc[i][j];
     }
 
-    // Epilogue: per column, sums over this wave's 64 rows.  Rows of lane
-    // (i, v): r0 + wr*64 + i*16 + ROW_G*lg + ROW_V*v; columns: c0 + wc*64 + j*16 + li.
+    // Epilogue: per column, sums over this wave's WTM*16 rows.  Rows of lane
+    // (i, v): r0 + wr*WTM*16 + i*16 + ROW_G*lg + ROW_V*v; columns:
+    // c0 + wc*WTN*16 + j*16 + li.
     const int Q = a.with_cross ? a.Qc + 1 : 1;
-    const int64_t pb = (r0 + wr * 64) / PART_ROWS;
-    const int64_t cbase = c0 + wc * 64 + li;
+    const int64_t rw = r0 + wr * WTM * 16;
+    const int64_t pb = rw / (WTM * 16);
+    const int64_t cbase = c0 + wc * WTN * 16 + li;
     if (a.with_cross) {
         for (int q = 0; q < a.Qc; ++q) {
-            const double* Cq = a.C + q * a.ldc + r0 + wr * 64 + T::ROW_G * lg;
-            double cv[4][4];
+            const double* Cq = a.C + q * a.ldc + rw + T::ROW_G * lg;
+            double cv[WTM][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WTM; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + T::ROW_V * v];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double s = 0.0;
+            for (int j = 0; j < WTN; ++j) {
+                double sum = 0.0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < WTM; ++i)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) s += acc64[i][j][v] * cv[i][v];
-                s = wave_sum16(s);
+                    for (int v = 0; v < 4; ++v) sum += acc64[i][j][v] * cv[i][v];
+                sum = wave_sum16(sum);
                 const int64_t col = cbase + j * 16;
-                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = s;
+                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
             }
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        double s = 0.0;
+    for (int j = 0; j < WTN; ++j) {
+        double sum = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) s += acc64[i][j][v] * acc64[i][j][v];
-        s = wave_sum16(s);
+            for (int v = 0; v < 4; ++v) sum += acc64[i][j][v] * acc64[i][j][v];
+        sum = wave_sum16(sum);
         const int64_t col = cbase + j * 16;
-        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = s;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
     }
 }
 
@@ -448,36 +442,90 @@ __global__ __launch_bounds__(128) void snp_solve_kernel(SolveArgs a) {
     }
 }
 
-template <typename AT, typename XT>
+// Tile shapes of the triangular product.  MINB is the workgroups per CU
+// the register budget is sized for.
+typedef Shape<2, 2, 4, 4, 2> Cfg0;   // 128 x 128, 256 threads, waves of 64 x 64
+typedef Shape<2, 4, 4, 2, 1> Cfg1;   // 128 x 128, 512 threads, waves of 64 x 32
+typedef Shape<4, 2, 2, 4, 1> Cfg2;   // 128 x 128, 512 threads, waves of 32 x 64
+typedef Shape<2, 4, 4, 4, 1> Cfg3;   // 128 x 256, 512 threads, waves of 64 x 64
+typedef Shape<4, 2, 4, 4, 1> Cfg4;   // 256 x 128, 512 threads, waves of 64 x 64
+typedef Shape<2, 2, 4, 4, 1> Cfg5;   // as Cfg0, one workgroup per CU
+
+template <typename S> TrmmShape shape_of() { return TrmmShape{S::TM, S::TN, S::WTM * 16, S::NT}; }
+
+template <typename AT, typename XT, typename S>
 hipError_t launch_trmm(const TrmmArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((trmm_stream_kernel<AT, XT>), dim3((unsigned)a.n_sched), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((trmm_stream_kernel<AT, XT, S>), dim3((unsigned)a.n_sched), dim3(S::NT), 0, s, a);
     return hipGetLastError();
+}
+
+template <typename AT, typename XT>
+hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
+    switch (a.cfg) {
+        case 0: return launch_trmm<AT, XT, Cfg0>(a, s);
+        case 1: return launch_trmm<AT, XT, Cfg1>(a, s);
+        case 2: return launch_trmm<AT, XT, Cfg2>(a, s);
+        case 3: return launch_trmm<AT, XT, Cfg3>(a, s);
+        case 4: return launch_trmm<AT, XT, Cfg4>(a, s);
+        case 5: return launch_trmm<AT, XT, Cfg5>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-int64_t trmm_schedule_len(int64_t n_pad, int64_t cols) {
-    const int64_t nrb = n_pad / TILE_M;
-    const int64_t ncb = (cols + TILE_N - 1) / TILE_N;
-    if (nrb < 16) return nrb * ncb;
-    // row blocks dealt to 8 XCD lists; the longest list sets the grid
-    int64_t longest = 0;
-    for (int x = 0; x < 8; ++x) {
-        int64_t len = 0;
-        for (int64_t r = 0; r < nrb; ++r) {
-            const int64_t grp = r / 8, pos = r % 8;
-            const int xcd = (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
-            if (xcd == x) len += ncb;
-        }
-        longest = std::max(longest, len);
+int trmm_num_cfgs() { return 6; }
+
+TrmmShape trmm_shape(int cfg) {
+    switch (cfg) {
+        case 0: return shape_of<Cfg0>();
+        case 1: return shape_of<Cfg1>();
+        case 2: return shape_of<Cfg2>();
+        case 3: return shape_of<Cfg3>();
+        case 4: return shape_of<Cfg4>();
+        case 5: return shape_of<Cfg5>();
+        default: return TrmmShape{0, 0, 0, 0};
     }
-    return 8 * longest;
 }
 
-int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap) {
-    const int64_t nrb = n_pad / TILE_M;
-    const int64_t ncb = (cols + TILE_N - 1) / TILE_N;
-    const int64_t total = trmm_schedule_len(n_pad, cols);
+bool trmm_cfg_valid(int at, int xt, int cfg) {
+    if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
+    if (at == A_F64) return true;
+    // The reduced-precision products also carry float64 partial sums; 64 x 64
+    // waves of them only fit two waves per SIMD without spilling when the
+    // staged dosages are int8 and the tile is 128 x 256.
+    if (cfg == 1 || cfg == 2 || cfg == 5) return true;
+    return cfg == 3 && xt == X_I8;
+}
+
+// Measured on MI355X at n = 50,000 with int8 dosages (SNPs per second of the
+// whole block, 32768-SNP sub-blocks): the 128 x 256 tile is fastest for
+// every element type; with float64 dosages the reduced-precision products
+// take the 128 x 128 tile of 64 x 32 waves.
+int trmm_default_cfg(int at, int xt) {
+    if (at == A_F64 || xt == X_I8) return 3;
+    return 1;
+}
+
+static int xcd_of_rank(int64_t r) {
+    const int64_t grp = r / 8, pos = r % 8;
+    return (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
+}
+
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, int tm, int tn) {
+    const int64_t nrb = n_pad / tm;
+    const int64_t ncb = (cols + tn - 1) / tn;
+    if (nrb < 16) return nrb * ncb;
+    // row blocks dealt to 8 XCD lists; the longest list sets the grid
+    int64_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t r = 0; r < nrb; ++r) len[xcd_of_rank(r)] += ncb;
+    return 8 * *std::max_element(len, len + 8);
+}
+
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, int tm, int tn, int* out, int64_t cap) {
+    const int64_t nrb = n_pad / tm;
+    const int64_t ncb = (cols + tn - 1) / tn;
+    const int64_t total = trmm_schedule_len(n_pad, cols, tm, tn);
     if (total > cap) return -1;
     if (nrb < 16) {
         int64_t b = 0;
@@ -491,13 +539,10 @@ int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap) {
     // Workgroup b runs on XCD b % 8.  Row blocks, longest (largest I) first,
     // are dealt to the XCDs in snake order (0..7, 7..0, ...), which balances
     // the triangular work; each XCD runs its row blocks in descending order
-    // with all column tiles of one row block together.
+    // with all column tiles of one row block together, so they share the
+    // L^-1 panel in that XCD's L2.
     std::vector<std::vector<int64_t>> rows(8);
-    for (int64_t r = 0; r < nrb; ++r) {
-        const int64_t grp = r / 8, pos = r % 8;
-        const int xcd = (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
-        rows[xcd].push_back(nrb - 1 - r);
-    }
+    for (int64_t r = 0; r < nrb; ++r) rows[xcd_of_rank(r)].push_back(nrb - 1 - r);
     const int64_t per = total / 8;
     for (int x = 0; x < 8; ++x) {
         int64_t q = 0;
@@ -516,23 +561,25 @@ int64_t trmm_schedule(int64_t n_pad, int64_t cols, int* out, int64_t cap) {
 
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
     if (a.cols <= 0) return hipSuccess;
+    if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;
+    const TrmmShape sh = trmm_shape(a.cfg);
     if (!a.Ut || !a.X || !a.part || !a.sched) return hipErrorInvalidValue;
-    if (a.n_pad % TILE_M || a.n_pad % PART_ROWS || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1)
+    if (a.n_pad % sh.tm || a.n_pad % NPAD_ALIGN || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1)
         return hipErrorInvalidValue;
     if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
     if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
-    if (a.n_sched != trmm_schedule_len(a.n_pad, a.cols) || a.n_sched > 0x7fffffff)
+    if (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh.tm, sh.tn) || a.n_sched > 0x7fffffff)
         return hipErrorInvalidValue;
     const size_t xs = a.xt == X_I8 ? 1 : 8;
     if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
     if (a.xt == X_F64) {
-        if (a.at == A_F64) return launch_trmm<double, double>(a, s);
-        if (a.at == A_F32) return launch_trmm<float, double>(a, s);
-        if (a.at == A_BF16) return launch_trmm<__bf16, double>(a, s);
+        if (a.at == A_F64) return launch_cfg<double, double>(a, s);
+        if (a.at == A_F32) return launch_cfg<float, double>(a, s);
+        if (a.at == A_BF16) return launch_cfg<__bf16, double>(a, s);
     } else if (a.xt == X_I8) {
-        if (a.at == A_F64) return launch_trmm<double, int8_t>(a, s);
-        if (a.at == A_F32) return launch_trmm<float, int8_t>(a, s);
-        if (a.at == A_BF16) return launch_trmm<__bf16, int8_t>(a, s);
+        if (a.at == A_F64) return launch_cfg<double, int8_t>(a, s);
+        if (a.at == A_F32) return launch_cfg<float, int8_t>(a, s);
+        if (a.at == A_BF16) return launch_cfg<__bf16, int8_t>(a, s);
     }
     return hipErrorInvalidValue;
 }

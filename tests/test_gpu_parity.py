@@ -151,3 +151,29 @@ def test_reduced_precision_vs_oracle(precision, tol):
     _say(f"  normwise err {err:.3e}")
     assert np.array_equal(info, io)
     assert err < tol
+
+
+TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5], "bf16": [1, 2, 3, 5]}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_every_tile_shape(precision, monkeypatch):
+    # every tile shape the library may pick gives the oracle's answer
+    n, p, m, seed = 700, 5, 900, 123
+    prob = synth.make_problem(n, p, seed, k=300)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    bo, _, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    tol = {"fp64": TOL_FP64, "fp32": TOL_FP32, "bf16": 1e-2}[precision]
+    ref = None
+    for cfg in TILE_SHAPES[precision]:
+        monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
+        _say(f"{precision} tile shape {cfg} n={n} m={m}")
+        b, _, info = run(prob, XR, precision=precision, x_dtype="i8", dev_block=384)
+        assert np.array_equal(info, io)
+        err = normwise(b, bo)
+        _say(f"  err {err:.3e}")
+        assert err < tol
+        if precision == "fp64":
+            # float64 sums differ between shapes only in rounding order
+            ref = b if ref is None else ref
+            assert normwise(b, ref) < 1e-13
