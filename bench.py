@@ -29,7 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "SNP GLS solves/sec at n=50k,p=8 (mixed vs FP64); TRSM % of MFMA peak"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense matrix-core peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}   # dense matrix-core peaks
+SLICES = 6   # int8 digits per entry of L^-1 in the int8 leg
 WORKLOADS = {
     "n50000_p8": dict(n=50_000, p=8, m=1_000_000, step=50_000, x_dtype="i8"),
     "n20000_p4": dict(n=20_000, p=4, m=500_000, step=50_000, x_dtype="f64"),
@@ -77,14 +78,14 @@ def cpu_baseline(workload, seed, n_s, m_s, threads):
     }
 
 
-def run_leg(name, prob_dev, blocks, steps, warmup, workload):
+def run_leg(name, prob_dev, blocks, steps, warmup, workload, pcie_steps=0):
     import torch
     from paper_1304_2272_amd import binding
     n = workload["n"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx = binding.GwasContext(prob_dev["M"], prob_dev["XL"], prob_dev["Y"], precision=name,
-                              x_dtype=workload["x_dtype"])
+                              x_dtype=workload["x_dtype"], slices=SLICES if name == "int8" else 0)
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t0
     outs = []
@@ -100,21 +101,43 @@ def run_leg(name, prob_dev, blocks, steps, warmup, workload):
     elapsed = time.perf_counter() - t0
     launches, kms, kcols = ctx.kernel_time()
     info_bad = int((info != 0).sum())
+    pcie = None
+    if pcie_steps:
+        # the same blocks handed over in pinned host memory: PCIe-inclusive rate
+        host = [blocks[s % len(blocks)].cpu().pin_memory() for s in range(pcie_steps)]
+        out = (torch.empty((host[0].shape[0], 1, workload["p"]), dtype=torch.float64).pin_memory(),
+               torch.empty(host[0].shape[0], dtype=torch.float64).pin_memory(),
+               torch.empty(host[0].shape[0], dtype=torch.int32).pin_memory())
+        ctx.stream_block(host[0], out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for h in host:
+            ctx.stream_block(h, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        nb = sum(h.numel() * h.element_size() for h in host)
+        pcie = {"snps_per_s": sum(h.shape[0] for h in host) / el, "host_to_device_GBps": nb / el / 1e9,
+                "steps": pcie_steps, "note": "dosages in pinned host memory, b/var/info to pinned host memory"}
+        log(f"[{name}] PCIe-inclusive: {pcie['snps_per_s']:.1f} SNP/s, {pcie['host_to_device_GBps']:.1f} GB/s of dosages")
     ctx.close()
     snps = sum(blocks[(warmup + s) % len(blocks)].shape[0] for s in range(steps))
-    flops = float(n) * float(n) * kcols           # L^-1 x: n^2 flops per SNP
-    achieved = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    ops_per_snp = float(n) * float(n) * (SLICES if name == "int8" else 1)
+    achieved = ops_per_snp * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    fp64_equiv = float(n) * float(n) * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     peak = PEAK_TFLOPS[name]
     log(f"[{name}] init {init_s:.2f} s, {snps} SNPs in {elapsed:.3f} s = {snps / elapsed:.1f} SNP/s, "
-        f"TRMM {launches} launches {kms:.1f} ms -> {achieved:.2f} TFLOP/s ({achieved / peak:.3f} of peak)")
+        f"TRMM {launches} launches {kms:.1f} ms -> {achieved:.2f} T{'OP' if name == 'int8' else 'FLOP'}/s "
+        f"({achieved / peak:.3f} of peak)")
     return {
         "snps_per_s": snps / elapsed, "elapsed_s": elapsed, "init_s": init_s, "snps": snps,
         "ms_per_step": 1e3 * elapsed / max(steps, 1),
         "kernel": {"launches": launches, "total_ms": kms, "avg_ms": kms / max(launches, 1),
                    "columns": kcols},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TOP/s" if name == "int8" else "TFLOP/s", "frac": achieved / peak},
+        "n2_tflops": fp64_equiv,
         "rank_flags_last_step": info_bad,
+        "pcie": pcie,
     }, outs
 
 
@@ -124,9 +147,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n50000_p8", choices=sorted(WORKLOADS))
-    ap.add_argument("--legs", default="fp32,fp64,bf16")
+    ap.add_argument("--legs", default="fp32,fp64,int8,bf16")
     ap.add_argument("--fp64-steps", type=int, default=4)
     ap.add_argument("--bf16-steps", type=int, default=2)
+    ap.add_argument("--int8-steps", type=int, default=4)
+    ap.add_argument("--pcie-steps", type=int, default=2,
+                    help="blocks streamed from pinned host memory after the timed steps (main leg)")
     ap.add_argument("--step-snps", type=int, default=0)
     ap.add_argument("--seed", type=int, default=1306)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -157,7 +183,7 @@ def main():
     prob = synth.make_problem(n, p, args.seed, device="cuda:0")
     prob_dev = {"M": prob["M"], "XL": torch.from_numpy(prob["XL"]).to(dev),
                 "Y": torch.from_numpy(prob["Y"]).to(dev)}
-    nblk = args.warmup + max(args.steps, args.fp64_steps, args.bf16_steps)
+    nblk = args.warmup + max(args.steps, args.fp64_steps, args.bf16_steps, args.int8_steps)
     xdt = torch.int8 if w["x_dtype"] == "i8" else torch.float64
     blocks = [synth.snp_block_device(n, args.seed, i * step, step, dev, dtype=xdt) for i in range(nblk)]
     torch.cuda.synchronize()
@@ -172,11 +198,13 @@ def main():
         log(f"copy probe: {nb} bytes read and written")
         del src, dst
 
-    steps_of = {"fp32": args.steps, "fp64": args.fp64_steps, "bf16": args.bf16_steps}
+    steps_of = {"fp32": args.steps, "fp64": args.fp64_steps, "bf16": args.bf16_steps,
+                "int8": args.int8_steps}
     steps_of[main_leg] = args.steps
     res, outs = {}, {}
     for leg in legs:
-        res[leg], outs[leg] = run_leg(leg, prob_dev, blocks, steps_of[leg], args.warmup, w)
+        res[leg], outs[leg] = run_leg(leg, prob_dev, blocks, steps_of[leg], args.warmup, w,
+                                      pcie_steps=args.pcie_steps if leg == main_leg else 0)
     errs = {}
     if "fp64" in outs:
         for leg in legs:
@@ -213,7 +241,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[main_leg],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "int8": "i8"}[main_leg],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "p": p, "snps_per_step": step,
                    "x_dtype": "int8" if w["x_dtype"] == "i8" else "f64",
@@ -222,8 +250,10 @@ def main():
         "cpu_baseline": cpu,
         "init_s": {k: v["init_s"] for k, v in res.items()},
         "legs": {k: {"snps_per_s": v["snps_per_s"], "ms_per_step": v["ms_per_step"],
-                     "roofline": v["roofline"], "kernel": v["kernel"], "snps": v["snps"]}
+                     "roofline": v["roofline"], "n2_tflops": v["n2_tflops"], "kernel": v["kernel"],
+                     "snps": v["snps"]}
                  for k, v in res.items()},
+        "pcie_inclusive": r["pcie"],
         "err_vs_fp64": errs,
         "end_to_end_snps_per_s": end_to_end,
         "end_to_end_m": w["m"],

@@ -63,6 +63,13 @@ extern "C" {
                                   cross products and the p x p solve in
                                   float64 with two refinement steps          */
 #define GWAS_BF16_REFINE   2   /* as above with bfloat16 operands           */
+#define GWAS_INT8_SLICED   3   /* L^-1 held as `slices` int8 digits per entry
+                                  with a power-of-two scale per row; the
+                                  product with int8 dosages runs on int8
+                                  matrix cores with exact int32 sums and one
+                                  float64 combination; cross products and
+                                  the p x p solve as in GWAS_FP32_REFINE.
+                                  Needs x_dtype = GWAS_X_I8.                */
 
 /* ---- element type of the SNP dosages handed to gwas_stream_block -------- */
 #define GWAS_X_F64         0   /* float64                                   */
@@ -88,6 +95,8 @@ typedef struct gwas_desc {
     void*   workspace;       /* caller device memory, or NULL: library allocates */
     size_t  workspace_bytes; /* size of workspace when given                 */
     void*   stream;          /* hipStream_t for compute, NULL: library stream */
+    int32_t slices;          /* GWAS_INT8_SLICED: digits per entry, 4..6
+                                (0 = 6); ignored otherwise                  */
 } gwas_desc;
 
 /*
@@ -96,7 +105,7 @@ typedef struct gwas_desc {
  * workspace must pass at least this many bytes, 256-byte aligned.
  */
 size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block,
-                            int32_t precision, int32_t x_dtype);
+                            int32_t precision, int32_t x_dtype);   /* slices = 6 */
 
 /*
  * Create a context: copies M, X_L and y to the device, factors M = L L^T
@@ -110,7 +119,8 @@ size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block,
  * owns all library memory (the caller's workspace, if given, must outlive
  * it).  Errors: GWAS_E_INVALID (n < p, p outside 2..20, t outside 1..256,
  * ld < n, NULL pointer, unknown precision or x_dtype; checked before any
- * device call), GWAS_E_NO_DEVICE, GWAS_E_WORKSPACE, GWAS_E_OOM, GWAS_E_HIP,
+ * device call; GWAS_INT8_SLICED with float64 dosages or slices outside
+ * 4..6), GWAS_E_NO_DEVICE, GWAS_E_WORKSPACE, GWAS_E_OOM, GWAS_E_HIP,
  * GWAS_E_NOT_SPD (gwas_info gives the 1-based order of the first leading
  * minor of M that is not positive, as LAPACK's potrf does) and
  * GWAS_E_RANK_XL.  On GWAS_E_NOT_SPD and GWAS_E_RANK_XL *out is set so that

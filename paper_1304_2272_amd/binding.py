@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgwas.so"
 GWAS_OK = 0
 ERRORS = {1: "GWAS_E_INVALID", 2: "GWAS_E_NOT_SPD", 3: "GWAS_E_RANK_XL", 4: "GWAS_E_NO_DEVICE",
           5: "GWAS_E_HIP", 6: "GWAS_E_OOM", 7: "GWAS_E_STATE", 8: "GWAS_E_WORKSPACE"}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "int8": 3}
 X_DTYPES = {"f64": 0, "i8": 1}
 
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
@@ -45,6 +45,7 @@ class Desc(ctypes.Structure):
         ("dev_block", ctypes.c_int64),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("slices", ctypes.c_int32),
     ]
 
 
@@ -137,7 +138,7 @@ class GwasContext:
     """One factorisation of M and its derived constants, reused for every block."""
 
     def __init__(self, M, XL, Y, precision="fp64", x_dtype="f64", dev_block=0, device=0,
-                 stream=None):
+                 stream=None, slices=0):
         L = load()
         self._lib = L
         self.precision = precision
@@ -169,7 +170,7 @@ class GwasContext:
         d = Desc(n=n, p=p, t=t, M=mp, ldm=n, XL=xlp, ldxl=n, Y=yp, ldy=n,
                  inputs_on_device=1 if dev else 0, precision=PRECISIONS[precision],
                  x_dtype=X_DTYPES[x_dtype], device=device, dev_block=dev_block,
-                 workspace=None, workspace_bytes=0, stream=stream)
+                 workspace=None, workspace_bytes=0, stream=stream, slices=slices)
         h = ctypes.c_void_p()
         rc = L.gwas_init(ctypes.byref(h), ctypes.byref(d))
         del keep

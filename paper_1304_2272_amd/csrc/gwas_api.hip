@@ -23,12 +23,14 @@ constexpr int MAX_T = 256;
 constexpr double RANK_TOL_F64 = 1e-10;
 constexpr double RANK_TOL_F32 = 1e-6;
 constexpr double RANK_TOL_BF16 = 1e-2;
+constexpr double RANK_TOL_I8S = 1e-10;
+constexpr int DEFAULT_SLICES = 6;
 constexpr int REFINE_STEPS = 2;
 
 struct Layout {
     int64_t n, n_pad, ld, dev_block, npb_max, Q;
-    int p, t, q1, Qc, precision, x_dtype;
-    size_t off_L, off_U, off_Ulow, off_XY, off_C, off_W, off_S, off_consts, off_flags,
+    int p, t, q1, Qc, precision, x_dtype, slices;
+    size_t off_L, off_U, off_Ulow, off_rscale, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
     size_t off_xbuf[2], off_part, off_xw, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
@@ -43,14 +45,21 @@ bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t pre
     if (p < 2 || p > 20 || n < p || t < 1 || t > MAX_T) return false;
     if (n > (int64_t)1 << 24) return false;
     if (dev_block < 0 || dev_block > ((int64_t)1 << 22)) return false;
-    if (precision != GWAS_FP64 && precision != GWAS_FP32_REFINE && precision != GWAS_BF16_REFINE)
-        return false;
+    if (precision < GWAS_FP64 || precision > GWAS_INT8_SLICED) return false;
     if (x_dtype != GWAS_X_F64 && x_dtype != GWAS_X_I8) return false;
+    if (precision == GWAS_INT8_SLICED && x_dtype != GWAS_X_I8) return false;
     return true;
 }
 
-Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, int x_dtype) {
+int atype_of(int precision) {
+    return precision == GWAS_FP64 ? A_F64 : precision == GWAS_FP32_REFINE ? A_F32
+         : precision == GWAS_BF16_REFINE ? A_BF16 : A_I8S;
+}
+
+Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, int x_dtype,
+                   int slices) {
     Layout L{};
+    L.slices = slices;
     L.n = n;
     L.p = p;
     L.t = t;
@@ -61,7 +70,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.n_pad = (n + NPAD_ALIGN - 1) / NPAD_ALIGN * NPAD_ALIGN;
     L.ld = L.n_pad;
     L.dev_block = dev_block > 0 ? (dev_block + TILE_N - 1) / TILE_N * TILE_N : DEFAULT_DEV_BLOCK;
-    L.npb_max = L.n_pad / MIN_PART_ROWS;
+    L.npb_max = L.n_pad / (precision == GWAS_INT8_SLICED ? trmm_sliced_shape().part_rows : MIN_PART_ROWS);
     L.Q = (precision == GWAS_FP64) ? L.Qc + 1 : 1;
     const size_t nn = (size_t)L.ld * (size_t)L.n_pad;
     const size_t A = 256;
@@ -70,7 +79,9 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_L = take(nn * 8);
     L.off_U = take(nn * 8);
     L.off_Ulow = (precision == GWAS_FP32_REFINE) ? take(nn * 4)
-               : (precision == GWAS_BF16_REFINE) ? take(nn * 2) : 0;
+               : (precision == GWAS_BF16_REFINE) ? take(nn * 2)
+               : (precision == GWAS_INT8_SLICED) ? take(nn * (size_t)slices) : 0;
+    L.off_rscale = (precision == GWAS_INT8_SLICED) ? take((size_t)L.n_pad * 8) : 0;
     L.off_XY = take((size_t)L.n_pad * L.Qc * 8);
     L.off_C = take((size_t)L.n_pad * L.Qc * 8);
     L.off_W = (precision != GWAS_FP64) ? take((size_t)L.n_pad * L.Qc * 8) : 0;
@@ -78,9 +89,13 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_consts = take((size_t)consts_len(L.q1, t) * 8);
     L.off_flags = take(256);
     // room for the schedule and partial sums of every tile shape
-    const int at = precision == GWAS_FP64 ? A_F64 : precision == GWAS_FP32_REFINE ? A_F32 : A_BF16;
+    const int at = atype_of(precision);
     L.sched_len = 0;
-    for (int c = 0; c < trmm_num_cfgs(); ++c) {
+    if (at == A_I8S) {
+        const TrmmShape sh = trmm_sliced_shape();
+        L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh.tm, sh.tn);
+    }
+    for (int c = 0; c < trmm_num_cfgs() && at != A_I8S; ++c) {
         if (!trmm_cfg_valid(at, x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c)) continue;
         const TrmmShape sh = trmm_shape(c);
         L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh.tm, sh.tn));
@@ -120,6 +135,8 @@ struct gwas_ctx {
     double *L = nullptr, *U = nullptr, *XY = nullptr, *C = nullptr, *W = nullptr, *S = nullptr,
            *consts = nullptr;
     void* Ulow = nullptr;
+    double* rscale = nullptr;
+    TrmmShape shape{};
     int* flags = nullptr;
     int* sched = nullptr;
     int* sched_tail = nullptr;
@@ -255,7 +272,7 @@ void release(gwas_ctx* c) {
 }
 
 int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host) {
-    const TrmmShape sh = trmm_shape(c->cfg);
+    const TrmmShape sh = c->shape;
     const int64_t len = trmm_schedule_len(c->lay.n_pad, cols, sh.tm, sh.tn);
     host.assign((size_t)(2 * len), 0);
     if (len > (int64_t)c->lay.sched_len ||
@@ -301,8 +318,10 @@ int init_body(gwas_ctx* c, const gwas_desc* d) {
         HIPCHK(c, gemm_f64(g, s));
         if (Y.precision == GWAS_FP32_REFINE)
             HIPCHK(c, convert_f32(c->U, (float*)c->Ulow, ld, n_pad, n_pad, s));
-        else
+        else if (Y.precision == GWAS_BF16_REFINE)
             HIPCHK(c, convert_bf16(c->U, (__bf16*)c->Ulow, ld, n_pad, n_pad, s));
+        else
+            HIPCHK(c, slice_rows(c->U, ld, n_pad, Y.slices, (int8_t*)c->Ulow, n_pad, c->rscale, s));
     }
     rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
     if (rc) return rc;
@@ -329,7 +348,7 @@ extern "C" {
 size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
                             int32_t x_dtype) {
     if (!sizes_valid(n, p, t, dev_block, precision, x_dtype)) return 0;
-    return make_layout(n, p, t, dev_block, precision, x_dtype).total;
+    return make_layout(n, p, t, dev_block, precision, x_dtype, DEFAULT_SLICES).total;
 }
 
 int gwas_init(gwas_ctx** out, const gwas_desc* d) {
@@ -339,6 +358,8 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     if (!sizes_valid(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype)) return GWAS_E_INVALID;
     if (d->ldm < d->n || d->ldxl < d->n || d->ldy < d->n) return GWAS_E_INVALID;
     if (d->workspace && (reinterpret_cast<uintptr_t>(d->workspace) % 256)) return GWAS_E_INVALID;
+    const int slices = (d->precision == GWAS_INT8_SLICED) ? (d->slices ? d->slices : DEFAULT_SLICES) : 0;
+    if (d->precision == GWAS_INT8_SLICED && (slices < 4 || slices > 6)) return GWAS_E_INVALID;
 
     gwas_ctx* c = new (std::nothrow) gwas_ctx();
     if (!c) return GWAS_E_OOM;
@@ -349,15 +370,16 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         delete c;
         return rc;
     }
-    c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype);
+    c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype, slices);
     const Layout& Y = c->lay;
-    c->at = d->precision == GWAS_FP64 ? A_F64 : d->precision == GWAS_FP32_REFINE ? A_F32 : A_BF16;
+    c->at = atype_of(d->precision);
     c->cfg = trmm_default_cfg(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64);
     if (const char* e = getenv("GWAS_TRMM_CFG")) {
         // tile-shape override for measurement; ignored when not valid here
         const int v = atoi(e);
         if (trmm_cfg_valid(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, v)) c->cfg = v;
     }
+    c->shape = (c->at == A_I8S) ? trmm_sliced_shape() : trmm_shape(c->cfg);
     auto bail = [&](int code) {
         release(c);
         c->magic = CTX_DEAD;
@@ -380,6 +402,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->L = (double*)(w + Y.off_L);
     c->U = (double*)(w + Y.off_U);
     c->Ulow = Y.off_Ulow ? (void*)(w + Y.off_Ulow) : nullptr;
+    c->rscale = Y.off_rscale ? (double*)(w + Y.off_rscale) : nullptr;
     c->XY = (double*)(w + Y.off_XY);
     c->C = (double*)(w + Y.off_C);
     c->W = Y.off_W ? (double*)(w + Y.off_W) : nullptr;
@@ -447,7 +470,8 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     const int at = c->at;
     const void* Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
     const double tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
-                     : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32 : RANK_TOL_BF16;
+                     : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32
+                     : (Y.precision == GWAS_BF16_REFINE) ? RANK_TOL_BF16 : RANK_TOL_I8S;
     const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
     if (c->timing && (int64_t)c->tev.size() < 2 * nsub) {
         while ((int64_t)c->tev.size() < 2 * nsub) {
@@ -518,7 +542,9 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         ta.ldp = Y.dev_block;
         ta.sched = sched;
         ta.cfg = c->cfg;
-        ta.n_sched = trmm_schedule_len(Y.n_pad, cols, trmm_shape(c->cfg).tm, trmm_shape(c->cfg).tn);
+        ta.slices = Y.slices;
+        ta.rscale = c->rscale;
+        ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape.tm, c->shape.tn);
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
         HIPCHK(c, trmm_stream(ta, c->s_comp));
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
@@ -531,7 +557,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         sa.cols = cols;
         sa.part = c->part;
         sa.ldp = Y.dev_block;
-        sa.npb = Y.n_pad / trmm_shape(c->cfg).part_rows;
+        sa.npb = Y.n_pad / c->shape.part_rows;
         sa.Q = Y.Q;
         sa.xw = c->xw;
         sa.ldxw = Y.dev_block;

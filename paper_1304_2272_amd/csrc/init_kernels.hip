@@ -221,6 +221,41 @@ __global__ void convert_kernel(const double* __restrict__ in, T* __restrict__ ou
             out[r + c * ld] = (T)in[r + c * ld];
 }
 
+// One workgroup per row of L^-1 (grid-stride): block max, power-of-two
+// scale, then exact 7-bit digits (every step is a multiplication by a power
+// of two or the subtraction of a nearby integer, so no rounding occurs).
+__global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ U, int64_t ld,
+                                                         int64_t n_pad, int S, int8_t* __restrict__ A,
+                                                         int64_t lda, double* __restrict__ rscale) {
+    __shared__ double red[256];
+    for (int64_t r = blockIdx.x; r < n_pad; r += gridDim.x) {
+        const double* col = U + r * ld;      // L^-1(r, k) = U(k, r), zero for k > r
+        double m = 0.0;
+        for (int64_t k = threadIdx.x; k <= r; k += blockDim.x) m = fmax(m, fabs(col[k]));
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        m = red[0];
+        __syncthreads();
+        int e = 0;
+        if (m > 0.0) (void)frexp(m, &e);        // m < 2^e
+        const double sc = ldexp(1.0, e);
+        if (threadIdx.x == 0) rscale[r] = sc;
+        const int64_t base = (r / 16) * 16 * S + (r % 16);
+        for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) {
+            double t = (k <= r) ? ldexp(col[k], 6 - e) : 0.0;   // (L^-1(r,k)/sc) * 2^6, |t| <= 64
+            for (int sl = 0; sl < S; ++sl) {
+                const double q = rint(t);
+                A[(base + sl * 16) * lda + k] = (int8_t)q;
+                t = (t - q) * 128.0;
+            }
+        }
+    }
+}
+
 // R = chol(S_TL), v = R^-1 bbar_T; single thread (q1 <= 19).
 __global__ void snp_constants_kernel(const double* S, int64_t lds, int q1, int t, double* K,
                                      int* fail) {
@@ -306,6 +341,15 @@ hipError_t convert_bf16(const double* in, __bf16* out, int64_t ld, int64_t rows,
     if (ld < rows) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<int64_t>(cols, 8192);
     hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(grid), dim3(256), 0, s, in, out, ld, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int S, int8_t* A, int64_t lda,
+                      double* rscale, hipStream_t s) {
+    if (!U || !A || !rscale || S < 1 || S > 8 || ld < n_pad || lda < n_pad || n_pad % 16)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(n_pad, 16384);
+    hipLaunchKernelGGL(slice_rows_kernel, dim3(grid), dim3(256), 0, s, U, ld, n_pad, S, A, lda, rscale);
     return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ __host__ __device__ inline int64_t consts_bT(int q1, int t) { return 2 * (int64_
 __host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64_t)q1 * q1 + 2 * (int64_t)q1 * t; }
 
 // ---- streaming kernels ---------------------------------------------------
-enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2 };
+enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2, A_I8S = 3 };
 enum XType : int { X_F64 = 0, X_I8 = 1 };
 
 // Z = L^-1 X for one sub-block, never stored: for every slice of part_rows
@@ -85,6 +85,8 @@ enum XType : int { X_F64 = 0, X_I8 = 1 };
 //   cfg   tile shape (trmm_shape).
 struct TrmmArgs {
     int at, xt, cfg;
+    int slices;                 // A_I8S: int8 slices per row of L^-1
+    const double* rscale;       // A_I8S: power-of-two scale of each row of L^-1
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const double* C; int64_t ldc; int Qc;
@@ -99,7 +101,15 @@ int trmm_num_cfgs();
 TrmmShape trmm_shape(int cfg);
 bool trmm_cfg_valid(int at, int xt, int cfg);
 int trmm_default_cfg(int at, int xt);
-constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of any shape
+constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of the floating-point shapes
+TrmmShape trmm_sliced_shape();       // tile of the int8-slice product (part_rows 16)
+
+// Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
+// and S int8 slices A_s(r,k) with L^-1(r,k)/rscale[r] = sum_s A_s(r,k) 2^(-6-7s)
+// up to 2^(-6-7S) / 2, written to sliced row (r/16)*16*S + s*16 + r%16 of A
+// (lda bytes per row).
+hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int S, int8_t* A,
+                      int64_t lda, double* rscale, hipStream_t s);
 
 // Host side: tile schedule for n_pad rows and `cols` SNP columns with tm x tn
 // tiles.  Returns the number of workgroups and fills `out` (2 ints each).

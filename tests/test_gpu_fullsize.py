@@ -1,0 +1,103 @@
+"""Parity at the workloads' full sizes, in the bench's launch configuration.
+
+n = 20,000 (FP64, float64 dosages streamed from host memory in 5,000-SNP host
+blocks): sampled SNPs against the oracle, chosen at both ends of every host
+block and at random.  n = 50,000 (int8 dosages resident on the device, the
+bench workload): the reduced-precision modes against the FP64 path on every
+SNP of a 32,768-SNP block, and the FP64 path against planted coefficients.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import GLSOracle
+from paper_1304_2272_amd import binding, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def normwise(b, bref):
+    num = np.linalg.norm((b - bref).reshape(b.shape[0], -1), axis=1)
+    den = np.linalg.norm(bref.reshape(b.shape[0], -1), axis=1)
+    return float(np.max(num / den))
+
+
+@pytest.mark.timeout(900)
+def test_n20000_fp64_streamed_sampled_vs_oracle():
+    n, p, seed, hb, nblk = 20_000, 4, 1305, 5_000, 4
+    _say(f"n={n} p={p}: {nblk} host blocks of {hb} float64 SNPs")
+    prob = synth.make_problem(n, p, seed)
+    b_all = []
+    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"]) as ctx:
+        for k in range(nblk):
+            XR = synth.snp_block(n, seed, k * hb, hb)
+            b, var, info = ctx.stream_block(XR)
+            assert (info == 0).all()
+            b_all.append(b)
+    b_all = np.concatenate(b_all)
+    rng = np.random.default_rng(seed)
+    idx = sorted(set([j for k in range(nblk) for j in list(range(k * hb, k * hb + 8)) +
+                      list(range((k + 1) * hb - 8, (k + 1) * hb))] +
+                     list(rng.choice(nblk * hb, 128, replace=False))))
+    chunks = {}
+    for j in idx:
+        c = j // synth.CHUNK
+        if c not in chunks:
+            chunks[c] = synth.snp_chunk(n, seed, c)
+    XS = np.stack([chunks[j // synth.CHUNK][j % synth.CHUNK] for j in idx])
+    _say(f"  oracle on {len(idx)} sampled SNPs")
+    bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XS)
+    err = normwise(b_all[idx], bo)
+    _say(f"  max normwise err {err:.3e}")
+    assert err < 1e-10
+
+
+@pytest.fixture(scope="module")
+def n50k():
+    import torch
+    n, p, seed, m = 50_000, 8, 1306, 32_768
+    dev = torch.device("cuda:0")
+    _say(f"n={n} p={p}: generating on the device")
+    prob = synth.make_problem(n, p, seed, device="cuda:0")
+    data = {"M": prob["M"], "XL": torch.from_numpy(prob["XL"]).to(dev),
+            "Y": torch.from_numpy(prob["Y"]).to(dev),
+            "X": synth.snp_block_device(n, seed, 0, m, dev), "beta": prob["beta"], "seed": seed}
+    with binding.GwasContext(data["M"], data["XL"], data["Y"], x_dtype="i8") as ctx:
+        b, var, info = ctx.stream_block(data["X"])
+        data["b64"] = b.cpu().numpy()
+        data["info64"] = info.cpu().numpy()
+    yield data
+    del data
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-8), ("int8", 1e-10)])
+def test_n50000_reduced_vs_fp64_all_snps(n50k, precision, tol):
+    _say(f"n=50000 p=8 {precision} vs fp64 on 32768 SNPs")
+    with binding.GwasContext(n50k["M"], n50k["XL"], n50k["Y"], precision=precision,
+                             x_dtype="i8") as ctx:
+        b, var, info = ctx.stream_block(n50k["X"])
+    b = b.cpu().numpy()
+    assert np.array_equal(info.cpu().numpy(), n50k["info64"])
+    err = normwise(b, n50k["b64"])
+    _say(f"  max normwise err {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.timeout(600)
+def test_n50000_fp64_planted(n50k):
+    import torch
+    # noise-free y = X_L beta: every SNP must give b = (beta, 0)
+    Yp = n50k["XL"] @ torch.from_numpy(n50k["beta"]).to(n50k["XL"].device)
+    _say("n=50000 p=8 fp64 planted coefficients")
+    with binding.GwasContext(n50k["M"], n50k["XL"], Yp, x_dtype="i8") as ctx:
+        b, _, info = ctx.stream_block(n50k["X"][:4096])
+    want = np.concatenate([n50k["beta"][:, 0], [0.0]])
+    dev = np.max(np.abs(b.cpu().numpy()[:, 0, :] - want))
+    _say(f"  max |b - planted| {dev:.3e}")
+    assert (info.cpu().numpy() == 0).all() and dev < 1e-9

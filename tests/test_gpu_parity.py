@@ -139,7 +139,7 @@ def test_rank_deficient_snp_and_not_spd():
     assert ei.value.code == 3
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16", 1e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16", 1e-2), ("int8", TOL_FP64)])
 def test_reduced_precision_vs_oracle(precision, tol):
     n, p, m, seed = 1500, 8, 3000, 77
     _say(f"{precision} n={n} p={p} m={m}")
@@ -177,3 +177,26 @@ def test_every_tile_shape(precision, monkeypatch):
             # float64 sums differ between shapes only in rounding order
             ref = b if ref is None else ref
             assert normwise(b, ref) < 1e-13
+
+
+@pytest.mark.parametrize("slices,tol", [(4, 1e-8), (5, 1e-9), (6, TOL_FP64)])
+def test_int8_slices(slices, tol):
+    # int8 digits of L^-1 against int8 dosages, exact int32 sums
+    n, p, m, seed = 2100, 6, 2500, 91
+    _say(f"int8 slices={slices} n={n} p={p} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    b, var, info = run(prob, XR, precision="int8", x_dtype="i8", slices=slices, dev_block=1024)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    err = normwise(b, bo)
+    verr = float(np.max(np.abs(var - vo) / vo))
+    _say(f"  normwise err {err:.3e} var err {verr:.3e}")
+    assert np.array_equal(info, io)
+    assert err < tol and verr < 100 * tol
+
+
+def test_int8_slices_needs_int8_dosages():
+    prob = synth.make_problem(100, 3, 1)
+    with pytest.raises(binding.GwasError) as ei:
+        binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision="int8", x_dtype="f64")
+    assert ei.value.code == 1
