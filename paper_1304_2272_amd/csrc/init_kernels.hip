@@ -21,76 +21,91 @@ __device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// 128 x GBK slab of an operand in registers: 8 doubles per thread.
-// kcontig: element (r,k) at P[k + r*ld] (K contiguous); else P[r + k*ld].
-__device__ __forceinline__ void load_slab(double (&v)[8], const double* __restrict__ P, int64_t ld,
-                                          bool kcontig, int64_t r0, int64_t rlim, int64_t k0,
+// R x GBK slab of an operand, moved global -> registers -> LDS in 16-byte
+// chunks of two doubles.  kcontig: element (r,k) at P[k + r*ld]; otherwise at
+// P[r + k*ld] (and the chunk is two consecutive r, stored transposed).
+// Out-of-range elements are zero; `vec` allows 16-byte loads (ld even and P
+// 16-byte aligned).
+template <int R, int NT> struct Slab {
+    static constexpr int CH = R * GBK / 2;           // chunks per stage
+    static constexpr int PER = (CH + NT - 1) / NT;
+    d2_t v[PER];
+};
+
+template <int R, int NT, bool kcontig>
+__device__ __forceinline__ void load_slab(Slab<R, NT>& sl, const double* __restrict__ P, int64_t ld,
+                                          bool vec, int64_t r0, int64_t rlim, int64_t k0,
                                           int64_t klim, int tid) {
-    if (kcontig) {
-        const int r = tid >> 1, kk = (tid & 1) * 8;
-        const int64_t row = r0 + r;
-        if (row < rlim && k0 + kk + 8 <= klim) {
-            const double* src = P + row * ld + k0 + kk;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = src[j];
+    for (int c = 0; c < Slab<R, NT>::PER; ++c) {
+        const int idx = tid + c * NT;
+        if (Slab<R, NT>::CH % NT != 0 && idx >= Slab<R, NT>::CH) break;
+        int64_t r, k;
+        if constexpr (kcontig) {
+            r = r0 + idx / (GBK / 2);
+            k = k0 + (idx % (GBK / 2)) * 2;
+            if (vec && r < rlim && k + 2 <= klim) {
+                sl.v[c] = *reinterpret_cast<const d2_t*>(P + r * ld + k);
+            } else {
+                sl.v[c][0] = (r < rlim && k < klim) ? P[r * ld + k] : 0.0;
+                sl.v[c][1] = (r < rlim && k + 1 < klim) ? P[r * ld + k + 1] : 0.0;
+            }
         } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                v[j] = (row < rlim && k0 + kk + j < klim) ? P[row * ld + k0 + kk + j] : 0.0;
-        }
-    } else {
-        const int k = tid >> 4, rr = (tid & 15) * 8;
-        const int64_t kk = k0 + k;
-        if (kk < klim && r0 + rr + 8 <= rlim) {
-            const double* src = P + kk * ld + r0 + rr;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = src[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                v[j] = (kk < klim && r0 + rr + j < rlim) ? P[kk * ld + r0 + rr + j] : 0.0;
+            k = k0 + idx / (R / 2);
+            r = r0 + (idx % (R / 2)) * 2;
+            if (vec && k < klim && r + 2 <= rlim) {
+                sl.v[c] = *reinterpret_cast<const d2_t*>(P + k * ld + r);
+            } else {
+                sl.v[c][0] = (k < klim && r < rlim) ? P[k * ld + r] : 0.0;
+                sl.v[c][1] = (k < klim && r + 1 < rlim) ? P[k * ld + r + 1] : 0.0;
+            }
         }
     }
 }
 
-__device__ __forceinline__ void store_slab(const double (&v)[8], double (*S)[GLD], bool kcontig,
-                                           int tid) {
-    if (kcontig) {
-        const int r = tid >> 1, kk = (tid & 1) * 8;
+template <int R, int NT, bool kcontig>
+__device__ __forceinline__ void store_slab(const Slab<R, NT>& sl, double (*S)[GLD], int tid) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) S[r][kk + j] = v[j];
-    } else {
-        const int k = tid >> 4, rr = (tid & 15) * 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) S[rr + j][k] = v[j];
+    for (int c = 0; c < Slab<R, NT>::PER; ++c) {
+        const int idx = tid + c * NT;
+        if (Slab<R, NT>::CH % NT != 0 && idx >= Slab<R, NT>::CH) break;
+        if constexpr (kcontig) {
+            *reinterpret_cast<d2_t*>(&S[idx / (GBK / 2)][(idx % (GBK / 2)) * 2]) = sl.v[c];
+        } else {
+            const int k = idx / (R / 2), r = (idx % (R / 2)) * 2;
+            S[r][k] = sl.v[c][0];
+            S[r + 1][k] = sl.v[c][1];
+        }
     }
 }
 
-// One 128 x 128 tile per workgroup; four waves in a 2 x 2 grid, 64 x 64 each
-// as 4 x 4 blocks of the 16x16x4 float64 matrix instruction.  Within a K
-// stage, lane group g = lane/16 supplies k = 4g + s at instruction step s,
-// for A and B alike, so every k of the stage is summed exactly once.
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
+// One 128 x (WGN*64) tile per workgroup of 2 x WGN waves, 64 x 64 each as
+// 4 x 4 blocks of the 16x16x4 float64 matrix instruction.  Within a K stage,
+// lane group g = lane/16 supplies k = 4g + s at instruction step s, for A
+// and B alike, so every k of the stage is summed exactly once.
+template <int WGN, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(128 * WGN, (WGN == 2 ? 2 : 1)) void gemm_f64_kernel(GemmArgs g, int avec,
+                                                                                 int bvec) {
+    constexpr int NT = 128 * WGN;
+    constexpr int TN = 64 * WGN;
     const int64_t m0 = (int64_t)blockIdx.x * TILE_M;
-    const int64_t n0 = (int64_t)blockIdx.y * TILE_N;
+    const int64_t n0 = (int64_t)blockIdx.y * TN;
     if (g.lower_only && m0 + TILE_M <= n0) return;
 
     int64_t kbeg = 0, kend = g.K;
     if (g.kflags & KR_A_LOWER) kend = min(kend, m0 + TILE_M);
-    if (g.kflags & KR_B_UPPER) kend = min(kend, n0 + TILE_N);
+    if (g.kflags & KR_B_UPPER) kend = min(kend, n0 + TN);
     if (g.kflags & KR_A_UPPER) kbeg = max(kbeg, m0);
     if (g.kflags & KR_B_LOWER) kbeg = max(kbeg, n0);
     kbeg = (kbeg / GBK) * GBK;
 
-    __shared__ double As[2][TILE_M][GLD];
-    __shared__ double Bs[2][TILE_N][GLD];
+    __shared__ __attribute__((aligned(16))) double As[2][TILE_M][GLD];
+    __shared__ __attribute__((aligned(16))) double Bs[2][TN][GLD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / WGN, wc = wave % WGN;
     const int li = lane & 15, lg = lane >> 4;
-    const bool a_kc = (g.opA == 'T');
-    const bool b_kc = (g.opB == 'N');
 
     d4_t acc[4][4];
 #pragma unroll
@@ -99,12 +114,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
         for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
     const int64_t nk = (kend > kbeg) ? (kend - kbeg + GBK - 1) / GBK : 0;
-    double ra[8], rb[8];
+    Slab<TILE_M, NT> ra;
+    Slab<TN, NT> rb;
     if (nk > 0) {
-        load_slab(ra, g.A, g.lda, a_kc, m0, g.M, kbeg, kend, tid);
-        load_slab(rb, g.B, g.ldb, b_kc, n0, g.N, kbeg, kend, tid);
-        store_slab(ra, As[0], a_kc, tid);
-        store_slab(rb, Bs[0], b_kc, tid);
+        load_slab<TILE_M, NT, A_KC>(ra, g.A, g.lda, avec, m0, g.M, kbeg, kend, tid);
+        load_slab<TN, NT, B_KC>(rb, g.B, g.ldb, bvec, n0, g.N, kbeg, kend, tid);
+        store_slab<TILE_M, NT, A_KC>(ra, As[0], tid);
+        store_slab<TN, NT, B_KC>(rb, Bs[0], tid);
     }
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
@@ -112,29 +128,27 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
         const bool more = kt + 1 < nk;
         if (more) {
             const int64_t k0 = kbeg + (kt + 1) * GBK;
-            load_slab(ra, g.A, g.lda, a_kc, m0, g.M, k0, kend, tid);
-            load_slab(rb, g.B, g.ldb, b_kc, n0, g.N, k0, kend, tid);
-        }
-        d2_t av[4][2], bv[4][2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const d2_t* pa = reinterpret_cast<const d2_t*>(&As[buf][wr * 64 + i * 16 + li][4 * lg]);
-            av[i][0] = pa[0];
-            av[i][1] = pa[1];
-            const d2_t* pb = reinterpret_cast<const d2_t*>(&Bs[buf][wc * 64 + i * 16 + li][4 * lg]);
-            bv[i][0] = pb[0];
-            bv[i][1] = pb[1];
+            load_slab<TILE_M, NT, A_KC>(ra, g.A, g.lda, avec, m0, g.M, k0, kend, tid);
+            load_slab<TN, NT, B_KC>(rb, g.B, g.ldb, bvec, n0, g.N, k0, kend, tid);
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int h = 0; h < 2; ++h) {
+            d2_t av[4], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) {
+                av[i] = *reinterpret_cast<const d2_t*>(&As[buf][wr * 64 + i * 16 + li][4 * lg + 2 * h]);
+                bv[i] = *reinterpret_cast<const d2_t*>(&Bs[buf][wc * 64 + i * 16 + li][4 * lg + 2 * h]);
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = mfma_f64(av[i][s >> 1][s & 1], bv[j][s >> 1][s & 1], acc[i][j]);
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(av[i][s], bv[j][s], acc[i][j]);
+        }
         if (more) {
-            store_slab(ra, As[buf ^ 1], a_kc, tid);
-            store_slab(rb, Bs[buf ^ 1], b_kc, tid);
+            store_slab<TILE_M, NT, A_KC>(ra, As[buf ^ 1], tid);
+            store_slab<TN, NT, B_KC>(rb, Bs[buf ^ 1], tid);
         }
         __syncthreads();
     }
@@ -305,9 +319,26 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t s) {
     if (g.ldc < g.M) return hipErrorInvalidValue;
     if (g.opA == 'N' ? g.lda < g.M : g.lda < g.K) return hipErrorInvalidValue;
     if (g.opB == 'N' ? g.ldb < g.K : g.ldb < g.N) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((g.M + TILE_M - 1) / TILE_M), (unsigned)((g.N + TILE_N - 1) / TILE_N));
+    const int avec = (g.lda % 2 == 0) && (reinterpret_cast<uintptr_t>(g.A) % 16 == 0);
+    const int bvec = (g.ldb % 2 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
+    const bool akc = g.opA == 'T', bkc = g.opB == 'N';
+    const bool wide = g.N >= 256;
+    dim3 grid((unsigned)((g.M + TILE_M - 1) / TILE_M), (unsigned)((g.N + (wide ? 255 : 127)) / (wide ? 256 : 128)));
     if (grid.y > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, g);
+#define GWAS_GEMM_LAUNCH(W, AK, BK)                                                              \
+    hipLaunchKernelGGL((gemm_f64_kernel<W, AK, BK>), grid, dim3(128 * W), 0, s, g, avec, bvec)
+    if (wide) {
+        if (akc && bkc) GWAS_GEMM_LAUNCH(4, true, true);
+        else if (akc) GWAS_GEMM_LAUNCH(4, true, false);
+        else if (bkc) GWAS_GEMM_LAUNCH(4, false, true);
+        else GWAS_GEMM_LAUNCH(4, false, false);
+    } else {
+        if (akc && bkc) GWAS_GEMM_LAUNCH(2, true, true);
+        else if (akc) GWAS_GEMM_LAUNCH(2, true, false);
+        else if (bkc) GWAS_GEMM_LAUNCH(2, false, true);
+        else GWAS_GEMM_LAUNCH(2, false, false);
+    }
+#undef GWAS_GEMM_LAUNCH
     return hipGetLastError();
 }
 
