@@ -156,12 +156,82 @@ def run_leg(name, prob_dev, blocks, steps, warmup, workload, pcie_steps=0):
     }, outs
 
 
+def run_cohorts(args):
+    """Eight cohorts of uneven n (2k..30k), h^2 ~ U(0.2, 0.8), t = 64 traits,
+    p = 4, sharing SNP positions with cohort-specific int8 dosages; a step is
+    one block of SNP positions solved for every cohort and trait."""
+    import torch
+    from paper_1304_2272_amd import binding, synth
+    binding.load()
+    dev = torch.device("cuda:0")
+    p, t, step = 4, 64, args.step_snps or 16384
+    spec = synth.cohorts(8, args.seed)
+    log("cohorts n =", [c["n"] for c in spec], "h2 =", [round(c["h2"], 3) for c in spec])
+    data = []
+    for i, c in enumerate(spec):
+        pr = synth.make_problem(c["n"], p, c["seed"], t=t, h2=c["h2"], device="cuda:0")
+        data.append({"M": pr["M"], "XL": torch.from_numpy(pr["XL"]).to(dev),
+                     "Y": torch.from_numpy(pr["Y"]).to(dev), "n": c["n"],
+                     "X": [synth.snp_block_device(c["n"], args.seed, s * step, step, dev, cohort=i)
+                           for s in range(args.warmup + args.steps)]})
+    torch.cuda.synchronize()
+    n2 = sum(float(d["n"]) ** 2 for d in data)
+    legs = {}
+    outs = {}
+    for leg, precision, grouped in [("fp64_grouped", "fp64", True), ("fp64_sequential", "fp64", False),
+                                    ("fp32_grouped", "fp32", True), ("int8_grouped", "int8", True)]:
+        t0 = time.perf_counter()
+        ctxs = [binding.GwasContext(d["M"], d["XL"], d["Y"], precision=precision, x_dtype="i8",
+                                    slices=SLICES if precision == "int8" else 0) for d in data]
+        torch.cuda.synchronize()
+        init_s = time.perf_counter() - t0
+        def one(s):
+            if grouped:
+                return binding.stream_group(ctxs, [d["X"][s] for d in data])
+            return [c.stream_block(d["X"][s]) for c, d in zip(ctxs, data)]
+        for s in range(args.warmup):
+            one(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [one(args.warmup + s) for s in range(args.steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        for c in ctxs:
+            c.close()
+        outs[leg] = res
+        rate = args.steps * step * len(data) / el
+        tflops = n2 * step * args.steps / el / 1e12
+        legs[leg] = {"cohort_snps_per_s": rate, "trait_solves_per_s": rate * t, "init_s": init_s,
+                     "ms_per_step": 1e3 * el / args.steps, "n2_tflops_whole_step": tflops}
+        log(f"[{leg}] init {init_s:.2f} s; {rate:.1f} cohort-SNP/s ({rate * t:.3g} trait solves/s), "
+            f"{tflops:.1f} TFLOP/s of triangular products over the whole step")
+    errs = {}
+    for leg in ("fp32_grouped", "int8_grouped"):
+        errs[leg] = max(normwise(outs[leg][s][c][0], outs["fp64_grouped"][s][c][0])
+                        for s in range(args.steps) for c in range(len(data)))
+    seq_same = all(torch.equal(outs["fp64_sequential"][s][c][0], outs["fp64_grouped"][s][c][0])
+                   for s in range(args.steps) for c in range(len(data)))
+    log("errors vs fp64:", errs, "grouped == sequential bitwise:", seq_same)
+    main = legs["fp32_grouped"]
+    line = {
+        "metric": "cohort-SNP GLS solves/sec, 8 cohorts n~U(2k,30k), t=64 traits, p=4",
+        "value": main["cohort_snps_per_s"], "unit": "cohort-SNP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cohorts8_t64", "cohort_n": [d["n"] for d in data], "p": p, "t": t,
+                   "snps_per_step": step, "x_dtype": "int8", "precision": "fp32",
+                   "inputs": "device-resident", "parallelism": "single GPU"},
+        "legs": legs, "err_vs_fp64": errs, "grouped_equals_sequential": seq_same,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n50000_p8", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="n50000_p8", choices=sorted(WORKLOADS) + ["cohorts8_t64"])
     ap.add_argument("--legs", default="fp32,fp64,int8,bf16")
     ap.add_argument("--fp64-steps", type=int, default=4)
     ap.add_argument("--bf16-steps", type=int, default=2)
@@ -181,6 +251,10 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cohorts8_t64":
+        run_cohorts(args)
+        return
 
     import torch
     from paper_1304_2272_amd import binding, synth

@@ -94,7 +94,10 @@ typedef struct gwas_desc {
     int64_t dev_block;       /* SNP columns per device sub-block, 0 = auto   */
     void*   workspace;       /* caller device memory, or NULL: library allocates */
     size_t  workspace_bytes; /* size of workspace when given                 */
-    void*   stream;          /* hipStream_t for compute, NULL: library stream */
+    void*   stream;          /* hipStream_t the caller's inputs are produced on
+                                (NULL = the default stream): every call first
+                                waits for the work queued there; the library
+                                computes on streams of its own            */
     int32_t slices;          /* GWAS_INT8_SLICED: digits per entry, 4..6
                                 (0 = 6); ignored otherwise                  */
 } gwas_desc;
@@ -150,6 +153,46 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d);
  */
 int gwas_stream_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
                       double* b, int64_t ldb, double* var_snp, int32_t* info);
+
+/*
+ * Several cohorts at once (the multi-cohort, multi-trait workload): contexts
+ * with their own M, X_L, y and n, sharing the SNP positions of a block of
+ * mblk SNPs.  Each sub-block of every context goes into ONE grouped launch
+ * of the triangular product, whose tile schedule deals every (context, row
+ * block) to the XCDs longest first, so cohorts of uneven n fill the chip
+ * together; the cross products and p x p solves follow per context.
+ * Results are identical to gwas_stream_block on each context.
+ *
+ *   ctxs, nctx   1..64 distinct contexts on one device with the same
+ *                precision, x_dtype, dev_block and tile shape
+ *   XR[i], ldx[i], b[i], ldb[i], var_snp[i], info[i]   as in
+ *                gwas_stream_block for context i (var_snp, info and their
+ *                entries may be NULL)
+ *   flags        GWAS_GROUP_GRAPH: full-width sub-blocks replay one HIP
+ *                graph of the grouped product, cross products and solves,
+ *                captured at first use (dosages are copied into and
+ *                results out of fixed device buffers around each replay)
+ *
+ * All work runs on the first context's compute stream; the call returns
+ * when every output is written.  Errors: GWAS_E_INVALID (incompatible or
+ * repeated contexts, bad sizes), GWAS_E_STATE, GWAS_E_HIP, GWAS_E_OOM.
+ */
+#define GWAS_GROUP_GRAPH 1
+int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR,
+                      const int64_t* ldx, int64_t mblk, double* const* b, const int64_t* ldb,
+                      double* const* var_snp, int32_t* const* info, int32_t flags);
+
+/*
+ * Pick the tile shape of the triangular product by timing every admissible
+ * shape on `cols` (<= dev_block) SNP columns of XR (host or device), and
+ * keep the fastest for later calls.  With the environment variable
+ * GWAS_TUNE_CACHE naming a file, an earlier result for the same padded n,
+ * precision, dosage type and width is reused and new results are appended.
+ * *best_cfg (may be NULL) receives the chosen shape, -1 for
+ * GWAS_INT8_SLICED (one shape).  Results of later calls are unchanged up to
+ * float64 rounding order.
+ */
+int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg);
 
 /* Release a context (NULL is accepted).  Later use returns GWAS_E_STATE. */
 int gwas_free(gwas_ctx* ctx);

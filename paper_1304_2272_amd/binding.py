@@ -31,7 +31,8 @@ X_DTYPES = {"f64": 0, "i8": 1}
 
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
-             "gwas_kernel_time", "gwas_query")
+             "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune")
+GROUP_GRAPH = 1
 
 
 class Desc(ctypes.Structure):
@@ -95,6 +96,12 @@ def load():
                                    ctypes.POINTER(i64)]
     L.gwas_query.restype = ctypes.c_int
     L.gwas_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.gwas_stream_group.restype = ctypes.c_int
+    L.gwas_stream_group.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64), i64,
+                                    ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), i32]
+    L.gwas_autotune.restype = ctypes.c_int
+    L.gwas_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32)]
     _lib = L
     return L
 
@@ -215,6 +222,24 @@ class GwasContext:
         self._check(rc)
         return b, var, info
 
+    def _outputs(self, m, xdev, device):
+        if xdev:
+            import torch
+            return (torch.empty((m, self.t, self.p), dtype=torch.float64, device=device),
+                    torch.empty(m, dtype=torch.float64, device=device),
+                    torch.empty(m, dtype=torch.int32, device=device))
+        return np.empty((m, self.t, self.p)), np.empty(m), np.empty(m, dtype=np.int32)
+
+    def autotune(self, XR, cols=None):
+        """Time every tile shape on the first ``cols`` SNPs of XR; keep the fastest."""
+        xdt = np.int8 if self.x_dtype == "i8" else np.float64
+        xp, ldx, keep, _ = _ptr_ld(XR, xdt, "XR")
+        cols = XR.shape[0] if cols is None else cols
+        best = ctypes.c_int32()
+        self._check(self._lib.gwas_autotune(self._h, xp, ldx, cols, ctypes.byref(best)))
+        del keep
+        return best.value
+
     def set_timing(self, on=True):
         self._check(self._lib.gwas_set_timing(self._h, 1 if on else 0))
 
@@ -250,3 +275,38 @@ class GwasContext:
             self.close()
         except Exception:
             pass
+
+
+def stream_group(ctxs, XRs, graph=False):
+    """Solve the same SNP positions for several contexts (cohorts) in grouped
+    launches; returns a list of (b, var, info) per context."""
+    L = load()
+    n = len(ctxs)
+    if len(XRs) != n or n == 0:
+        raise ValueError("one dosage block per context")
+    xdt = np.int8 if ctxs[0].x_dtype == "i8" else np.float64
+    ptrs, lds, keeps, outs = [], [], [], []
+    m = XRs[0].shape[0]
+    for c, X in zip(ctxs, XRs):
+        if X.shape[0] != m:
+            raise ValueError("all blocks must hold the same SNP positions")
+        xp, ldx, keep, xdev = _ptr_ld(X, xdt, "XR")
+        ptrs.append(xp)
+        lds.append(ldx)
+        keeps.append(keep)
+        outs.append(c._outputs(m, xdev, X.device if xdev else None))
+    ptr = (lambda a: a.data_ptr()) if _is_torch(outs[0][0]) else (lambda a: a.ctypes.data)
+    VP = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    hs = (VP * n)(*[c._h.value for c in ctxs])
+    xs = (VP * n)(*ptrs)
+    lx = (I64 * n)(*lds)
+    bs = (VP * n)(*[ptr(o[0]) for o in outs])
+    lb = (I64 * n)(*[c.p * c.t for c in ctxs])
+    vs = (VP * n)(*[ptr(o[1]) for o in outs])
+    ins = (VP * n)(*[ptr(o[2]) for o in outs])
+    rc = L.gwas_stream_group(hs, n, xs, lx, m, bs, lb, vs, ins, GROUP_GRAPH if graph else 0)
+    del keeps
+    if rc != GWAS_OK:
+        raise GwasError(rc, L.gwas_last_error(ctxs[0]._h).decode())
+    return outs

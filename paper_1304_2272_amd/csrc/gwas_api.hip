@@ -4,6 +4,7 @@
 #include "gwas.h"
 #include "internal.h"
 
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -151,6 +152,8 @@ struct gwas_ctx {
     int* ibuf[2] = {nullptr, nullptr};
     double* tmp = nullptr;
     hipStream_t s_comp = nullptr, s_h2d = nullptr, s_d2h = nullptr;
+    hipStream_t s_user = nullptr;   // caller's stream: joined before each call reads inputs
+    hipEvent_t ev_user = nullptr;
     bool own_comp = false;
     hipEvent_t ev_loaded[2] = {}, ev_done[2] = {}, ev_out[2] = {};
     std::vector<int> host_sched, host_tail;
@@ -160,6 +163,28 @@ struct gwas_ctx {
     double t_ms = 0.0;
     int64_t info = 0;
     std::string err;
+    struct Group* grp = nullptr;    // grouped-launch state, owned by the first context of a group
+};
+
+// State of grouped launches (gwas_stream_group), kept by the group's first
+// context: the combined tile schedule, per-context kernel arguments (pinned
+// host and device copies, double buffered) and an optional captured graph.
+struct Group {
+    std::vector<const gwas_ctx*> key;
+    int64_t sched_cols = -1;
+    int* d_sched = nullptr;
+    size_t sched_cap = 0;
+    int64_t n_sched = 0;
+    TrmmArgs* h_args[2] = {nullptr, nullptr};
+    TrmmArgs* d_args[2] = {nullptr, nullptr};
+    std::vector<int> host_sched;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const gwas_ctx*> graph_key;
+    // the graph's own argument array and schedule, never rewritten after capture
+    TrmmArgs* h_args_graph = nullptr;
+    TrmmArgs* d_args_graph = nullptr;
+    int* d_sched_graph = nullptr;
 };
 
 namespace {
@@ -179,6 +204,13 @@ int fail_hip(gwas_ctx* c, hipError_t e, const char* what) {
     } while (0)
 
 bool live(const gwas_ctx* c) { return c && c->magic == CTX_MAGIC && !c->poisoned; }
+
+// make `s` wait for everything the caller queued on its own stream so far
+hipError_t join_user(gwas_ctx* c, hipStream_t s) {
+    hipError_t e = hipEventRecord(c->ev_user, c->s_user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_user, 0);
+    return e;
+}
 
 bool on_device(const void* p) {
     if (!p) return false;
@@ -264,9 +296,25 @@ void release(gwas_ctx* c) {
         if (c->ev_out[s]) (void)hipEventDestroy(c->ev_out[s]);
     }
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    if (c->grp) {
+        Group* g = c->grp;
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        for (int s = 0; s < 2; ++s) {
+            if (g->h_args[s]) (void)hipHostFree(g->h_args[s]);
+            if (g->d_args[s]) (void)hipFree(g->d_args[s]);
+        }
+        if (g->d_sched) (void)hipFree(g->d_sched);
+        if (g->h_args_graph) (void)hipHostFree(g->h_args_graph);
+        if (g->d_args_graph) (void)hipFree(g->d_args_graph);
+        if (g->d_sched_graph) (void)hipFree(g->d_sched_graph);
+        delete g;
+        c->grp = nullptr;
+    }
     if (c->s_h2d) (void)hipStreamDestroy(c->s_h2d);
     if (c->s_d2h) (void)hipStreamDestroy(c->s_d2h);
     if (c->own_comp && c->s_comp) (void)hipStreamDestroy(c->s_comp);
+    if (c->ev_user) (void)hipEventDestroy(c->ev_user);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     (void)hipGetLastError();
 }
@@ -285,12 +333,110 @@ int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host)
     return GWAS_OK;
 }
 
+TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols) {
+    const Layout& Y = c->lay;
+    TrmmArgs ta{};
+    ta.at = c->at;
+    ta.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    ta.cfg = c->cfg;
+    ta.slices = Y.slices;
+    ta.rscale = c->rscale;
+    ta.Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
+    ta.ldu = Y.ld;
+    ta.n_pad = Y.n_pad;
+    ta.X = xptr;
+    ta.ldx = xld;
+    ta.n = Y.n;
+    ta.cols = cols;
+    ta.C = c->C;
+    ta.ldc = Y.n_pad;
+    ta.Qc = Y.Qc;
+    ta.with_cross = (Y.precision == GWAS_FP64);
+    ta.part = c->part;
+    ta.ldp = Y.dev_block;
+    ta.sched = c->sched;
+    ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape.tm, c->shape.tn);
+    return ta;
+}
+
+SolveArgs solve_args_for(const gwas_ctx* c, int64_t cols, double* bo, int64_t ldbo, double* vo, int* io) {
+    const Layout& Y = c->lay;
+    SolveArgs sa{};
+    sa.p = Y.p;
+    sa.t = Y.t;
+    sa.cols = cols;
+    sa.part = c->part;
+    sa.ldp = Y.dev_block;
+    sa.npb = Y.n_pad / c->shape.part_rows;
+    sa.Q = Y.Q;
+    sa.xw = c->xw;
+    sa.ldxw = Y.dev_block;
+    sa.consts = c->consts;
+    sa.refine = (Y.precision == GWAS_FP64) ? 0 : REFINE_STEPS;
+    sa.rank_tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
+                : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32
+                : (Y.precision == GWAS_BF16_REFINE) ? RANK_TOL_BF16 : RANK_TOL_I8S;
+    sa.b = bo;
+    sa.ldb = ldbo;
+    sa.var = vo;
+    sa.info = io;
+    return sa;
+}
+
+// Cross products x^T W (reduced modes) and the per-SNP solves of one sub-block.
+hipError_t finish_sub(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, double* bo,
+                      int64_t ldbo, double* vo, int* io, hipStream_t s) {
+    const Layout& Y = c->lay;
+    if (Y.precision != GWAS_FP64) {
+        hipError_t e = snp_cross_w((Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64, xptr, xld, Y.n, cols, c->W,
+                                   Y.n_pad, Y.Qc, c->xw, Y.dev_block, s);
+        if (e != hipSuccess) return e;
+    }
+    return snp_solve(solve_args_for(c, cols, bo, ldbo, vo, io), s);
+}
+
+// Combined tile schedule of several contexts with one tile shape: every
+// (context, row block) is a unit of work (K length x column tiles), dealt
+// longest first to the least loaded of the 8 XCD lists (workgroup b runs on
+// XCD b % 8); each list keeps its units in that order.
+int64_t group_schedule(const std::vector<gwas_ctx*>& cs, int64_t cols, std::vector<int>& out) {
+    const TrmmShape sh = cs[0]->shape;
+    const int64_t ncb = (cols + sh.tn - 1) / sh.tn;
+    struct Unit { int64_t w; int c; int I; };
+    std::vector<Unit> units;
+    for (size_t c = 0; c < cs.size(); ++c) {
+        const int64_t nrb = cs[c]->lay.n_pad / sh.tm;
+        for (int64_t I = 0; I < nrb; ++I) units.push_back(Unit{(I + 1) * sh.tm, (int)c, (int)I});
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.w > b.w; });
+    std::vector<std::vector<int>> lists(8);
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const Unit& u : units) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        load[x] += u.w * ncb;
+        lists[x].push_back((int)(u.I | (u.c << SCHED_CTX_SHIFT)));
+    }
+    size_t longest = 0;
+    for (auto& l : lists) longest = std::max(longest, l.size() * (size_t)ncb);
+    out.assign(2 * 8 * longest, -1);
+    for (int x = 0; x < 8; ++x) {
+        size_t q = 0;
+        for (int e : lists[x])
+            for (int64_t J = 0; J < ncb; ++J, ++q) {
+                out[2 * (8 * q + x)] = e;
+                out[2 * (8 * q + x) + 1] = (int)J;
+            }
+    }
+    return (int64_t)(8 * longest);
+}
+
 int init_body(gwas_ctx* c, const gwas_desc* d) {
     const Layout& Y = c->lay;
     const int64_t ld = Y.ld, n = Y.n, n_pad = Y.n_pad;
     hipStream_t s = c->s_comp;
     const hipMemcpyKind kin = d->inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
 
+    HIPCHK(c, join_user(c, s));
     HIPCHK(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->flags), INT_MAX, 1, s));
     HIPCHK(c, hipMemsetAsync(c->flags + 1, 0, 4, s));
     // M -> L (the lower triangle is what the factorisation reads), identity padding
@@ -421,13 +567,12 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
     c->tmp = (double*)(w + Y.off_tmp);
 
-    hipError_t e = hipSuccess;
-    if (d->stream) {
-        c->s_comp = static_cast<hipStream_t>(d->stream);
-    } else {
-        e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking);
-        c->own_comp = true;
-    }
+    // The library computes on streams of its own (default priority); work the
+    // caller queued on its stream before a call is joined through an event.
+    c->s_user = static_cast<hipStream_t>(d->stream);
+    hipError_t e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking);
+    c->own_comp = true;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_h2d, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_d2h, hipStreamNonBlocking);
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {
@@ -459,6 +604,8 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     if (!XR || !b || ldx < Y.n || ldb < (int64_t)Y.p * Y.t) return GWAS_E_INVALID;
     HIPCHK(c, hipSetDevice(c->device));
 
+    HIPCHK(c, join_user(c, c->s_comp));
+    HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_user, 0));
     const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
     const char* xr = static_cast<const char*>(XR);
     const bool x_dev = on_device(XR);
@@ -467,11 +614,6 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     const bool direct_out = on_device(b) && (!var_snp || on_device(var_snp)) &&
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
-    const int at = c->at;
-    const void* Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
-    const double tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
-                     : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32
-                     : (Y.precision == GWAS_BF16_REFINE) ? RANK_TOL_BF16 : RANK_TOL_I8S;
     const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
     if (c->timing && (int64_t)c->tev.size() < 2 * nsub) {
         while ((int64_t)c->tev.size() < 2 * nsub) {
@@ -524,51 +666,12 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
             }
             sched = c->sched_tail;
         }
-        TrmmArgs ta{};
-        ta.at = at;
-        ta.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
-        ta.Ut = Ut;
-        ta.ldu = Y.ld;
-        ta.n_pad = Y.n_pad;
-        ta.X = xptr;
-        ta.ldx = xld;
-        ta.n = Y.n;
-        ta.cols = cols;
-        ta.C = c->C;
-        ta.ldc = Y.n_pad;
-        ta.Qc = Y.Qc;
-        ta.with_cross = (Y.precision == GWAS_FP64);
-        ta.part = c->part;
-        ta.ldp = Y.dev_block;
+        TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
         ta.sched = sched;
-        ta.cfg = c->cfg;
-        ta.slices = Y.slices;
-        ta.rscale = c->rscale;
-        ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape.tm, c->shape.tn);
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
         HIPCHK(c, trmm_stream(ta, c->s_comp));
         if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
-        if (Y.precision != GWAS_FP64)
-            HIPCHK(c, snp_cross_w(ta.xt, xptr, xld, Y.n, cols, c->W, Y.n_pad, Y.Qc, c->xw,
-                                  Y.dev_block, c->s_comp));
-        SolveArgs sa{};
-        sa.p = Y.p;
-        sa.t = Y.t;
-        sa.cols = cols;
-        sa.part = c->part;
-        sa.ldp = Y.dev_block;
-        sa.npb = Y.n_pad / c->shape.part_rows;
-        sa.Q = Y.Q;
-        sa.xw = c->xw;
-        sa.ldxw = Y.dev_block;
-        sa.consts = c->consts;
-        sa.refine = (Y.precision == GWAS_FP64) ? 0 : REFINE_STEPS;
-        sa.rank_tol = tol;
-        sa.b = bo;
-        sa.ldb = ldbo;
-        sa.var = vo;
-        sa.info = io;
-        HIPCHK(c, snp_solve(sa, c->s_comp));
+        HIPCHK(c, finish_sub(c, xptr, xld, cols, bo, ldbo, vo, io, c->s_comp));
         HIPCHK(c, hipEventRecord(c->ev_done[slot], c->s_comp));
         if (!direct_out) {
             HIPCHK(c, hipStreamWaitEvent(c->s_d2h, c->ev_done[slot], 0));
@@ -593,6 +696,291 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
             c->t_cols += std::min<int64_t>(Y.dev_block, mblk - k * Y.dev_block);
         }
     }
+    return GWAS_OK;
+}
+
+int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR, const int64_t* ldx,
+                      int64_t mblk, double* const* b, const int64_t* ldb, double* const* var_snp,
+                      int32_t* const* info, int32_t flags) {
+    if (!ctxs || nctx < 1 || nctx > MAX_GROUP || !XR || !ldx || !b || !ldb || mblk < 0)
+        return GWAS_E_INVALID;
+    if (flags & ~GWAS_GROUP_GRAPH) return GWAS_E_INVALID;
+    for (int i = 0; i < nctx; ++i)
+        if (!live(ctxs[i])) return GWAS_E_STATE;
+    gwas_ctx* c0 = ctxs[0];
+    for (int i = 0; i < nctx; ++i) {
+        const gwas_ctx* c = ctxs[i];
+        if (c->device != c0->device || c->at != c0->at || c->cfg != c0->cfg ||
+            c->lay.x_dtype != c0->lay.x_dtype || c->lay.dev_block != c0->lay.dev_block ||
+            c->lay.slices != c0->lay.slices)
+            return GWAS_E_INVALID;
+        if (!XR[i] || !b[i] || ldx[i] < c->lay.n || ldb[i] < (int64_t)c->lay.p * c->lay.t)
+            return GWAS_E_INVALID;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return GWAS_E_INVALID;
+    }
+    if (mblk == 0) return GWAS_OK;
+    HIPCHK(c0, hipSetDevice(c0->device));
+    if (!c0->grp) c0->grp = new (std::nothrow) Group();
+    Group* g = c0->grp;
+    if (!g) return GWAS_E_OOM;
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!g->h_args[sl]) HIPCHK(c0, hipHostMalloc((void**)&g->h_args[sl], MAX_GROUP * sizeof(TrmmArgs), 0));
+        if (!g->d_args[sl]) HIPCHK(c0, hipMalloc((void**)&g->d_args[sl], MAX_GROUP * sizeof(TrmmArgs)));
+    }
+    std::vector<gwas_ctx*> cs(ctxs, ctxs + nctx);
+    std::vector<const gwas_ctx*> key(cs.begin(), cs.end());
+    hipStream_t s = c0->s_comp;
+    for (int i = 0; i < nctx; ++i) HIPCHK(c0, join_user(cs[i], s));
+    const int64_t blk = c0->lay.dev_block;
+    const size_t elem = (c0->lay.x_dtype == GWAS_X_I8) ? 1 : 8;
+    std::vector<char> direct_x(nctx), direct_out(nctx);
+    for (int i = 0; i < nctx; ++i) {
+        direct_x[i] = on_device(XR[i]) && (reinterpret_cast<uintptr_t>(XR[i]) % 16 == 0) &&
+                      ((ldx[i] * (int64_t)elem) % 16 == 0);
+        direct_out[i] = on_device(b[i]) && (!var_snp || !var_snp[i] || on_device(var_snp[i])) &&
+                        (!info || !info[i] || on_device(info[i]));
+    }
+    const bool want_graph = (flags & GWAS_GROUP_GRAPH) != 0;
+    const int64_t nsub = (mblk + blk - 1) / blk;
+    if (c0->timing && (int64_t)c0->tev.size() < 2 * nsub) {
+        while ((int64_t)c0->tev.size() < 2 * nsub) {
+            hipEvent_t ev;
+            HIPCHK(c0, hipEventCreate(&ev));
+            c0->tev.push_back(ev);
+        }
+    }
+    auto ensure_schedule = [&](int64_t cols) -> int {
+        if (g->key == key && g->sched_cols == cols) return GWAS_OK;
+        const int64_t len = group_schedule(cs, cols, g->host_sched);
+        const size_t bytes = g->host_sched.size() * sizeof(int);
+        HIPCHK(c0, hipStreamSynchronize(s));   // no launch may still read the old schedule
+        if (bytes > g->sched_cap) {
+            if (g->d_sched) HIPCHK(c0, hipFree(g->d_sched));
+            g->d_sched = nullptr;
+            HIPCHK(c0, hipMalloc((void**)&g->d_sched, bytes));
+            g->sched_cap = bytes;
+        }
+        HIPCHK(c0, hipMemcpy(g->d_sched, g->host_sched.data(), bytes, hipMemcpyHostToDevice));
+        g->key = key;
+        g->sched_cols = cols;
+        g->n_sched = len;
+        return GWAS_OK;
+    };
+    // one grouped product and every context's cross products and solves
+    auto enqueue = [&](TrmmArgs* h, TrmmArgs* d, const int* sched, int64_t n_sched,
+                       const std::vector<const void*>& xp, const std::vector<int64_t>& xl,
+                       const std::vector<double*>& bo, const std::vector<int64_t>& lb,
+                       const std::vector<double*>& vo, const std::vector<int*>& io, int64_t cols,
+                       bool async_args, bool args_ready) -> int {
+        if (!args_ready) {
+            for (int i = 0; i < nctx; ++i) {
+                h[i] = trmm_args_for(cs[i], xp[i], xl[i], cols);
+                h[i].sched = sched;
+                HIPCHK(c0, trmm_check(h[i], false));
+            }
+            if (async_args)
+                HIPCHK(c0, hipMemcpyAsync(d, h, nctx * sizeof(TrmmArgs), hipMemcpyHostToDevice, s));
+            else
+                HIPCHK(c0, hipMemcpy(d, h, nctx * sizeof(TrmmArgs), hipMemcpyHostToDevice));
+        }
+        TrmmArgs la = h[0];
+        la.group = d;
+        la.sched = sched;
+        la.n_sched = n_sched;
+        HIPCHK(c0, trmm_stream(la, s));
+        for (int i = 0; i < nctx; ++i)
+            HIPCHK(c0, finish_sub(cs[i], xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], s));
+        return GWAS_OK;
+    };
+
+    for (int64_t k = 0; k < nsub; ++k) {
+        const int64_t col0 = k * blk;
+        const int64_t cols = std::min<int64_t>(blk, mblk - col0);
+        const int slot = (int)(k & 1);
+        const bool use_graph = want_graph && cols == blk;
+        int rc = ensure_schedule(cols);
+        if (rc) return rc;
+        std::vector<const void*> xp(nctx);
+        std::vector<int64_t> xl(nctx), lb(nctx);
+        std::vector<double*> bo(nctx), vo(nctx);
+        std::vector<int*> io(nctx);
+        const int bslot = use_graph ? 0 : slot;
+        for (int i = 0; i < nctx; ++i) {
+            gwas_ctx* c = cs[i];
+            const char* src = static_cast<const char*>(XR[i]) + (size_t)col0 * ldx[i] * elem;
+            if (direct_x[i] && !use_graph) {
+                xp[i] = src;
+                xl[i] = ldx[i];
+            } else {
+                HIPCHK(c0, hipMemcpy2DAsync(c->xbuf[bslot], c->lay.n_pad * elem, src, ldx[i] * elem,
+                                            c->lay.n * elem, cols, hipMemcpyDefault, s));
+                xp[i] = c->xbuf[bslot];
+                xl[i] = c->lay.n_pad;
+            }
+            if (direct_out[i] && !use_graph) {
+                bo[i] = b[i] + (size_t)col0 * ldb[i];
+                lb[i] = ldb[i];
+                vo[i] = (var_snp && var_snp[i]) ? var_snp[i] + col0 : nullptr;
+                io[i] = (info && info[i]) ? info[i] + col0 : nullptr;
+            } else {
+                bo[i] = c->bbuf[bslot];
+                lb[i] = (int64_t)c->lay.p * c->lay.t;
+                vo[i] = c->vbuf[bslot];
+                io[i] = c->ibuf[bslot];
+            }
+        }
+        if (c0->timing) HIPCHK(c0, hipEventRecord(c0->tev[2 * k], s));
+        if (use_graph) {
+            if (!g->exec || g->graph_key != key) {
+                HIPCHK(c0, hipStreamSynchronize(s));
+                if (g->exec) HIPCHK(c0, hipGraphExecDestroy(g->exec));
+                if (g->graph) HIPCHK(c0, hipGraphDestroy(g->graph));
+                g->exec = nullptr;
+                g->graph = nullptr;
+                if (g->d_sched_graph) HIPCHK(c0, hipFree(g->d_sched_graph));
+                g->d_sched_graph = nullptr;
+                if (!g->h_args_graph)
+                    HIPCHK(c0, hipHostMalloc((void**)&g->h_args_graph, MAX_GROUP * sizeof(TrmmArgs), 0));
+                if (!g->d_args_graph) HIPCHK(c0, hipMalloc((void**)&g->d_args_graph, MAX_GROUP * sizeof(TrmmArgs)));
+                // the graph's own copy of the full-width schedule and of the
+                // arguments (fixed buffers), so later eager launches of other
+                // widths cannot change what a replay reads
+                const size_t sbytes = g->host_sched.size() * sizeof(int);
+                HIPCHK(c0, hipMalloc((void**)&g->d_sched_graph, sbytes));
+                HIPCHK(c0, hipMemcpy(g->d_sched_graph, g->host_sched.data(), sbytes, hipMemcpyHostToDevice));
+                // arguments are uploaded synchronously before capture begins
+                for (int i = 0; i < nctx; ++i) {
+                    g->h_args_graph[i] = trmm_args_for(cs[i], xp[i], xl[i], cols);
+                    g->h_args_graph[i].sched = g->d_sched_graph;
+                    HIPCHK(c0, trmm_check(g->h_args_graph[i], false));
+                }
+                HIPCHK(c0, hipMemcpy(g->d_args_graph, g->h_args_graph, nctx * sizeof(TrmmArgs),
+                                     hipMemcpyHostToDevice));
+                HIPCHK(c0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                const int erc = enqueue(g->h_args_graph, g->d_args_graph, g->d_sched_graph, g->n_sched, xp, xl,
+                                        bo, lb, vo, io, cols, false, true);
+                hipGraph_t graph = nullptr;
+                const hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (erc) return erc;
+                HIPCHK(c0, ec);
+                g->graph = graph;
+                HIPCHK(c0, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+                g->graph_key = key;
+            }
+            HIPCHK(c0, hipGraphLaunch(g->exec, s));
+        } else {
+            if (k >= 2) HIPCHK(c0, hipEventSynchronize(c0->ev_done[slot]));   // slot's arguments free
+            const int erc = enqueue(g->h_args[slot], g->d_args[slot], g->d_sched, g->n_sched, xp, xl, bo, lb,
+                                    vo, io, cols, true, false);
+            if (erc) return erc;
+        }
+        if (c0->timing) HIPCHK(c0, hipEventRecord(c0->tev[2 * k + 1], s));
+        for (int i = 0; i < nctx; ++i) {
+            if (direct_out[i] && !use_graph) continue;
+            const int64_t pt = (int64_t)cs[i]->lay.p * cs[i]->lay.t;
+            HIPCHK(c0, hipMemcpy2DAsync(b[i] + (size_t)col0 * ldb[i], ldb[i] * 8, bo[i], pt * 8, pt * 8, cols,
+                                        hipMemcpyDefault, s));
+            if (var_snp && var_snp[i])
+                HIPCHK(c0, hipMemcpyAsync(var_snp[i] + col0, vo[i], cols * 8, hipMemcpyDefault, s));
+            if (info && info[i])
+                HIPCHK(c0, hipMemcpyAsync(info[i] + col0, io[i], cols * 4, hipMemcpyDefault, s));
+        }
+        HIPCHK(c0, hipEventRecord(c0->ev_done[slot], s));
+    }
+    HIPCHK(c0, hipStreamSynchronize(s));
+    if (c0->timing) {
+        for (int64_t k = 0; k < nsub; ++k) {
+            float ms = 0.f;
+            HIPCHK(c0, hipEventElapsedTime(&ms, c0->tev[2 * k], c0->tev[2 * k + 1]));
+            c0->t_ms += ms;
+            c0->t_launches += 1;
+            c0->t_cols += std::min<int64_t>(blk, mblk - k * blk) * nctx;
+        }
+    }
+    return GWAS_OK;
+}
+
+int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg) {
+    if (!live(c)) return GWAS_E_STATE;
+    const Layout& Y = c->lay;
+    if (!XR || ldx < Y.n || cols < 1) return GWAS_E_INVALID;
+    cols = std::min<int64_t>(cols, Y.dev_block);
+    if (c->at == A_I8S) {   // one tile shape
+        if (best_cfg) *best_cfg = -1;
+        return GWAS_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, join_user(c, c->s_comp));
+    HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    const char* cache = getenv("GWAS_TUNE_CACHE");
+    char keyline[160];
+    snprintf(keyline, sizeof(keyline), "gfx950 n_pad=%lld precision=%d x_dtype=%d cols=%lld",
+             (long long)Y.n_pad, Y.precision, Y.x_dtype, (long long)cols);
+    int best = -1;
+    if (cache) {
+        if (FILE* f = fopen(cache, "r")) {
+            char line[256];
+            while (fgets(line, sizeof(line), f)) {
+                const size_t kl = strlen(keyline);
+                int v = -1;
+                if (strncmp(line, keyline, kl) == 0 && sscanf(line + kl, " cfg=%d", &v) == 1 &&
+                    trmm_cfg_valid(c->at, xt, v))
+                    best = v;
+            }
+            fclose(f);
+        }
+    }
+    if (best < 0) {
+        const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
+        const void* xptr = XR;
+        int64_t xld = ldx;
+        if (!(on_device(XR) && reinterpret_cast<uintptr_t>(XR) % 16 == 0 && (ldx * (int64_t)elem) % 16 == 0)) {
+            HIPCHK(c, hipMemcpy2D(c->xbuf[0], Y.n_pad * elem, XR, ldx * elem, Y.n * elem, cols, hipMemcpyDefault));
+            xptr = c->xbuf[0];
+            xld = Y.n_pad;
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        float best_ms = 0.f;
+        for (int cfg = 0; cfg < trmm_num_cfgs(); ++cfg) {
+            if (!trmm_cfg_valid(c->at, xt, cfg)) continue;
+            c->cfg = cfg;
+            c->shape = trmm_shape(cfg);
+            int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
+            if (rc) return rc;
+            TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
+            ta.sched = c->sched_tail;
+            HIPCHK(c, trmm_stream(ta, c->s_comp));                  // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->s_comp));
+            HIPCHK(c, trmm_stream(ta, c->s_comp));
+            HIPCHK(c, hipEventRecord(e1, c->s_comp));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (best < 0 || ms < best_ms) {
+                best = cfg;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache) {
+            if (FILE* f = fopen(cache, "a")) {
+                fprintf(f, "%s cfg=%d ms=%.3f\n", keyline, best, best_ms);
+                fclose(f);
+            }
+        }
+    }
+    c->cfg = best;
+    c->shape = trmm_shape(best);
+    c->tail_cols = -1;
+    int rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    if (best_cfg) *best_cfg = best;
     return GWAS_OK;
 }
 

@@ -83,8 +83,14 @@ enum XType : int { X_F64 = 0, X_I8 = 1 };
 //   C     n_pad x Qc whitened [Xbar_L | Ybar] (zero padding rows).
 //   sched two int32 per workgroup: (row tile, column tile), -1 = idle.
 //   cfg   tile shape (trmm_shape).
+// Schedule entries: (row tile | context << SCHED_CTX_SHIFT, column tile).
+constexpr int SCHED_CTX_SHIFT = 20;
+constexpr int SCHED_ROW_MASK = (1 << SCHED_CTX_SHIFT) - 1;
+constexpr int MAX_GROUP = 64;
+
 struct TrmmArgs {
     int at, xt, cfg;
+    const TrmmArgs* group;      // grouped launch: device array of per-context arguments
     int slices;                 // A_I8S: int8 slices per row of L^-1
     const double* rscale;       // A_I8S: power-of-two scale of each row of L^-1
     const void* Ut; int64_t ldu; int64_t n_pad;
@@ -95,6 +101,7 @@ struct TrmmArgs {
     const int* sched; int64_t n_sched;
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
+hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
 
 struct TrmmShape { int tm, tn, part_rows, threads; };
 int trmm_num_cfgs();

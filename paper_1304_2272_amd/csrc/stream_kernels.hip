@@ -96,8 +96,8 @@ template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_> struct Shape {
 // per row go global -> registers -> LDS (double buffered); within a stage
 // lane group g = lane/16 supplies the contiguous K slice [g*BK/4, (g+1)*BK/4)
 // to A and B alike.  Tile coordinates come from the schedule.
-template <typename AT, typename XT, typename S>
-__global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs a) {
+template <typename AT, typename XT, typename S, bool GROUPED>
+__global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la) {
     typedef MM<AT> T;
     constexpr int BK = T::BK;
     constexpr bool LOWP = sizeof(AT) < 8;
@@ -111,9 +111,13 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs a)
     constexpr int CB = (B_CHUNKS + NT - 1) / NT;
     static_assert(XB % 16 == 0, "a column stage must be whole 16-byte chunks");
 
-    const int I = a.sched[2 * (int64_t)blockIdx.x];
-    const int J = a.sched[2 * (int64_t)blockIdx.x + 1];
-    if (I < 0) return;
+    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
+    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
+    if (e0 < 0) return;
+    const int I = e0 & SCHED_ROW_MASK;
+    // grouped launches carry one argument set per context; the schedule
+    // entry names the context in its high bits
+    const TrmmArgs& a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
 
     __shared__ __attribute__((aligned(16))) char As[2][TM * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
@@ -294,8 +298,8 @@ constexpr int I8_ROW_G = 4, I8_ROW_V = 1;
 // float64 combination in the epilogue is the only rounding of the product.
 // Each wave owns 16 real rows with all S slices (block i = slice i) and
 // WTN * 16 SNP columns; the workgroup is WGM x WGN waves.
-template <int S, int WGM, int WGN, int WTN>
-__global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs a) {
+template <int S, int WGM, int WGN, int WTN, bool GROUPED>
+__global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la) {
     constexpr int BK = ROW_BYTES;                 // int8 K per stage row
     constexpr int TMR = WGM * 16;                 // real rows per tile
     constexpr int TMS = TMR * S;                  // sliced rows per tile
@@ -306,9 +310,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs a)
     constexpr int B_CHUNKS = TN * (ROW_BYTES / 16);
     constexpr int CB = (B_CHUNKS + NT - 1) / NT;
 
-    const int I = a.sched[2 * (int64_t)blockIdx.x];
-    const int J = a.sched[2 * (int64_t)blockIdx.x + 1];
-    if (I < 0) return;
+    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
+    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
+    if (e0 < 0) return;
+    const int I = e0 & SCHED_ROW_MASK;
+    // grouped launches carry one argument set per context; the schedule
+    // entry names the context in its high bits
+    const TrmmArgs& a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
 
     __shared__ __attribute__((aligned(16))) char As[2][TMS * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
@@ -625,19 +633,31 @@ template <typename S> TrmmShape shape_of() { return TrmmShape{S::TM, S::TN, S::W
 
 template <typename AT, typename XT, typename S>
 hipError_t launch_trmm(const TrmmArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((trmm_stream_kernel<AT, XT, S>), dim3((unsigned)a.n_sched), dim3(S::NT), 0, s, a);
+    if (a.group)
+        hipLaunchKernelGGL((trmm_stream_kernel<AT, XT, S, true>), dim3((unsigned)a.n_sched), dim3(S::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((trmm_stream_kernel<AT, XT, S, false>), dim3((unsigned)a.n_sched), dim3(S::NT), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename AT, typename XT>
 hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
+    // only the shapes trmm_cfg_valid admits are instantiated
+    constexpr bool F64 = sizeof(AT) == 8;
+    constexpr bool I8 = sizeof(XT) == 1;
     switch (a.cfg) {
-        case 0: return launch_trmm<AT, XT, Cfg0>(a, s);
         case 1: return launch_trmm<AT, XT, Cfg1>(a, s);
         case 2: return launch_trmm<AT, XT, Cfg2>(a, s);
-        case 3: return launch_trmm<AT, XT, Cfg3>(a, s);
-        case 4: return launch_trmm<AT, XT, Cfg4>(a, s);
         case 5: return launch_trmm<AT, XT, Cfg5>(a, s);
+        case 3:
+            if constexpr (F64 || I8) return launch_trmm<AT, XT, Cfg3>(a, s);
+            else return hipErrorInvalidValue;
+        case 0:
+            if constexpr (F64) return launch_trmm<AT, XT, Cfg0>(a, s);
+            else return hipErrorInvalidValue;
+        case 4:
+            if constexpr (F64) return launch_trmm<AT, XT, Cfg4>(a, s);
+            else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -731,40 +751,56 @@ int64_t trmm_schedule(int64_t n_pad, int64_t cols, int tm, int tn, int* out, int
 
 TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512}; }
 
-hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
+hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.cols <= 0) return hipSuccess;
+    if (!a.Ut || !a.X || !a.part || !a.sched) return hipErrorInvalidValue;
+    if (a.n_pad % NPAD_ALIGN || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1) return hipErrorInvalidValue;
+    if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
+    if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
+    const size_t xs = a.xt == X_I8 ? 1 : 8;
+    if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
+    TrmmShape sh;
     if (a.at == A_I8S) {
-        const TrmmShape sh = trmm_sliced_shape();
-        if (!a.Ut || !a.X || !a.part || !a.sched || !a.rscale || a.xt != X_I8) return hipErrorInvalidValue;
-        if (a.n_pad % NPAD_ALIGN || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1) return hipErrorInvalidValue;
-        if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
-        if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
-        if (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh.tm, sh.tn) || a.n_sched > 0x7fffffff)
+        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6)
             return hipErrorInvalidValue;
-        if ((reinterpret_cast<uintptr_t>(a.X) % 16) || (a.ldx % 16) || (a.ldu % 16))
-            return hipErrorInvalidValue;
+        sh = trmm_sliced_shape();
+    } else {
+        if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;
+        sh = trmm_shape(a.cfg);
+    }
+    if (a.n_pad % sh.tm) return hipErrorInvalidValue;
+    if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh.tm, sh.tn)))
+        return hipErrorInvalidValue;
+    if (a.n_sched > 0x7fffffff) return hipErrorInvalidValue;
+    return hipSuccess;
+}
+
+// Single launches check their own arguments; grouped launches (a.group set)
+// have had every context's arguments checked by the caller with trmm_check.
+hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
+    if (a.cols <= 0 && !a.group) return hipSuccess;
+    if (!a.group) {
+        hipError_t e = trmm_check(a, true);
+        if (e != hipSuccess) return e;
+    } else if (!a.sched || a.n_sched <= 0 || a.n_sched > 0x7fffffff) {
+        return hipErrorInvalidValue;
+    }
+    if (a.at == A_I8S) {
         switch (a.slices) {
 #define GWAS_SLICED_CASE(S)                                                                       \
     case S:                                                                                       \
-        hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4>), dim3((unsigned)a.n_sched), dim3(512), \
-                           0, s, a);                                                              \
+        if (a.group)                                                                              \
+            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, true>), dim3((unsigned)a.n_sched),  \
+                               dim3(512), 0, s, a);                                               \
+        else                                                                                      \
+            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, false>), dim3((unsigned)a.n_sched), \
+                               dim3(512), 0, s, a);                                               \
         return hipGetLastError();
             GWAS_SLICED_CASE(4) GWAS_SLICED_CASE(5) GWAS_SLICED_CASE(6)
 #undef GWAS_SLICED_CASE
             default: return hipErrorInvalidValue;
         }
     }
-    if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;
-    const TrmmShape sh = trmm_shape(a.cfg);
-    if (!a.Ut || !a.X || !a.part || !a.sched) return hipErrorInvalidValue;
-    if (a.n_pad % sh.tm || a.n_pad % NPAD_ALIGN || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1)
-        return hipErrorInvalidValue;
-    if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
-    if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
-    if (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh.tm, sh.tn) || a.n_sched > 0x7fffffff)
-        return hipErrorInvalidValue;
-    const size_t xs = a.xt == X_I8 ? 1 : 8;
-    if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
     if (a.xt == X_F64) {
         if (a.at == A_F64) return launch_cfg<double, double>(a, s);
         if (a.at == A_F32) return launch_cfg<float, double>(a, s);

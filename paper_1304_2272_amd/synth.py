@@ -85,6 +85,16 @@ def covariance(Z: np.ndarray, h2: float = 0.5, sigma2: float = 1.0, device=None)
     return M
 
 
+def cohorts(count: int, seed: int, n_lo: int = 2000, n_hi: int = 30000, h2_lo: float = 0.2,
+            h2_hi: float = 0.8):
+    """Sizes and heritabilities of ``count`` cohorts: n_c ~ U{n_lo..n_hi},
+    h2_c ~ U(h2_lo, h2_hi); cohort c draws its inputs from seed (seed, c)."""
+    rng = _child(seed, 8)
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    h2 = rng.uniform(h2_lo, h2_hi, size=count)
+    return [dict(n=int(ns[c]), h2=float(h2[c]), seed=int(seed * 1000 + c)) for c in range(count)]
+
+
 def make_problem(n: int, p: int, seed: int, t: int = 1, h2: float = 0.5,
                  sigma2: float = 1.0, k: int = K_BACKGROUND, device=None,
                  noise: bool = True):
@@ -112,28 +122,34 @@ def make_problem(n: int, p: int, seed: int, t: int = 1, h2: float = 0.5,
             "h2": h2, "sigma2": sigma2, "k": k, "seed": seed}
 
 
-def snp_chunk(n: int, seed: int, chunk: int, dtype=np.float64) -> np.ndarray:
-    """Dosage chunk ``chunk`` (CHUNK SNPs), SNP-major (CHUNK, n)."""
+def snp_chunk(n: int, seed: int, chunk: int, dtype=np.float64, cohort=None) -> np.ndarray:
+    """Dosage chunk ``chunk`` (CHUNK SNPs), SNP-major (CHUNK, n).
+
+    With ``cohort`` set, the allele frequencies of the chunk's positions are
+    the shared ones and the dosages are that cohort's own draw.
+    """
     rng = _child(seed, _S_XR, chunk)
     f = rng.uniform(0.05, 0.5, size=CHUNK)
+    if cohort is not None:
+        rng = _child(seed, _S_XR, chunk, 2 + cohort)
     u = rng.random((CHUNK, n))
     return _dosages_from_uniform(u, f[:, None]).astype(dtype, copy=False)
 
 
-def snp_block(n: int, seed: int, start: int, cols: int, dtype=np.float64) -> np.ndarray:
+def snp_block(n: int, seed: int, start: int, cols: int, dtype=np.float64, cohort=None) -> np.ndarray:
     """SNPs [start, start+cols) as a SNP-major (cols, n) array of ``dtype``."""
     out = np.empty((cols, n), dtype=dtype)
     c0 = start // CHUNK
     c1 = (start + cols + CHUNK - 1) // CHUNK
     for c in range(c0, c1):
-        blk = snp_chunk(n, seed, c, dtype)
+        blk = snp_chunk(n, seed, c, dtype, cohort)
         lo = max(start, c * CHUNK)
         hi = min(start + cols, (c + 1) * CHUNK)
         out[lo - start:hi - start] = blk[lo - c * CHUNK:hi - c * CHUNK]
     return out
 
 
-def snp_block_device(n: int, seed: int, start: int, cols: int, device, dtype=None):
+def snp_block_device(n: int, seed: int, start: int, cols: int, device, dtype=None, cohort=None):
     """Device-side dosages for large runs, SNP-major (cols, n) torch tensor.
 
     Same distribution as :func:`snp_block`, drawn with torch's generator on
@@ -150,6 +166,9 @@ def snp_block_device(n: int, seed: int, start: int, cols: int, device, dtype=Non
         st = np.random.SeedSequence(seed, spawn_key=(_S_XR, c, 1)).generate_state(2, np.uint64)
         g.manual_seed(int(st[0] & np.uint64(0x7FFFFFFFFFFFFFFF)))
         f = torch.rand(CHUNK, 1, generator=g, device=device, dtype=torch.float64) * 0.45 + 0.05
+        if cohort is not None:   # shared positions and frequencies, the cohort's own dosages
+            st = np.random.SeedSequence(seed, spawn_key=(_S_XR, c, 2 + cohort)).generate_state(2, np.uint64)
+            g.manual_seed(int(st[0] & np.uint64(0x7FFFFFFFFFFFFFFF)))
         lo = max(start, c * CHUNK)
         hi = min(start + cols, (c + 1) * CHUNK)
         u = torch.rand(CHUNK, n, generator=g, device=device, dtype=torch.float32)[lo - c * CHUNK:hi - c * CHUNK]

@@ -200,3 +200,89 @@ def test_int8_slices_needs_int8_dosages():
     with pytest.raises(binding.GwasError) as ei:
         binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision="int8", x_dtype="f64")
     assert ei.value.code == 1
+
+
+def _cohort_contexts(precision, dev_block, t=3, p=4, ns=(700, 1300, 2100)):
+    probs = [synth.make_problem(n, p, 50 + i, t=t, k=400) for i, n in enumerate(ns)]
+    xd = "i8"
+    ctxs = [binding.GwasContext(pr["M"], pr["XL"], pr["Y"], precision=precision, x_dtype=xd,
+                                dev_block=dev_block) for pr in probs]
+    return probs, ctxs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "int8"])
+def test_group_matches_single_contexts(precision):
+    m = 1500
+    _say(f"group of 3 cohorts ({precision}), m={m}, ragged sub-blocks")
+    probs, ctxs = _cohort_contexts(precision, dev_block=512)
+    XRs = [synth.snp_block(pr["n"], 9, 0, m, dtype=np.int8, cohort=i) for i, pr in enumerate(probs)]
+    try:
+        grouped = binding.stream_group(ctxs, XRs)
+        for c, X, (b, v, info) in zip(ctxs, XRs, grouped):
+            b1, v1, i1 = c.stream_block(X)
+            assert np.array_equal(b, b1) and np.array_equal(v, v1) and np.array_equal(info, i1)
+        if precision == "fp64":
+            for pr, X, (b, _, _) in zip(probs, XRs, grouped):
+                bo, _, _ = GLSOracle(pr["M"], pr["XL"], pr["Y"]).solve(X)
+                assert normwise(b, bo) < TOL_FP64
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_group_graph_replays_match_eager():
+    import torch
+    dev = torch.device("cuda:0")
+    blk, m = 256, 1024
+    _say(f"group graph: 3 cohorts, {m // blk} full sub-blocks per call, two calls")
+    probs, ctxs = _cohort_contexts("fp64", dev_block=blk)
+    try:
+        for call in range(2):
+            XRs = [synth.snp_block_device(pr["n"], 10 + call, 0, m, dev, cohort=i)
+                   for i, pr in enumerate(probs)]
+            eager = binding.stream_group(ctxs, XRs)
+            torch.cuda.synchronize()
+            replay = binding.stream_group(ctxs, XRs, graph=True)
+            torch.cuda.synchronize()
+            for (be, ve, ie), (bg, vg, ig) in zip(eager, replay):
+                assert torch.equal(be, bg) and torch.equal(ve, vg) and torch.equal(ie, ig)
+            # eager work of the program between replays
+            _ = [c.stream_block(X[:100]) for c, X in zip(ctxs, XRs)]
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    n, p, m, seed = 1500, 4, 2048, 61
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GWAS_TUNE_CACHE", str(cache))
+    for precision, tol in [("fp64", TOL_FP64), ("fp32", TOL_FP32)]:
+        with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
+                                 dev_block=1024) as ctx:
+            best = ctx.autotune(XR, 1024)
+            _say(f"autotune {precision}: tile shape {best}")
+            assert best in TILE_SHAPES[precision]
+            b, _, _ = ctx.stream_block(XR)
+            assert normwise(b, bo) < tol
+        with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
+                                 dev_block=1024) as ctx:
+            assert ctx.autotune(XR, 1024) == best          # read back from the cache
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and all("cfg=" in ln for ln in lines)
+
+
+def test_many_traits():
+    n, p, t, m, seed = 1500, 4, 64, 600, 71
+    _say(f"traits n={n} p={p} t={t} m={m}")
+    prob = synth.make_problem(n, p, seed, t=t)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    for precision, tol in [("fp64", TOL_FP64), ("int8", TOL_FP64), ("fp32", TOL_FP32)]:
+        b, var, info = run(prob, XR, precision=precision, x_dtype="i8")
+        err = normwise(b, bo)
+        _say(f"  {precision}: err {err:.3e}")
+        assert b.shape == (m, t, p) and err < tol
