@@ -194,6 +194,41 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  */
 int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg);
 
+/*
+ * Reverse mode (one trait, t = 1): the gradient of a scalar loss l(b, var)
+ * over the GLS solutions of Eq. (1), given its cotangents gb_i = dl/db_i and
+ * gv_i = dl/dvar_i.  With a_i = S_i^-1 gb_i, tau_i = S_i^-1 e_p,
+ * Q_i = X_i^T M^-2 X_i and q_i = X_i^T M^-2 y (dM^-1 = -M^-1 dM M^-1):
+ *   dl/dy        = M^-1 sum_i X_i a_i
+ *   dl/dM        = Mbar = -sum_i sym(M^-1 X_i a_i (M^-1 (y - X_i b_i))^T)
+ *                         + sum_i gv_i (M^-1 X_i tau_i)(M^-1 X_i tau_i)^T
+ * and for a covariance model dM/dtheta = alpha M + beta I (for
+ * M = sigma^2 (h^2 Phi + (1 - h^2) I): d/dh^2 has alpha = 1/h^2 and
+ * beta = -sigma^2/h^2) the two contractions
+ *   <Mbar, M> = sum_i gv_i var_i,
+ *   tr Mbar   = sum_i [-a_i^T (q_i - Q_i b_i) + gv_i tau_i^T Q_i tau_i],
+ * so that dl/dtheta = alpha <Mbar, M> + beta tr Mbar.  The per-SNP O(n^2)
+ * work is one product w_i = M^-1 x_i (M^-1 = L^-T L^-1 formed once, float64).
+ *
+ *   gwas_backward_begin  forms M^-1 and W (first call allocates device
+ *                        memory for them) and zeroes the accumulators.
+ *   gwas_backward_block  one block: XR, ldx, mblk as given to
+ *                        gwas_stream_block; b, ldb, var_snp, info its outputs;
+ *                        gb (p per SNP, ldgb >= p) and gvar (NULL = 0) the
+ *                        cotangents; host or device memory.  SNPs with
+ *                        info != 0 contribute nothing.
+ *   gwas_backward_end    gy (n doubles, host or device, may be NULL) = dl/dy,
+ *                        *tr_mbar = tr Mbar, *ip_mbar_m = <Mbar, M>.
+ * Errors: GWAS_E_INVALID (t != 1, bad sizes), GWAS_E_STATE (no begin),
+ * GWAS_E_OOM, GWAS_E_HIP.
+ */
+int gwas_backward_begin(gwas_ctx* ctx);
+int gwas_backward_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
+                        const double* b, int64_t ldb, const double* var_snp,
+                        const int32_t* info, const double* gb, int64_t ldgb,
+                        const double* gvar);
+int gwas_backward_end(gwas_ctx* ctx, double* gy, double* tr_mbar, double* ip_mbar_m);
+
 /* Release a context (NULL is accepted).  Later use returns GWAS_E_STATE. */
 int gwas_free(gwas_ctx* ctx);
 

@@ -31,7 +31,8 @@ X_DTYPES = {"f64": 0, "i8": 1}
 
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
-             "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune")
+             "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
+             "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end")
 GROUP_GRAPH = 1
 
 
@@ -102,6 +103,12 @@ def load():
                                     ctypes.POINTER(vp), i32]
     L.gwas_autotune.restype = ctypes.c_int
     L.gwas_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32)]
+    L.gwas_backward_begin.restype = ctypes.c_int
+    L.gwas_backward_begin.argtypes = [vp]
+    L.gwas_backward_block.restype = ctypes.c_int
+    L.gwas_backward_block.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp, vp, i64, vp]
+    L.gwas_backward_end.restype = ctypes.c_int
+    L.gwas_backward_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
 
@@ -239,6 +246,41 @@ class GwasContext:
         self._check(self._lib.gwas_autotune(self._h, xp, ldx, cols, ctypes.byref(best)))
         del keep
         return best.value
+
+    def backward_begin(self):
+        """Start a reverse pass (forms M^-1 and W on the first call)."""
+        self._check(self._lib.gwas_backward_begin(self._h))
+
+    def backward_block(self, XR, b, var, info, gb, gvar=None):
+        """Add one block's contribution: XR as given to stream_block, (b, var,
+        info) its outputs, gb = dl/db (m, p) and gvar = dl/dvar (m,)."""
+        xdt = np.int8 if self.x_dtype == "i8" else np.float64
+        xp, ldx, keep, _ = _ptr_ld(XR, xdt, "XR")
+        m = XR.shape[0] if XR.ndim == 2 else 1
+        arrs = [b, var, info, gb] + ([gvar] if gvar is not None else [])
+        conv = []
+        for a in arrs:
+            if _is_torch(a):
+                conv.append(a.contiguous())
+            else:
+                conv.append(np.ascontiguousarray(a))
+        ptr = lambda a: a.data_ptr() if _is_torch(a) else a.ctypes.data
+        bb, vv, ii, gg = conv[:4]
+        gv = conv[4] if gvar is not None else None
+        rc = self._lib.gwas_backward_block(self._h, xp, ldx, m, ptr(bb), self.p, ptr(vv), ptr(ii), ptr(gg),
+                                           self.p, ptr(gv) if gv is not None else None)
+        del keep, conv
+        self._check(rc)
+
+    def backward_end(self, gy=None):
+        """(dl/dy, tr Mbar, <Mbar, M>); dl/dy goes into ``gy`` if given."""
+        if gy is None:
+            gy = np.empty(self.n)
+        tr = ctypes.c_double()
+        ip = ctypes.c_double()
+        ptr = gy.data_ptr() if _is_torch(gy) else gy.ctypes.data
+        self._check(self._lib.gwas_backward_end(self._h, ptr, ctypes.byref(tr), ctypes.byref(ip)))
+        return gy, tr.value, ip.value
 
     def set_timing(self, on=True):
         self._check(self._lib.gwas_set_timing(self._h, 1 if on else 0))

@@ -164,6 +164,19 @@ struct gwas_ctx {
     int64_t info = 0;
     std::string err;
     struct Group* grp = nullptr;    // grouped-launch state, owned by the first context of a group
+    struct Back* back = nullptr;    // reverse-pass state (gwas_backward_*)
+};
+
+// Reverse-pass state: M^-1 = U U^T, W = M^-1 [X_L | y], the constants
+// W_L^T W_L and W_L^T w_y, per-sub-block scratch and the accumulators.
+struct Back {
+    char* mem = nullptr;
+    double *Minv = nullptr, *W = nullptr, *GW = nullptr, *part = nullptr, *xw = nullptr,
+           *contrib = nullptr, *coef = nullptr, *g = nullptr, *acc = nullptr, *v = nullptr,
+           *gy = nullptr, *sb = nullptr, *sv = nullptr, *sgb = nullptr, *sgv = nullptr;
+    int* si = nullptr;
+    int64_t npb = 0;
+    bool ready = false;
 };
 
 // State of grouped launches (gwas_stream_group), kept by the group's first
@@ -296,6 +309,11 @@ void release(gwas_ctx* c) {
         if (c->ev_out[s]) (void)hipEventDestroy(c->ev_out[s]);
     }
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    if (c->back) {
+        if (c->back->mem) (void)hipFree(c->back->mem);
+        delete c->back;
+        c->back = nullptr;
+    }
     if (c->grp) {
         Group* g = c->grp;
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -981,6 +999,192 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     if (best_cfg) *best_cfg = best;
+    return GWAS_OK;
+}
+
+int gwas_backward_begin(gwas_ctx* c) {
+    if (!live(c)) return GWAS_E_STATE;
+    const Layout& Y = c->lay;
+    if (Y.t != 1) return GWAS_E_INVALID;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->s_comp;
+    if (!c->back) {
+        c->back = new (std::nothrow) Back();
+        if (!c->back) return GWAS_E_OOM;
+    }
+    Back* B = c->back;
+    const int p = Y.p;
+    const int64_t np = Y.n_pad, blk = Y.dev_block;
+    const TrmmShape sh = trmm_shape(trmm_default_cfg(A_F64, (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64));
+    if (!B->mem) {
+        B->npb = np / sh.part_rows;
+        size_t o = 0;
+        std::vector<std::pair<double**, size_t>> parts = {
+            {&B->Minv, (size_t)np * np}, {&B->W, (size_t)np * p}, {&B->GW, (size_t)(p - 1) * p},
+            {&B->part, (size_t)B->npb * (p + 1) * blk}, {&B->xw, (size_t)p * blk},
+            {&B->contrib, (size_t)(p + 1) * blk}, {&B->coef, (size_t)blk}, {&B->g, (size_t)np},
+            {&B->acc, (size_t)(p + 1)}, {&B->v, (size_t)np}, {&B->gy, (size_t)np},
+            {&B->sb, (size_t)p * blk}, {&B->sv, (size_t)blk}, {&B->sgb, (size_t)p * blk},
+            {&B->sgv, (size_t)blk}};
+        std::vector<size_t> offs;
+        for (auto& pr : parts) {
+            offs.push_back(o);
+            o = align_up(o + pr.second * 8, 256);
+        }
+        const size_t off_si = o;
+        o = align_up(o + (size_t)blk * 4, 256);
+        if (hipMalloc(&B->mem, o) != hipSuccess) {
+            (void)hipGetLastError();
+            B->mem = nullptr;
+            c->err = "reverse-pass workspace allocation failed";
+            return GWAS_E_OOM;
+        }
+        for (size_t i = 0; i < parts.size(); ++i) *parts[i].first = (double*)(B->mem + offs[i]);
+        B->si = (int*)(B->mem + off_si);
+        B->ready = false;
+    }
+    HIPCHK(c, join_user(c, s));
+    if (!B->ready) {
+        // M^-1 = U U^T (U = L^-T upper): K range [max(m0, n0), n_pad)
+        GemmArgs g{np, np, np, c->U, Y.ld, 'N', c->U, Y.ld, 'T', B->Minv, np, 1.0, 0.0,
+                   KR_A_UPPER | KR_B_LOWER, 0};
+        HIPCHK(c, gemm_f64(g, s));
+        // W = U C with C = L^-1 [X_L | y]
+        g = GemmArgs{np, p, np, c->U, Y.ld, 'N', c->C, np, 'N', B->W, np, 1.0, 0.0, KR_A_UPPER, 0};
+        HIPCHK(c, gemm_f64(g, s));
+        // [W_L^T W_L | W_L^T w_y]
+        g = GemmArgs{p - 1, p, np, B->W, np, 'T', B->W, np, 'N', B->GW, p - 1, 1.0, 0.0, 0, 0};
+        HIPCHK(c, gemm_f64(g, s));
+        B->ready = true;
+    }
+    HIPCHK(c, hipMemsetAsync(B->g, 0, (size_t)np * 8, s));
+    HIPCHK(c, hipMemsetAsync(B->acc, 0, (size_t)(p + 1) * 8, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return GWAS_OK;
+}
+
+int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, const double* b,
+                        int64_t ldb, const double* var_snp, const int32_t* info, const double* gb,
+                        int64_t ldgb, const double* gvar) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (!c->back || !c->back->ready) return GWAS_E_STATE;
+    const Layout& Y = c->lay;
+    const int p = Y.p;
+    if (mblk < 0 || (mblk > 0 && (!XR || !b || !var_snp || !info || !gb)) || ldx < Y.n || ldb < p ||
+        ldgb < p)
+        return GWAS_E_INVALID;
+    if (mblk == 0) return GWAS_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    Back* B = c->back;
+    hipStream_t s = c->s_comp;
+    HIPCHK(c, join_user(c, s));
+    const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
+    const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    const int cfg = trmm_default_cfg(A_F64, xt);
+    const TrmmShape sh = trmm_shape(cfg);
+    const bool direct_x = on_device(XR) && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
+                          ((ldx * (int64_t)elem) % 16 == 0);
+    const int64_t blk = Y.dev_block;
+    for (int64_t col0 = 0; col0 < mblk; col0 += blk) {
+        const int64_t cols = std::min<int64_t>(blk, mblk - col0);
+        const char* src = static_cast<const char*>(XR) + (size_t)col0 * ldx * elem;
+        const void* xptr = src;
+        int64_t xld = ldx;
+        if (!direct_x) {
+            HIPCHK(c, hipMemcpy2DAsync(c->xbuf[0], Y.n_pad * elem, src, ldx * elem, Y.n * elem, cols,
+                                       hipMemcpyDefault, s));
+            xptr = c->xbuf[0];
+            xld = Y.n_pad;
+        }
+        // forward results and cotangents of this sub-block into device scratch
+        HIPCHK(c, hipMemcpy2DAsync(B->sb, p * 8, b + (size_t)col0 * ldb, ldb * 8, p * 8, cols, hipMemcpyDefault, s));
+        HIPCHK(c, hipMemcpy2DAsync(B->sgb, p * 8, gb + (size_t)col0 * ldgb, ldgb * 8, p * 8, cols,
+                                   hipMemcpyDefault, s));
+        HIPCHK(c, hipMemcpyAsync(B->sv, var_snp + col0, cols * 8, hipMemcpyDefault, s));
+        HIPCHK(c, hipMemcpyAsync(B->si, info + col0, cols * 4, hipMemcpyDefault, s));
+        if (gvar) HIPCHK(c, hipMemcpyAsync(B->sgv, gvar + col0, cols * 8, hipMemcpyDefault, s));
+        // w = M^-1 x with the sums w^T [W_L | w_y] and w^T w
+        std::vector<int> sched((size_t)(2 * trmm_schedule_len(Y.n_pad, cols, sh.tm, sh.tn)));
+        const int64_t ns = trmm_schedule(Y.n_pad, cols, sh.tm, sh.tn, sched.data(), (int64_t)sched.size() / 2);
+        if (ns < 0 || (size_t)(2 * ns) * sizeof(int) > Y.sched_len * 2 * sizeof(int)) {
+            c->err = "reverse-pass schedule does not fit";
+            return GWAS_E_INVALID;
+        }
+        HIPCHK(c, hipMemcpy(c->sched_tail, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice));
+        c->tail_cols = -1;
+        TrmmArgs ta{};
+        ta.at = A_F64;
+        ta.xt = xt;
+        ta.cfg = cfg;
+        ta.Ut = B->Minv;
+        ta.ldu = Y.n_pad;
+        ta.n_pad = Y.n_pad;
+        ta.X = xptr;
+        ta.ldx = xld;
+        ta.n = Y.n;
+        ta.cols = cols;
+        ta.C = B->W;
+        ta.ldc = Y.n_pad;
+        ta.Qc = p;
+        ta.with_cross = 1;
+        ta.part = B->part;
+        ta.ldp = blk;
+        ta.sched = c->sched_tail;
+        ta.n_sched = ns;
+        ta.full_k = 1;
+        HIPCHK(c, trmm_stream(ta, s));
+        HIPCHK(c, snp_cross_w(xt, xptr, xld, Y.n, cols, B->W, Y.n_pad, p, B->xw, blk, s));
+        BackArgs ba{};
+        ba.p = p;
+        ba.cols = cols;
+        ba.part = B->part;
+        ba.ldp = blk;
+        ba.npb = Y.n_pad / sh.part_rows;
+        ba.xw = B->xw;
+        ba.ldxw = blk;
+        ba.consts = c->consts;
+        ba.G = B->GW;
+        ba.gy0 = B->GW + (size_t)(p - 1) * (p - 1);
+        ba.b = B->sb;
+        ba.ldb = p;
+        ba.var = B->sv;
+        ba.info = B->si;
+        ba.gb = B->sgb;
+        ba.ldgb = p;
+        ba.gv = gvar ? B->sgv : nullptr;
+        ba.contrib = B->contrib;
+        ba.ldc = blk;
+        ba.coef = B->coef;
+        HIPCHK(c, snp_backward(ba, s));
+        HIPCHK(c, sum_columns(B->contrib, blk, p + 1, cols, B->acc, s));
+        HIPCHK(c, dosage_gemv(xt, xptr, xld, Y.n, cols, B->coef, B->g, s));
+        HIPCHK(c, hipStreamSynchronize(s));   // scratch and schedule are reused by the next sub-block
+    }
+    return GWAS_OK;
+}
+
+int gwas_backward_end(gwas_ctx* c, double* gy, double* tr_mbar, double* ip_mbar_m) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (!c->back || !c->back->ready) return GWAS_E_STATE;
+    const Layout& Y = c->lay;
+    Back* B = c->back;
+    hipStream_t s = c->s_comp;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, join_user(c, s));
+    const int p = Y.p;
+    const int64_t np = Y.n_pad;
+    // v = X_L a_L + X_R a_SNP, then dl/dy = M^-1 v
+    HIPCHK(c, hipMemcpyAsync(B->v, B->g, (size_t)np * 8, hipMemcpyDeviceToDevice, s));
+    GemmArgs g{np, 1, p - 1, c->XY, np, 'N', B->acc, p - 1, 'N', B->v, np, 1.0, 1.0, 0, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    g = GemmArgs{np, 1, np, B->Minv, np, 'N', B->v, np, 'N', B->gy, np, 1.0, 0.0, 0, 0};
+    HIPCHK(c, gemm_f64(g, s));
+    double acc2[2] = {0.0, 0.0};
+    HIPCHK(c, hipMemcpyAsync(acc2, B->acc + (p - 1), 16, hipMemcpyDeviceToHost, s));
+    if (gy) HIPCHK(c, hipMemcpyAsync(gy, B->gy, (size_t)Y.n * 8, hipMemcpyDefault, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (tr_mbar) *tr_mbar = acc2[0];
+    if (ip_mbar_m) *ip_mbar_m = acc2[1];
     return GWAS_OK;
 }
 

@@ -99,6 +99,7 @@ struct TrmmArgs {
     int with_cross;
     double* part; int64_t ldp;
     const int* sched; int64_t n_sched;
+    int full_k;                 // A is a full (not lower-triangular) n_pad x n_pad matrix
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
@@ -127,6 +128,36 @@ int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, int tm, int tn);
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw,
                        int64_t ldxw, hipStream_t s);
+
+// Reverse mode through the per-SNP solves (one trait).  For SNP j, with the
+// Cholesky factor of S_j from R = chol(S_TL), S_BL = x^T W_L and s = 1/var,
+// and the cotangents gb (p values) and gv of b_j and var_j:
+//   a = S^-1 gb, tau = S^-1 e_p;  Q = X^T M^-2 X and q = X^T M^-2 y from
+//   G = W_L^T W_L, gy0 = W_L^T w_y (constants) and the partial sums of
+//   w = M^-1 x against [W_L | w_y] and w^T w (part, Q = p+1 rows per slice);
+// writes contrib[k*ldc + j]: k < p-1: a_L; k = p-1: -a^T (q - Q b) + gv tau^T Q tau;
+// k = p: gv var; and coef[j] = a_SNP (SNPs with info != 0 contribute zero).
+struct BackArgs {
+    int p;
+    int64_t cols;
+    const double* part; int64_t ldp; int64_t npb;   // partials of the M^-1 product
+    const double* xw; int64_t ldxw;                 // x^T [W_L | w_y]
+    const double* consts;                           // R (as in snp_constants)
+    const double* G; const double* gy0;             // W_L^T W_L ((p-1)^2), W_L^T w_y (p-1)
+    const double* b; int64_t ldb; const double* var; const int* info;
+    const double* gb; int64_t ldgb; const double* gv;
+    double* contrib; int64_t ldc;
+    double* coef;
+};
+hipError_t snp_backward(const BackArgs& a, hipStream_t s);
+
+// acc[k] += sum_j contrib[k*ldc + j] for k < rows (fixed summation order).
+hipError_t sum_columns(const double* contrib, int64_t ldc, int rows, int64_t cols, double* acc,
+                       hipStream_t s);
+
+// g[r] += sum_j X(r, j) coef[j] for r < n (dosages column-major, fixed order).
+hipError_t dosage_gemv(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
+                       const double* coef, double* g, hipStream_t s);
 
 // Per-SNP reduction of the partials and the p x p Cholesky solve.
 struct SolveArgs {

@@ -129,7 +129,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 
     const int64_t r0 = (int64_t)I * TM;
     const int64_t c0 = (int64_t)J * TN;
-    const int64_t kend = std::min<int64_t>(r0 + TM, a.n_pad);
+    // L^-1 is lower triangular: its rows r0.. end at column r0 + TM; a full
+    // matrix (M^-1 in the reverse pass) runs the whole K range
+    const int64_t kend = a.full_k ? a.n_pad : std::min<int64_t>(r0 + TM, a.n_pad);
     const int64_t nk = kend / BK;
     const char* Ut = reinterpret_cast<const char*>(a.Ut);
     const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
@@ -620,6 +622,140 @@ __global__ __launch_bounds__(128) void snp_solve_kernel(SolveArgs a) {
     }
 }
 
+// Reverse pass through the per-SNP solves, one SNP per thread (one trait).
+// The factor of S = [[S_TL, S_BL^T], [S_BL, S_BR]] is [[R, 0], [u^T, sqrt(s)]]
+// with u = R^-1 S_BL^T and s = 1/var; S^-1 v follows from two solves with it.
+template <int Q1>
+__global__ __launch_bounds__(128) void snp_backward_kernel(BackArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.cols) return;
+    constexpr int P = Q1 + 1;
+    double* out = a.contrib + j;
+    if (a.info[j] != 0) {
+        for (int k = 0; k <= P; ++k) out[k * a.ldc] = 0.0;
+        a.coef[j] = 0.0;
+        return;
+    }
+    const double* R = a.consts + consts_R(Q1);
+    double sbl[Q1], h[Q1];
+    double eta = 0.0, hy = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q1; ++q) {
+        sbl[q] = a.xw[q * a.ldxw + j];
+        h[q] = 0.0;
+    }
+    for (int64_t pb = 0; pb < a.npb; ++pb) {
+        const double* Pp = a.part + pb * (P + 1) * a.ldp + j;
+#pragma unroll
+        for (int q = 0; q < Q1; ++q) h[q] += Pp[q * a.ldp];       // w^T W_L
+        hy += Pp[Q1 * a.ldp];                                       // w^T w_y
+        eta += Pp[P * a.ldp];                                       // w^T w
+    }
+    const double xwy = a.xw[Q1 * a.ldxw + j];                       // x^T w_y
+    const double var = a.var[j];
+    const double s = 1.0 / var;
+    double u[Q1];
+#pragma unroll
+    for (int r = 0; r < Q1; ++r) {
+        double t = sbl[r];
+#pragma unroll
+        for (int k = 0; k < r; ++k) t -= R[r + k * Q1] * u[k];
+        u[r] = t / R[r + r * Q1];
+    }
+    // v = S^-1 g for a p-vector g (last entry g[Q1])
+    auto solve = [&](const double (&g)[P], double (&v)[P]) {
+        double y[Q1];
+#pragma unroll
+        for (int r = 0; r < Q1; ++r) {
+            double t = g[r];
+#pragma unroll
+            for (int k = 0; k < r; ++k) t -= R[r + k * Q1] * y[k];
+            y[r] = t / R[r + r * Q1];
+        }
+        double yb = g[Q1];
+#pragma unroll
+        for (int r = 0; r < Q1; ++r) yb -= u[r] * y[r];
+        const double vb = yb / s;
+#pragma unroll
+        for (int r = Q1 - 1; r >= 0; --r) {
+            double t = y[r] - u[r] * vb;
+#pragma unroll
+            for (int k = r + 1; k < Q1; ++k) t -= R[k + r * Q1] * v[k];
+            v[r] = t / R[r + r * Q1];
+        }
+        v[Q1] = vb;
+    };
+    double g[P], av[P], tau[P], e[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        g[k] = a.gb[j * a.ldgb + k];
+        e[k] = (k == Q1) ? 1.0 : 0.0;
+    }
+    solve(g, av);
+    solve(e, tau);
+    const double gv = a.gv ? a.gv[j] : 0.0;
+    // Q = [[G, h], [h^T, eta]], q = [gy0; hy]
+    double bb[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) bb[k] = a.b[j * a.ldb + k];
+    auto Qmul = [&](const double (&x)[P], double (&y)[P]) {
+#pragma unroll
+        for (int r = 0; r < Q1; ++r) {
+            double t = h[r] * x[Q1];
+#pragma unroll
+            for (int k = 0; k < Q1; ++k) t += a.G[r + k * Q1] * x[k];
+            y[r] = t;
+        }
+        double t = eta * x[Q1];
+#pragma unroll
+        for (int k = 0; k < Q1; ++k) t += h[k] * x[k];
+        y[Q1] = t;
+    };
+    double Qb[P], Qt[P];
+    Qmul(bb, Qb);
+    Qmul(tau, Qt);
+    double tr = 0.0, tqt = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q1; ++k) tr -= av[k] * (a.gy0[k] - Qb[k]);
+    tr -= av[Q1] * (hy - Qb[Q1]);
+#pragma unroll
+    for (int k = 0; k < P; ++k) tqt += tau[k] * Qt[k];
+    tr += gv * tqt;
+#pragma unroll
+    for (int k = 0; k < Q1; ++k) out[k * a.ldc] = av[k];
+    out[Q1 * a.ldc] = tr;
+    out[P * a.ldc] = gv * var;
+    a.coef[j] = av[Q1];
+    (void)xwy;
+}
+
+__global__ __launch_bounds__(256) void sum_columns_kernel(const double* __restrict__ c, int64_t ldc,
+                                                          int64_t cols, double* __restrict__ acc) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    double t = 0.0;
+    for (int64_t j = threadIdx.x; j < cols; j += 256) t += c[k * ldc + j];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[k] += red[0];
+}
+
+// one thread per row r: g[r] += sum_j X(r, j) coef[j], columns in order
+template <typename XT>
+__global__ __launch_bounds__(256) void dosage_gemv_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
+                                                          int64_t cols, const double* __restrict__ coef,
+                                                          double* __restrict__ g) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double t = 0.0;
+    for (int64_t j = 0; j < cols; ++j) t += (double)X[j * ldx + r] * coef[j];
+    g[r] += t;
+}
+
 // Tile shapes of the triangular product.  MINB is the workgroups per CU
 // the register budget is sized for.
 typedef Shape<2, 2, 4, 4, 2> Cfg0;   // 128 x 128, 256 threads, waves of 64 x 64
@@ -826,6 +962,48 @@ hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t co
     else
         hipLaunchKernelGGL(snp_cross_w_kernel<double>, dim3(grid), dim3(256), 0, s,
                            (const double*)X, ldx, n, cols, W, ldw, Qc, xw, ldxw);
+    return hipGetLastError();
+}
+
+hipError_t snp_backward(const BackArgs& a, hipStream_t s) {
+    if (a.cols <= 0) return hipSuccess;
+    if (a.p < 2 || a.p > 20 || !a.part || !a.xw || !a.consts || !a.G || !a.gy0 || !a.b || !a.var ||
+        !a.info || !a.gb || !a.contrib || !a.coef || a.ldc < a.cols || a.ldb < a.p || a.ldgb < a.p)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((a.cols + 127) / 128);
+    switch (a.p - 1) {
+#define GWAS_BACK_CASE(q) \
+    case q: hipLaunchKernelGGL(snp_backward_kernel<q>, dim3(grid), dim3(128), 0, s, a); break;
+        GWAS_BACK_CASE(1) GWAS_BACK_CASE(2) GWAS_BACK_CASE(3) GWAS_BACK_CASE(4)
+        GWAS_BACK_CASE(5) GWAS_BACK_CASE(6) GWAS_BACK_CASE(7) GWAS_BACK_CASE(8)
+        GWAS_BACK_CASE(9) GWAS_BACK_CASE(10) GWAS_BACK_CASE(11) GWAS_BACK_CASE(12)
+        GWAS_BACK_CASE(13) GWAS_BACK_CASE(14) GWAS_BACK_CASE(15) GWAS_BACK_CASE(16)
+        GWAS_BACK_CASE(17) GWAS_BACK_CASE(18) GWAS_BACK_CASE(19)
+#undef GWAS_BACK_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t sum_columns(const double* contrib, int64_t ldc, int rows, int64_t cols, double* acc,
+                       hipStream_t s) {
+    if (cols <= 0 || rows <= 0) return hipSuccess;
+    if (!contrib || !acc || ldc < cols) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sum_columns_kernel, dim3(rows), dim3(256), 0, s, contrib, ldc, cols, acc);
+    return hipGetLastError();
+}
+
+hipError_t dosage_gemv(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols, const double* coef,
+                       double* g, hipStream_t s) {
+    if (cols <= 0) return hipSuccess;
+    if (!X || !coef || !g || ldx < n) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (xt == X_I8)
+        hipLaunchKernelGGL(dosage_gemv_kernel<int8_t>, dim3(grid), dim3(256), 0, s, (const int8_t*)X, ldx, n,
+                           cols, coef, g);
+    else
+        hipLaunchKernelGGL(dosage_gemv_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)X, ldx, n,
+                           cols, coef, g);
     return hipGetLastError();
 }
 

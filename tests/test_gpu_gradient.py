@@ -1,0 +1,110 @@
+"""GPU reverse pass against the reverse-mode oracle and finite differences."""
+
+import numpy as np
+import pytest
+
+from oracle import gradient as og
+from paper_1304_2272_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _case(n, p, m, seed, h2=0.5, sigma2=1.0, dtype=np.float64):
+    Z = synth.background_genotypes(n, seed, k=min(2000, 2 * n))
+    Phi = Z @ Z.T / Z.shape[1]
+    prob = synth.make_problem(n, p, seed, k=min(2000, 2 * n))
+    XR = synth.snp_block(n, seed, 0, m, dtype=dtype)
+    return Phi, sigma2, h2, prob["XL"], prob["Y"][:, 0], XR
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    binding.load()
+
+
+@pytest.mark.parametrize("x_dtype", ["f64", "i8"])
+def test_reverse_generic_cotangents_vs_oracle(x_dtype):
+    n, p, m = 300, 4, 700
+    _say(f"reverse pass, random cotangents, n={n} p={p} m={m} x={x_dtype}")
+    Phi, s2, h2, XL, y, XR = _case(n, p, m, 21, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    M = og.model_covariance(Phi, s2, h2)
+    rng = np.random.default_rng(4)
+    gb = rng.standard_normal((m, p))
+    gv = rng.standard_normal(m)
+    with binding.GwasContext(M, XL, y, x_dtype=x_dtype, dev_block=256) as ctx:
+        b, var, info = ctx.stream_block(XR)
+        ctx.backward_begin()
+        ctx.backward_block(XR, b[:, 0, :], var, info, gb, gv)
+        gy, tr, ip = ctx.backward_end()
+    gy_o, Mbar = og.reverse(M, XL, y, XR, gb, gv)
+    rel = np.max(np.abs(gy - gy_o)) / np.max(np.abs(gy_o))
+    _say(f"  dl/dy rel err {rel:.2e}; tr {tr:.6e} vs {np.trace(Mbar):.6e}; <Mbar,M> {ip:.6e} vs {np.sum(Mbar * M):.6e}")
+    assert rel < 1e-9
+    assert abs(tr - np.trace(Mbar)) < 1e-9 * np.abs(Mbar).sum()
+    assert abs(ip - np.sum(Mbar * M)) < 1e-9 * max(1.0, np.abs(Mbar * M).sum())
+
+
+def test_autograd_wald_loss_vs_oracle():
+    import torch
+    from paper_1304_2272_amd.autograd import GwasGLS
+    n, p, m = 1200, 4, 1500
+    _say(f"autograd Wald loss n={n} p={p} m={m}")
+    Phi, s2, h2, XL, y, XR = _case(n, p, m, 31, h2=0.37, sigma2=1.4)
+    dev = torch.device("cuda:0")
+    yt = torch.tensor(y, device=dev, requires_grad=True)
+    h2t = torch.tensor(h2, dtype=torch.float64, device=dev, requires_grad=True)
+    b, var = GwasGLS.apply(yt, h2t, torch.tensor(Phi, device=dev), torch.tensor(XL, device=dev),
+                           torch.tensor(XR, device=dev), s2, {"dev_block": 512})
+    loss = (b[:, -1] ** 2 / var).sum()
+    loss.backward()
+    lo, gyo, gho = og.wald_gradient(Phi, s2, h2, XL, y, XR)
+    gy = yt.grad.cpu().numpy()
+    _say(f"  loss {loss.item():.10e} vs {lo:.10e}; dh2 {h2t.grad.item():.10e} vs {gho:.10e}")
+    assert abs(loss.item() - lo) < 1e-10 * lo
+    assert np.max(np.abs(gy - gyo)) < 1e-8 * np.max(np.abs(gyo))
+    assert abs(h2t.grad.item() - gho) < 1e-8 * abs(gho)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_n10000_gradient_vs_differences():
+    import torch
+    from paper_1304_2272_amd.autograd import GwasGLS
+    n, p, m, seed = 10_000, 4, 100_000, 1309
+    _say(f"n={n} p={p} m={m}: gradient vs central differences of the GPU forward")
+    dev = torch.device("cuda:0")
+    Z = torch.tensor(synth.background_genotypes(n, seed), device=dev)
+    Phi = Z @ Z.t().contiguous() / Z.shape[1]
+    del Z
+    prob = synth.make_problem(n, p, seed)
+    XL = torch.tensor(prob["XL"], device=dev)
+    y0 = torch.tensor(prob["Y"][:, 0], device=dev)
+    XR = synth.snp_block_device(n, seed, 0, m, dev)
+    opts = {"x_dtype": "i8"}
+
+    def loss_at(yv, h2v):
+        with torch.no_grad():
+            b, var = GwasGLS.apply(yv, torch.tensor(h2v, dtype=torch.float64, device=dev), Phi, XL, XR, 1.0, opts)
+            return float((b[:, -1] ** 2 / var).sum())
+
+    yt = y0.clone().requires_grad_(True)
+    h2t = torch.tensor(0.5, dtype=torch.float64, device=dev, requires_grad=True)
+    b, var = GwasGLS.apply(yt, h2t, Phi, XL, XR, 1.0, opts)
+    loss = (b[:, -1] ** 2 / var).sum()
+    loss.backward()
+    d = 1e-6
+    fd_h2 = (loss_at(y0, 0.5 + d) - loss_at(y0, 0.5 - d)) / (2 * d)
+    _say(f"  loss {loss.item():.6e}; dh2 {h2t.grad.item():.8e} vs FD {fd_h2:.8e}")
+    assert abs(h2t.grad.item() - fd_h2) < 1e-6 * abs(fd_h2)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    for k in range(4):
+        v = torch.randn(n, generator=g, dtype=torch.float64).to(dev)
+        v /= v.norm()
+        fd = (loss_at(y0 + d * v, 0.5) - loss_at(y0 - d * v, 0.5)) / (2 * d)
+        an = float(yt.grad @ v)
+        _say(f"  direction {k}: dy.v {an:.8e} vs FD {fd:.8e}")
+        assert abs(an - fd) < 1e-4 * max(abs(fd), 1e-3 * float(yt.grad.norm()))
