@@ -91,15 +91,18 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_flags = take(256);
     // room for the schedule and partial sums of every tile shape
     const int at = atype_of(precision);
-    L.sched_len = 0;
+    const int xt = x_dtype == GWAS_X_I8 ? X_I8 : X_F64;
+    // the reverse pass runs the float64 product with its default shape
+    L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
+                                            trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0));
     if (at == A_I8S) {
-        const TrmmShape sh = trmm_sliced_shape();
-        L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh.tm, sh.tn);
+        const TrmmShape sh = trmm_geom(at, xt, 0, slices);
+        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
     }
     for (int c = 0; c < trmm_num_cfgs() && at != A_I8S; ++c) {
-        if (!trmm_cfg_valid(at, x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c)) continue;
-        const TrmmShape sh = trmm_shape(c);
-        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh.tm, sh.tn));
+        if (!trmm_cfg_valid(at, xt, c)) continue;
+        const TrmmShape sh = trmm_geom(at, xt, c, slices);
+        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
     }
     L.off_sched = take(L.sched_len * 2 * 4);
     L.off_sched_tail = take(L.sched_len * 2 * 4);
@@ -339,10 +342,10 @@ void release(gwas_ctx* c) {
 
 int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host) {
     const TrmmShape sh = c->shape;
-    const int64_t len = trmm_schedule_len(c->lay.n_pad, cols, sh.tm, sh.tn);
+    const int64_t len = trmm_schedule_len(c->lay.n_pad, cols, sh);
     host.assign((size_t)(2 * len), 0);
     if (len > (int64_t)c->lay.sched_len ||
-        trmm_schedule(c->lay.n_pad, cols, sh.tm, sh.tn, host.data(), len) != len) {
+        trmm_schedule(c->lay.n_pad, cols, sh, host.data(), len) != len) {
         c->err = "tile schedule does not fit";
         return GWAS_E_INVALID;
     }
@@ -373,7 +376,7 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.part = c->part;
     ta.ldp = Y.dev_block;
     ta.sched = c->sched;
-    ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape.tm, c->shape.tn);
+    ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape);
     return ta;
 }
 
@@ -418,34 +421,9 @@ hipError_t finish_sub(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t 
 // longest first to the least loaded of the 8 XCD lists (workgroup b runs on
 // XCD b % 8); each list keeps its units in that order.
 int64_t group_schedule(const std::vector<gwas_ctx*>& cs, int64_t cols, std::vector<int>& out) {
-    const TrmmShape sh = cs[0]->shape;
-    const int64_t ncb = (cols + sh.tn - 1) / sh.tn;
-    struct Unit { int64_t w; int c; int I; };
-    std::vector<Unit> units;
-    for (size_t c = 0; c < cs.size(); ++c) {
-        const int64_t nrb = cs[c]->lay.n_pad / sh.tm;
-        for (int64_t I = 0; I < nrb; ++I) units.push_back(Unit{(I + 1) * sh.tm, (int)c, (int)I});
-    }
-    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.w > b.w; });
-    std::vector<std::vector<int>> lists(8);
-    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (const Unit& u : units) {
-        const int x = (int)(std::min_element(load, load + 8) - load);
-        load[x] += u.w * ncb;
-        lists[x].push_back((int)(u.I | (u.c << SCHED_CTX_SHIFT)));
-    }
-    size_t longest = 0;
-    for (auto& l : lists) longest = std::max(longest, l.size() * (size_t)ncb);
-    out.assign(2 * 8 * longest, -1);
-    for (int x = 0; x < 8; ++x) {
-        size_t q = 0;
-        for (int e : lists[x])
-            for (int64_t J = 0; J < ncb; ++J, ++q) {
-                out[2 * (8 * q + x)] = e;
-                out[2 * (8 * q + x) + 1] = (int)J;
-            }
-    }
-    return (int64_t)(8 * longest);
+    std::vector<int64_t> nrb(cs.size());
+    for (size_t c = 0; c < cs.size(); ++c) nrb[c] = cs[c]->lay.n_pad / cs[0]->shape.tm;
+    return trmm_schedule_multi(nrb.data(), (int)cs.size(), cols, cs[0]->shape, &out);
 }
 
 int init_body(gwas_ctx* c, const gwas_desc* d) {
@@ -543,7 +521,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         const int v = atoi(e);
         if (trmm_cfg_valid(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, v)) c->cfg = v;
     }
-    c->shape = (c->at == A_I8S) ? trmm_sliced_shape() : trmm_shape(c->cfg);
+    c->shape = trmm_geom(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c->cfg, slices);
     auto bail = [&](int code) {
         release(c);
         c->magic = CTX_DEAD;
@@ -966,7 +944,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         for (int cfg = 0; cfg < trmm_num_cfgs(); ++cfg) {
             if (!trmm_cfg_valid(c->at, xt, cfg)) continue;
             c->cfg = cfg;
-            c->shape = trmm_shape(cfg);
+            c->shape = trmm_geom(c->at, xt, cfg, Y.slices);
             int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
             if (rc) return rc;
             TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
@@ -993,7 +971,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         }
     }
     c->cfg = best;
-    c->shape = trmm_shape(best);
+    c->shape = trmm_geom(c->at, xt, best, Y.slices);
     c->tail_cols = -1;
     int rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
     if (rc) return rc;
@@ -1015,7 +993,8 @@ int gwas_backward_begin(gwas_ctx* c) {
     Back* B = c->back;
     const int p = Y.p;
     const int64_t np = Y.n_pad, blk = Y.dev_block;
-    const TrmmShape sh = trmm_shape(trmm_default_cfg(A_F64, (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64));
+    const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    const TrmmShape sh = trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0);
     if (!B->mem) {
         B->npb = np / sh.part_rows;
         size_t o = 0;
@@ -1081,7 +1060,7 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
     const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
     const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
     const int cfg = trmm_default_cfg(A_F64, xt);
-    const TrmmShape sh = trmm_shape(cfg);
+    const TrmmShape sh = trmm_geom(A_F64, xt, cfg, 0);
     const bool direct_x = on_device(XR) && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
                           ((ldx * (int64_t)elem) % 16 == 0);
     const int64_t blk = Y.dev_block;
@@ -1104,8 +1083,8 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
         HIPCHK(c, hipMemcpyAsync(B->si, info + col0, cols * 4, hipMemcpyDefault, s));
         if (gvar) HIPCHK(c, hipMemcpyAsync(B->sgv, gvar + col0, cols * 8, hipMemcpyDefault, s));
         // w = M^-1 x with the sums w^T [W_L | w_y] and w^T w
-        std::vector<int> sched((size_t)(2 * trmm_schedule_len(Y.n_pad, cols, sh.tm, sh.tn)));
-        const int64_t ns = trmm_schedule(Y.n_pad, cols, sh.tm, sh.tn, sched.data(), (int64_t)sched.size() / 2);
+        std::vector<int> sched((size_t)(2 * trmm_schedule_len(Y.n_pad, cols, sh)));
+        const int64_t ns = trmm_schedule(Y.n_pad, cols, sh, sched.data(), (int64_t)sched.size() / 2);
         if (ns < 0 || (size_t)(2 * ns) * sizeof(int) > Y.sched_len * 2 * sizeof(int)) {
             c->err = "reverse-pass schedule does not fit";
             return GWAS_E_INVALID;

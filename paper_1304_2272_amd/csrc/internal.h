@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "schedule.h"
+
 namespace gwas {
 
 // ---- tiles of the matrix-core kernels ----------------------------------
@@ -84,8 +86,6 @@ enum XType : int { X_F64 = 0, X_I8 = 1 };
 //   sched two int32 per workgroup: (row tile, column tile), -1 = idle.
 //   cfg   tile shape (trmm_shape).
 // Schedule entries: (row tile | context << SCHED_CTX_SHIFT, column tile).
-constexpr int SCHED_CTX_SHIFT = 20;
-constexpr int SCHED_ROW_MASK = (1 << SCHED_CTX_SHIFT) - 1;
 constexpr int MAX_GROUP = 64;
 
 struct TrmmArgs {
@@ -104,13 +104,14 @@ struct TrmmArgs {
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
 
-struct TrmmShape { int tm, tn, part_rows, threads; };
 int trmm_num_cfgs();
 TrmmShape trmm_shape(int cfg);
 bool trmm_cfg_valid(int at, int xt, int cfg);
 int trmm_default_cfg(int at, int xt);
 constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of the floating-point shapes
 TrmmShape trmm_sliced_shape();       // tile of the int8-slice product (part_rows 16)
+// shape of the kernel that runs (at, xt, cfg, slices), with its schedule grouping
+TrmmShape trmm_geom(int at, int xt, int cfg, int slices);
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
 // and S int8 slices A_s(r,k) with L^-1(r,k)/rscale[r] = sum_s A_s(r,k) 2^(-6-7s)
@@ -119,10 +120,13 @@ TrmmShape trmm_sliced_shape();       // tile of the int8-slice product (part_row
 hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int S, int8_t* A,
                       int64_t lda, double* rscale, hipStream_t s);
 
-// Host side: tile schedule for n_pad rows and `cols` SNP columns with tm x tn
-// tiles.  Returns the number of workgroups and fills `out` (2 ints each).
-int64_t trmm_schedule(int64_t n_pad, int64_t cols, int tm, int tn, int* out, int64_t cap);
-int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, int tm, int tn);
+// Host side: tile schedule for n_pad rows and `cols` SNP columns with the
+// tiles of `sh`.  Returns the number of workgroups and fills `out` (2 ints
+// each; -1 = idle workgroup).  The multi-context form takes each context's
+// row-tile count and tags entries with the context index.
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, const TrmmShape& sh, int* out, int64_t cap);
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, const TrmmShape& sh);
+// (trmm_schedule_multi, the multi-context form, is in schedule.h)
 
 // xw[q * ldxw + j] = x_j^T W[:, q] for q < Qc (float64 accumulation).
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,

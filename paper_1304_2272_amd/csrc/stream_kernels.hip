@@ -9,6 +9,7 @@
 #include "internal.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -31,10 +32,11 @@ constexpr int ROW_STRIDE = ROW_BYTES + 16;
 constexpr int FLUSH_STAGES = 4;   // reduced-precision sums move to float64 every 4 stages
 
 // Accumulator layout of the 16x16 instructions: element v of a lane holds
-// column lane%16 and row ROW_G*(lane/16) + ROW_V*v.
+// column lane%16 and row ROW_G*(lane/16) + ROW_V*v.  NQ: sub-steps a lane's
+// 32-byte K slice of a stage is read in (see trmm_stream_kernel).
 template <typename AT> struct MM;
 template <> struct MM<double> {
-    static constexpr int BK = 16, KPL = 1;
+    static constexpr int BK = 16, KPL = 1, NQ = 4;
     static constexpr int ROW_G = 1, ROW_V = 4;
     typedef d4_t acc_t;
     typedef double frag_t;
@@ -43,7 +45,7 @@ template <> struct MM<double> {
     }
 };
 template <> struct MM<float> {
-    static constexpr int BK = 32, KPL = 1;
+    static constexpr int BK = 32, KPL = 1, NQ = 4;
     static constexpr int ROW_G = 4, ROW_V = 1;
     typedef f4_t acc_t;
     typedef float frag_t;
@@ -52,7 +54,7 @@ template <> struct MM<float> {
     }
 };
 template <> struct MM<__bf16> {
-    static constexpr int BK = 64, KPL = 8;
+    static constexpr int BK = 64, KPL = 8, NQ = 2;
     static constexpr int ROW_G = 4, ROW_V = 1;
     typedef f4_t acc_t;
     typedef bf8_t frag_t;
@@ -65,16 +67,32 @@ template <typename AT> __device__ __forceinline__ AT from_i8(int8_t x) { return 
 template <typename AT> __device__ __forceinline__ AT from_f64(double x) { return (AT)x; }
 template <> __device__ __forceinline__ __bf16 from_f64<__bf16>(double x) { return (__bf16)(float)x; }
 
+// Operand of instruction s from a lane's 8- or 16-byte fragment piece.  A
+// vector element is copied to a scalar before its bit cast: hipcc's
+// __builtin_bit_cast of an element expression v[s] reads element 0.
 template <typename AT>
-__device__ __forceinline__ typename MM<AT>::frag_t frag(const u4_t (&f)[2], int s) {
+__device__ __forceinline__ typename MM<AT>::frag_t frag(const u4_t& f, int s) {
     if constexpr (sizeof(AT) == 8) {
-        return reinterpret_cast<const double*>(f)[s];
+        return __builtin_bit_cast(double, u2_t{f[2 * s], f[2 * s + 1]});
     } else if constexpr (sizeof(AT) == 4) {
-        return reinterpret_cast<const float*>(f)[s];
+        const uint32_t w = f[s];
+        return __builtin_bit_cast(float, w);
     } else {
-        return reinterpret_cast<const bf8_t*>(f)[s];
+        return __builtin_bit_cast(bf8_t, f);
     }
 }
+template <typename AT>
+__device__ __forceinline__ typename MM<AT>::frag_t frag(const u2_t& f, int s) {
+    if constexpr (sizeof(AT) == 8) {
+        return __builtin_bit_cast(double, f);
+    } else {
+        static_assert(sizeof(AT) == 4, "8-byte pieces hold float64 or float32 operands");
+        const uint32_t w = f[s];
+        return __builtin_bit_cast(float, w);
+    }
+}
+template <int BYTES> struct Piece { typedef u4_t type; };
+template <> struct Piece<8> { typedef u2_t type; };
 
 __device__ __forceinline__ double wave_sum16(double v) {
     // sum over the four lane groups (lanes l, l+16, l+32, l+48)
@@ -157,6 +175,23 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 ra[c] = *reinterpret_cast<const u4_t*>(Ut + (r0 + row) * row_bytes + kt * ROW_BYTES + ch * 16);
             }
         }
+        // Whole tile inside the block and the stage inside n: one branch for
+        // the workgroup and plain 16-byte loads.  This pays where a stage
+        // holds few matrix-core cycles (float32, bfloat16); the float64
+        // product measured faster with the per-lane checks alone.
+        if constexpr (sizeof(AT) < 8) {
+            if (c0 + TN <= a.cols && (kt + 1) * BK <= a.n) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const int idx = tid + c * NT;
+                    if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
+                        const int col = idx / CPC, ch = idx % CPC;
+                        rb[c] = *reinterpret_cast<const u4_t*>(X + (c0 + col) * a.ldx + kt * BK + ch * EPC);
+                    }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int idx = tid + c * NT;
@@ -199,47 +234,95 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         }
     };
 
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) load(kt + 1);
-        u4_t af[WTM][2], bf[WTN][2];
+    auto flush = [&]() {
 #pragma unroll
-        for (int i = 0; i < WTM; ++i) {
-            const u4_t* pa = reinterpret_cast<const u4_t*>(As[buf] + (wr * WTM * 16 + i * 16 + li) * ROW_STRIDE + lg * 32);
-            af[i][0] = pa[0];
-            af[i][1] = pa[1];
-        }
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-            const u4_t* pb = reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32);
-            bf[j][0] = pb[0];
-            bf[j][1] = pb[1];
-        }
+            for (int j = 0; j < WTN; ++j) {
 #pragma unroll
-        for (int s = 0; s < BK / 4 / T::KPL; ++s)
+                for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+                acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+            }
+    };
+    // A lane's K slice of a stage (32 bytes of A and of B per 16-row block)
+    // is read in NQ pieces into two alternating register sets: piece q + 1
+    // is read while piece q's matrix instructions run, and the next stage's
+    // first piece is read right after the barrier, behind the last piece's
+    // instructions, so no wave waits on LDS at a stage boundary.  NQ = 1
+    // reads the whole slice before the stage's instructions (for tiles with
+    // no registers to spare).
+    // 64 x 64 waves of the reduced-precision products carry float64 sums
+    // besides their float32 ones; two of them per SIMD leave no registers
+    // for a second set
+    constexpr bool TIGHT = (NT / 64) * S::MINB > 4;
+    constexpr int NQ = (LOWP && TIGHT && WTM * WTN >= 16) ? 1 : T::NQ;
+    constexpr int PB = NQ == 1 ? 16 : 32 / NQ;                   // bytes per piece
+    constexpr int IPP = PB / (int)(sizeof(AT) * T::KPL);         // instructions per piece
+    typedef typename Piece<PB>::type piece_t;
+    auto read_piece = [&](int buf, int q, piece_t (&fa)[WTM], piece_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+            fa[i] = *reinterpret_cast<const piece_t*>(As[buf] + (wr * WTM * 16 + i * 16 + li) * ROW_STRIDE + lg * 32 + q * PB);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+            fb[j] = *reinterpret_cast<const piece_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32 + q * PB);
+    };
+    auto mma_piece = [&](const piece_t (&fa)[WTM], const piece_t (&fb)[WTN]) {
+#pragma unroll
+        for (int s = 0; s < IPP; ++s)
 #pragma unroll
             for (int i = 0; i < WTM; ++i)
 #pragma unroll
                 for (int j = 0; j < WTN; ++j)
-                    acc[i][j] = T::mma(frag<AT>(af[i], s), frag<AT>(bf[j], s), acc[i][j]);
-        if constexpr (LOWP) {
-            if ((kt + 1) % FLUSH_STAGES == 0 || !more) {
+                    acc[i][j] = T::mma(frag<AT>(fa[i], s), frag<AT>(fb[j], s), acc[i][j]);
+    };
+
+    load(0);
+    store(0);
+    __syncthreads();
+    if constexpr (NQ == 1) {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) load(kt + 1);
+            piece_t fa[2][WTM], fb[2][WTN];
+            read_piece(buf, 0, fa[0], fb[0]);
+            read_piece(buf, 1, fa[1], fb[1]);
+            mma_piece(fa[0], fb[0]);
+            mma_piece(fa[1], fb[1]);
+            if constexpr (LOWP) {
+                if ((kt + 1) % FLUSH_STAGES == 0 || !more) flush();
+            }
+            // the other buffer held stage kt - 1, which every wave finished
+            // reading before the previous barrier
+            if (more) store(buf ^ 1);
+            __syncthreads();
+        }
+    } else {
+        piece_t pa[2][WTM], pb[2][WTN];
+        read_piece(0, 0, pa[0], pb[0]);
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) load(kt + 1);
 #pragma unroll
-                for (int i = 0; i < WTM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WTN; ++j) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
-                        acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+            for (int q = 0; q < NQ; ++q) {
+                if (q + 1 < NQ) {
+                    read_piece(buf, q + 1, pa[(q + 1) & 1], pb[(q + 1) & 1]);
+                } else {
+                    // the other buffer held stage kt - 1, which every wave
+                    // finished reading before the previous barrier
+                    if (more) store(buf ^ 1);
+                    if constexpr (LOWP) {
+                        if (kt % FLUSH_STAGES == FLUSH_STAGES - 1) flush();
                     }
+                    __syncthreads();
+                    if (more) read_piece(buf ^ 1, 0, pa[0], pb[0]);
+                }
+                mma_piece(pa[q & 1], pb[q & 1]);
             }
         }
-        if (more) store(buf ^ 1);
-        __syncthreads();
+        if constexpr (LOWP) flush();
     }
     if constexpr (!LOWP) {
 #pragma unroll
@@ -341,6 +424,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
 #pragma unroll
         for (int j = 0; j < WTN; ++j) acc[i][j] = i4_t{0, 0, 0, 0};
 
+    // Staged operands of the next stage: loaded at the top of a stage,
+    // written to the other LDS buffer before its barrier.
     u4_t ra[CA], rb[CB];
     auto load = [&](int64_t kt) {
 #pragma unroll
@@ -348,6 +433,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
             const int idx = tid + c * NT;
             if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
                 ra[c] = *reinterpret_cast<const u4_t*>(A + (int64_t)(idx >> 3) * a.ldu + kt * BK + (idx & 7) * 16);
+        }
+        // whole tile inside the block and the stage inside n: one branch for
+        // the workgroup, plain 16-byte loads
+        if (c0 + TN <= a.cols && (kt + 1) * BK <= a.n) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int idx = tid + c * NT;
+                if (B_CHUNKS % NT == 0 || idx < B_CHUNKS)
+                    rb[c] = *reinterpret_cast<const u4_t*>(X + (c0 + (idx >> 3)) * a.ldx + kt * BK + (idx & 7) * 16);
+            }
+            return;
         }
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -382,7 +478,25 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
                 *reinterpret_cast<u4_t*>(Bs[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = rb[c];
         }
     };
-
+    // Fragments of one 64-deep K step (h = 0, 1 of a stage).  (Reading the
+    // second step behind the first step's instructions, as the floating-point
+    // product does, measured slower here.)
+    auto read_step = [&](int buf, int h, u4_t (&fa)[S], u4_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            fa[i] = *reinterpret_cast<const u4_t*>(As[buf] + (wr * S * 16 + i * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+            fb[j] = *reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
+    };
+    auto mma_step = [&](const u4_t (&fa)[S], const u4_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reinterpret_cast<const i4_t&>(fa[i]),
+                                                                 reinterpret_cast<const i4_t&>(fb[j]), acc[i][j], 0, 0, 0);
+    };
     load(0);
     store(0);
     __syncthreads();
@@ -390,28 +504,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) load(kt + 1);
-        u4_t af[S][2], bf[WTN][2];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const u4_t* pa = reinterpret_cast<const u4_t*>(As[buf] + (wr * S * 16 + i * 16 + li) * ROW_STRIDE + lg * 32);
-            af[i][0] = pa[0];
-            af[i][1] = pa[1];
-        }
-#pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-            const u4_t* pb = reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32);
-            bf[j][0] = pb[0];
-            bf[j][1] = pb[1];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < S; ++i)
-#pragma unroll
-                for (int j = 0; j < WTN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                        reinterpret_cast<const i4_t&>(af[i][h]), reinterpret_cast<const i4_t&>(bf[j][h]),
-                        acc[i][j], 0, 0, 0);
+        u4_t a0[S], b0[WTN], a1[S], b1[WTN];
+        read_step(buf, 0, a0, b0);
+        read_step(buf, 1, a1, b1);
+        mma_step(a0, b0);
+        mma_step(a1, b1);
+        // the other buffer held stage kt - 1, which every wave finished
+        // reading before the previous barrier
         if (more) store(buf ^ 1);
         __syncthreads();
     }
@@ -765,7 +864,7 @@ typedef Shape<2, 4, 4, 4, 1> Cfg3;   // 128 x 256, 512 threads, waves of 64 x 64
 typedef Shape<4, 2, 4, 4, 1> Cfg4;   // 256 x 128, 512 threads, waves of 64 x 64
 typedef Shape<2, 2, 4, 4, 1> Cfg5;   // as Cfg0, one workgroup per CU
 
-template <typename S> TrmmShape shape_of() { return TrmmShape{S::TM, S::TN, S::WTM * 16, S::NT}; }
+template <typename S> TrmmShape shape_of() { return TrmmShape{S::TM, S::TN, S::WTM * 16, S::NT, 1, 32}; }
 
 template <typename AT, typename XT, typename S>
 hipError_t launch_trmm(const TrmmArgs& a, hipStream_t s) {
@@ -810,7 +909,7 @@ TrmmShape trmm_shape(int cfg) {
         case 3: return shape_of<Cfg3>();
         case 4: return shape_of<Cfg4>();
         case 5: return shape_of<Cfg5>();
-        default: return TrmmShape{0, 0, 0, 0};
+        default: return TrmmShape{0, 0, 0, 0, 0, 0};
     }
 }
 
@@ -833,59 +932,38 @@ int trmm_default_cfg(int at, int xt) {
     return 1;
 }
 
-static int xcd_of_rank(int64_t r) {
-    const int64_t grp = r / 8, pos = r % 8;
-    return (grp % 2 == 0) ? (int)pos : (int)(7 - pos);
+TrmmShape trmm_geom(int at, int xt, int cfg, int slices) {
+    TrmmShape sh = (at == A_I8S) ? trmm_sliced_shape() : trmm_shape(cfg);
+    if (sh.tm == 0) return sh;
+    // workgroups per CU: the 256-thread shape is sized for two
+    const int per_cu = (at != A_I8S && cfg == 0) ? 2 : 1;
+    sh.inflight = 32 * per_cu;
+    const int64_t asz = at == A_F64 ? 8 : at == A_F32 ? 4 : at == A_BF16 ? 2 : 1;
+    const int64_t arows = at == A_I8S ? (int64_t)sh.tm * slices : sh.tm;
+    const int64_t xsz = xt == X_I8 ? 1 : 8;
+    sh.rgroup = row_group_for(arows * asz, (int64_t)sh.tn * xsz, sh.inflight);
+    if (const char* e = getenv("GWAS_SCHED_RGROUP")) {   // measurement override
+        const int v = atoi(e);
+        if (v >= 1 && v <= sh.inflight) sh.rgroup = v;
+    }
+    return sh;
 }
 
-int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, int tm, int tn) {
-    const int64_t nrb = n_pad / tm;
-    const int64_t ncb = (cols + tn - 1) / tn;
-    if (nrb < 16) return nrb * ncb;
-    // row blocks dealt to 8 XCD lists; the longest list sets the grid
-    int64_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t r = 0; r < nrb; ++r) len[xcd_of_rank(r)] += ncb;
-    return 8 * *std::max_element(len, len + 8);
+int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, const TrmmShape& sh) {
+    const int64_t nrb = n_pad / sh.tm;
+    return trmm_schedule_multi(&nrb, 1, cols, sh, nullptr);
 }
 
-int64_t trmm_schedule(int64_t n_pad, int64_t cols, int tm, int tn, int* out, int64_t cap) {
-    const int64_t nrb = n_pad / tm;
-    const int64_t ncb = (cols + tn - 1) / tn;
-    const int64_t total = trmm_schedule_len(n_pad, cols, tm, tn);
+int64_t trmm_schedule(int64_t n_pad, int64_t cols, const TrmmShape& sh, int* out, int64_t cap) {
+    const int64_t nrb = n_pad / sh.tm;
+    std::vector<int> v;
+    const int64_t total = trmm_schedule_multi(&nrb, 1, cols, sh, &v);
     if (total > cap) return -1;
-    if (nrb < 16) {
-        int64_t b = 0;
-        for (int64_t I = nrb - 1; I >= 0; --I)
-            for (int64_t J = 0; J < ncb; ++J, ++b) {
-                out[2 * b] = (int)I;
-                out[2 * b + 1] = (int)J;
-            }
-        return total;
-    }
-    // Workgroup b runs on XCD b % 8.  Row blocks, longest (largest I) first,
-    // are dealt to the XCDs in snake order (0..7, 7..0, ...), which balances
-    // the triangular work; each XCD runs its row blocks in descending order
-    // with all column tiles of one row block together, so they share the
-    // L^-1 panel in that XCD's L2.
-    std::vector<std::vector<int64_t>> rows(8);
-    for (int64_t r = 0; r < nrb; ++r) rows[xcd_of_rank(r)].push_back(nrb - 1 - r);
-    const int64_t per = total / 8;
-    for (int x = 0; x < 8; ++x) {
-        int64_t q = 0;
-        for (int64_t I : rows[x])
-            for (int64_t J = 0; J < ncb; ++J, ++q) {
-                out[2 * (8 * q + x)] = (int)I;
-                out[2 * (8 * q + x) + 1] = (int)J;
-            }
-        for (; q < per; ++q) {
-            out[2 * (8 * q + x)] = -1;
-            out[2 * (8 * q + x) + 1] = -1;
-        }
-    }
+    std::copy(v.begin(), v.end(), out);
     return total;
 }
 
-TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512}; }
+TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512, 1, 32}; }
 
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.cols <= 0) return hipSuccess;
@@ -895,17 +973,15 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
     const size_t xs = a.xt == X_I8 ? 1 : 8;
     if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
-    TrmmShape sh;
     if (a.at == A_I8S) {
         if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6)
             return hipErrorInvalidValue;
-        sh = trmm_sliced_shape();
     } else {
         if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;
-        sh = trmm_shape(a.cfg);
     }
+    const TrmmShape sh = trmm_geom(a.at, a.xt, a.cfg, a.slices);
     if (a.n_pad % sh.tm) return hipErrorInvalidValue;
-    if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh.tm, sh.tn)))
+    if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh)))
         return hipErrorInvalidValue;
     if (a.n_sched > 0x7fffffff) return hipErrorInvalidValue;
     return hipSuccess;
