@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "SNP GLS solves/sec at n=50k,p=8 (mixed vs FP64); TRSM % of MFMA peak"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}   # dense matrix-core peaks
+PROBE_ITERS = 100000   # runs of 8 instructions per wave in the measured-peak probe
 SLICES = 6   # int8 digits per entry of L^-1 in the int8 leg
 WORKLOADS = {
     "n50000_p8": dict(n=50_000, p=8, m=1_000_000, step=50_000, x_dtype="i8"),
@@ -93,6 +94,25 @@ def cpu_baseline(workload, seed, n_s, m_s, threads):
     }
 
 
+def pinned_h2d_peak(nbytes=1 << 30, reps=3):
+    """Host-to-device rate of one large copy from pinned host memory (GB/s),
+    the roof of the PCIe-inclusive path."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return rate
+
+
 def run_leg(name, prob_dev, blocks, steps, warmup, workload, pcie_steps=0):
     import torch
     from paper_1304_2272_amd import binding
@@ -132,6 +152,7 @@ def run_leg(name, prob_dev, blocks, steps, warmup, workload, pcie_steps=0):
         el = time.perf_counter() - t1
         nb = sum(h.numel() * h.element_size() for h in host)
         pcie = {"snps_per_s": sum(h.shape[0] for h in host) / el, "host_to_device_GBps": nb / el / 1e9,
+                "pinned_h2d_peak_GBps": pinned_h2d_peak(),
                 "steps": pcie_steps, "note": "dosages in pinned host memory, b/var/info to pinned host memory"}
         log(f"[{name}] PCIe-inclusive: {pcie['snps_per_s']:.1f} SNP/s, {pcie['host_to_device_GBps']:.1f} GB/s of dosages")
     ctx.close()
@@ -140,16 +161,19 @@ def run_leg(name, prob_dev, blocks, steps, warmup, workload, pcie_steps=0):
     achieved = ops_per_snp * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     fp64_equiv = float(n) * float(n) * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     peak = PEAK_TFLOPS[name]
+    # the same instruction's rate measured on this device at its clock under load
+    measured_peak = binding.peak_probe(name, iters=PROBE_ITERS) / 1e12
     log(f"[{name}] init {init_s:.2f} s, {snps} SNPs in {elapsed:.3f} s = {snps / elapsed:.1f} SNP/s, "
         f"TRMM {launches} launches {kms:.1f} ms -> {achieved:.2f} T{'OP' if name == 'int8' else 'FLOP'}/s "
-        f"({achieved / peak:.3f} of peak)")
+        f"({achieved / peak:.3f} of peak, {achieved / measured_peak:.3f} of the measured {measured_peak:.1f})")
     return {
         "snps_per_s": snps / elapsed, "elapsed_s": elapsed, "init_s": init_s, "snps": snps,
         "ms_per_step": 1e3 * elapsed / max(steps, 1),
         "kernel": {"launches": launches, "total_ms": kms, "avg_ms": kms / max(launches, 1),
                    "columns": kcols},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TOP/s" if name == "int8" else "TFLOP/s", "frac": achieved / peak},
+                     "unit": "TOP/s" if name == "int8" else "TFLOP/s", "frac": achieved / peak,
+                     "measured_peak": measured_peak, "frac_of_measured": achieved / measured_peak},
         "n2_tflops": fp64_equiv,
         "rank_flags_last_step": info_bad,
         "pcie": pcie,

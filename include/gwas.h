@@ -258,6 +258,20 @@ int gwas_kernel_time(gwas_ctx* ctx, int64_t* launches, double* total_ms,
 int gwas_query(const gwas_ctx* ctx, int64_t* n_pad, int64_t* dev_block,
                int32_t* device);
 
+/* ---- measured matrix-core peak ------------------------------------------
+ * Sustained rate, in operations per second, of the matrix-core instruction
+ * the triangular product of precision `kind` runs (GWAS_FP64: float64
+ * 16x16x4; GWAS_FP32_REFINE: float32 16x16x4; GWAS_BF16_REFINE: bfloat16
+ * 16x16x32; GWAS_INT8_SLICED: int8 16x16x64), on `device`, with `iters`
+ * runs of 8 independent instructions per wave over a launch that fills the
+ * chip (after an equal untimed launch that lets the clock settle).  It
+ * measures the clock the device holds under matrix load, beside the
+ * published peak that fractions of peak are quoted against.  Allocates and
+ * frees a 4 MB device buffer; needs no context; leaves the current device
+ * as it was.  GWAS_E_INVALID for a bad kind, iters outside [1, 2^32] or a
+ * NULL result pointer; GWAS_E_NO_DEVICE, GWAS_E_OOM or GWAS_E_HIP. */
+int gwas_peak_probe(int32_t kind, int32_t device, int64_t iters, double* ops_per_s);
+
 #ifdef __cplusplus
 }
 #endif

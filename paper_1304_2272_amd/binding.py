@@ -32,7 +32,7 @@ X_DTYPES = {"f64": 0, "i8": 1}
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
              "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
-             "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end")
+             "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe")
 GROUP_GRAPH = 1
 
 
@@ -109,8 +109,21 @@ def load():
     L.gwas_backward_block.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp, vp, i64, vp]
     L.gwas_backward_end.restype = ctypes.c_int
     L.gwas_backward_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.gwas_peak_probe.restype = ctypes.c_int
+    L.gwas_peak_probe.argtypes = [i32, i32, i64, ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
+
+
+def peak_probe(precision, device=0, iters=20000):
+    """Measured matrix-core rate (operations/s) of the instruction the
+    triangular product of ``precision`` runs (see ``gwas_peak_probe``)."""
+    L = load()
+    out = ctypes.c_double()
+    rc = L.gwas_peak_probe(PRECISIONS[precision], device, iters, ctypes.byref(out))
+    if rc:
+        raise GwasError(rc, L.gwas_strerror(rc).decode())
+    return out.value
 
 
 def workspace_bytes(n, p, t=1, dev_block=0, precision="fp64", x_dtype="f64"):

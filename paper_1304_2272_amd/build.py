@@ -28,9 +28,16 @@ FLAGS = [
 ]
 
 
+# Per-source flags.  The matrix-core peak probe keeps its loop-carried
+# accumulators in VGPRs: with accumulation registers the compiler copies
+# them at the loop back-edge, which serialises the independent chains the
+# probe is meant to time.
+FILE_FLAGS = {"peak_probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -95,3 +95,14 @@ def test_null_context_calls(lib):
     assert lib.gwas_set_timing(None, 1) == 7
     assert lib.gwas_strerror(2).decode().startswith("M is not positive definite")
     assert lib.gwas_strerror(12345).decode() == "unknown status"
+
+
+def test_peak_probe_validates_before_device(lib):
+    out = ctypes.c_double(-1.0)
+    assert lib.gwas_peak_probe(7, 0, 100, ctypes.byref(out)) == 1      # bad kind
+    assert lib.gwas_peak_probe(0, 0, 0, ctypes.byref(out)) == 1        # iters < 1
+    assert lib.gwas_peak_probe(0, 0, 100, None) == 1                   # no result pointer
+    assert out.value == -1.0
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.gwas_peak_probe(0, 0, 100, ctypes.byref(out)) == 4  # GWAS_E_NO_DEVICE

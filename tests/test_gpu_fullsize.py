@@ -101,3 +101,46 @@ def test_n50000_fp64_planted(n50k):
     dev = np.max(np.abs(b.cpu().numpy()[:, 0, :] - want))
     _say(f"  max |b - planted| {dev:.3e}")
     assert (info.cpu().numpy() == 0).all() and dev < 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_cohorts_grouped_graph_sampled_vs_oracle():
+    """Eight cohorts of uneven n (2k..30k), t = 64 traits, p = 4, int8
+    dosages, one grouped graph-replayed call over 4,096 SNP positions: 64
+    SNPs x 4 traits of every cohort against the oracle."""
+    import torch
+    p, t, m, seed = 4, 64, 4096, 1307
+    dev = torch.device("cuda:0")
+    spec = synth.cohorts(8, seed)
+    _say("cohorts n =", [c["n"] for c in spec])
+    data = []
+    for i, c in enumerate(spec):
+        pr = synth.make_problem(c["n"], p, c["seed"], t=t, h2=c["h2"], device="cuda:0")
+        data.append({"M": pr["M"], "XL": pr["XL"], "Y": pr["Y"],
+                     "X": synth.snp_block_device(c["n"], seed, 0, m, dev, cohort=i)})
+    ctxs = [binding.GwasContext(d["M"], torch.from_numpy(d["XL"]).to(dev), torch.from_numpy(d["Y"]).to(dev),
+                                x_dtype="i8") for d in data]
+    try:
+        eager = binding.stream_group(ctxs, [d["X"] for d in data])
+        res = binding.stream_group(ctxs, [d["X"] for d in data], graph=True)
+        for (be, _, _), (bg, _, _) in zip(eager, res):
+            assert torch.equal(be, bg)
+    finally:
+        for c in ctxs:
+            c.close()
+    rng = np.random.default_rng(seed)
+    traits = [0, 21, 42, 63]
+    worst = 0.0
+    for i, d in enumerate(data):
+        idx = sorted(set([0, 1, m - 2, m - 1]) | set(rng.choice(m, 60, replace=False).tolist()))
+        XS = d["X"][idx].cpu().numpy().astype(np.float64)
+        M = d["M"].cpu().numpy() if hasattr(d["M"], "cpu") else d["M"]
+        _say(f"  cohort {i} n={M.shape[0]}: oracle on {len(idx)} SNPs x {len(traits)} traits")
+        bo, _, io = GLSOracle(M, d["XL"], d["Y"][:, traits]).solve(XS)
+        b = res[i][0].cpu().numpy()[idx][:, traits, :]
+        assert np.array_equal(res[i][2].cpu().numpy()[idx], io)
+        err = normwise(b, bo)
+        worst = max(worst, err)
+        _say(f"    max normwise err {err:.3e}")
+        del M
+    assert worst < 1e-10

@@ -108,3 +108,34 @@ def test_n10000_gradient_vs_differences():
         an = float(yt.grad @ v)
         _say(f"  direction {k}: dy.v {an:.8e} vs FD {fd:.8e}")
         assert abs(an - fd) < 1e-4 * max(abs(fd), 1e-3 * float(yt.grad.norm()))
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_n10000_gradient_vs_oracle_on_2000_snps():
+    """The differentiation workload's shape (n = 10,000, p = 4, float64
+    dosages) on a fixed 2,000-SNP subset, loss restricted to that subset:
+    loss, dl/dy and dl/dh^2 against the oracle gradient."""
+    import torch
+    from paper_1304_2272_amd.autograd import GwasGLS
+    n, p, m, seed, h2, s2 = 10_000, 4, 2000, 1310, 0.5, 1.0
+    _say(f"n={n} p={p} m={m}: GPU reverse pass vs oracle gradient")
+    Z = synth.background_genotypes(n, seed)
+    Phi = Z @ Z.T / Z.shape[1]
+    del Z
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m)
+    dev = torch.device("cuda:0")
+    yt = torch.tensor(prob["Y"][:, 0], device=dev, requires_grad=True)
+    h2t = torch.tensor(h2, dtype=torch.float64, device=dev, requires_grad=True)
+    b, var = GwasGLS.apply(yt, h2t, torch.tensor(Phi, device=dev), torch.tensor(prob["XL"], device=dev),
+                           torch.tensor(XR, device=dev), s2, {})
+    loss = (b[:, -1] ** 2 / var).sum()
+    loss.backward()
+    lo, gyo, gho = og.wald_gradient_contracted(Phi, s2, h2, prob["XL"], prob["Y"][:, 0], XR)
+    gy = yt.grad.cpu().numpy()
+    rel_y = np.max(np.abs(gy - gyo)) / np.max(np.abs(gyo))
+    _say(f"  loss {loss.item():.10e} vs {lo:.10e}; dh2 {h2t.grad.item():.10e} vs {gho:.10e}; dl/dy rel {rel_y:.2e}")
+    assert abs(loss.item() - lo) < 1e-10 * lo
+    assert rel_y < 1e-8
+    assert abs(h2t.grad.item() - gho) < 1e-8 * abs(gho)

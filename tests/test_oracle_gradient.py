@@ -66,3 +66,18 @@ def test_generic_cotangents_match_differences():
     v = rng.standard_normal(y.shape[0])
     fdy = (loss(M, y + d * v) - loss(M, y - d * v)) / (2 * d)
     assert abs(gy @ v - fdy) < 1e-6 * max(1.0, abs(fdy))
+
+
+def test_contracted_gradient_equals_dense():
+    """The batched form used at n = 10^4 reproduces the dense-dl/dM oracle."""
+    from oracle import gradient as og
+    n, p, m, seed = 240, 4, 60, 9
+    Z = synth.background_genotypes(n, seed, k=300)
+    Phi = Z @ Z.T / Z.shape[1]
+    prob = synth.make_problem(n, p, seed, k=300)
+    XR = synth.snp_block(n, seed, 0, m)
+    l0, gy0, gh0 = og.wald_gradient(Phi, 1.3, 0.41, prob["XL"], prob["Y"][:, 0], XR)
+    l1, gy1, gh1 = og.wald_gradient_contracted(Phi, 1.3, 0.41, prob["XL"], prob["Y"][:, 0], XR)
+    assert abs(l1 - l0) <= 1e-11 * abs(l0)
+    assert np.max(np.abs(gy1 - gy0)) <= 1e-10 * np.max(np.abs(gy0))
+    assert abs(gh1 - gh0) <= 1e-10 * abs(gh0)
