@@ -62,8 +62,9 @@ def measured_traffic(leg, workload_name):
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None, "kernel changed since the counters were taken"
-    return rec["traffic_bytes"], (f"FETCH_SIZE+WRITE_SIZE per {rec['columns_per_launch']}-SNP launch, "
-                                  f"calibrated on a plain copy kernel; algorithmic {rec['algorithmic_bytes']:.3g} B")
+    return rec["traffic_bytes_per_launch"], (
+        f"FETCH_SIZE+WRITE_SIZE per launch over the {rec['launches']} launches of one step, calibrated on a "
+        f"plain element-wise kernel; algorithmic {rec['algorithmic_bytes_per_launch']:.3g} B per launch")
 
 
 def cpu_baseline(workload, seed, n_s, m_s, threads):
