@@ -134,8 +134,10 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     if (e0 < 0) return;
     const int I = e0 & SCHED_ROW_MASK;
     // grouped launches carry one argument set per context; the schedule
-    // entry names the context in its high bits
-    const TrmmArgs& a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+    // entry names the context in its high bits.  The set is copied into
+    // registers once: read through a reference, every field would be loaded
+    // again after each barrier (a barrier is a memory fence).
+    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
 
     __shared__ __attribute__((aligned(16))) char As[2][TM * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
@@ -400,8 +402,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
     if (e0 < 0) return;
     const int I = e0 & SCHED_ROW_MASK;
     // grouped launches carry one argument set per context; the schedule
-    // entry names the context in its high bits
-    const TrmmArgs& a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+    // entry names the context in its high bits.  The set is copied into
+    // registers once: read through a reference, every field would be loaded
+    // again after each barrier (a barrier is a memory fence).
+    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
 
     __shared__ __attribute__((aligned(16))) char As[2][TMS * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
