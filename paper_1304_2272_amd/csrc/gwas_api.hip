@@ -33,7 +33,7 @@ struct Layout {
     int p, t, q1, Qc, precision, x_dtype, slices;
     size_t off_L, off_U, off_Ulow, off_rscale, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
-    size_t off_xbuf[2], off_part, off_xw, off_b[2], off_v[2], off_i[2];
+    size_t off_xbuf[2], off_part, off_red, off_xw, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
     size_t sched_len;
     size_t total;
@@ -114,6 +114,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_xbuf[0] = rtake((size_t)L.n_pad * L.dev_block * elem);
     L.off_xbuf[1] = rtake((size_t)L.n_pad * L.dev_block * elem);
     L.off_part = rtake((size_t)L.npb_max * L.Q * L.dev_block * 8);
+    L.off_red = rtake((size_t)chunks_of(L.npb_max) * L.Q * L.dev_block * 8);
     L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
     for (int s = 0; s < 2; ++s) {
         L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
@@ -149,6 +150,7 @@ struct gwas_ctx {
     int cfg = 0;
     char* xbuf[2] = {nullptr, nullptr};
     double* part = nullptr;
+    double* red = nullptr;          // chunk totals of part
     double* xw = nullptr;
     double* bbuf[2] = {nullptr, nullptr};
     double* vbuf[2] = {nullptr, nullptr};
@@ -174,7 +176,7 @@ struct gwas_ctx {
 // W_L^T W_L and W_L^T w_y, per-sub-block scratch and the accumulators.
 struct Back {
     char* mem = nullptr;
-    double *Minv = nullptr, *W = nullptr, *GW = nullptr, *part = nullptr, *xw = nullptr,
+    double *Minv = nullptr, *W = nullptr, *GW = nullptr, *part = nullptr, *red = nullptr, *xw = nullptr,
            *contrib = nullptr, *coef = nullptr, *g = nullptr, *acc = nullptr, *v = nullptr,
            *gy = nullptr, *sb = nullptr, *sv = nullptr, *sgb = nullptr, *sgv = nullptr;
     int* si = nullptr;
@@ -386,9 +388,9 @@ SolveArgs solve_args_for(const gwas_ctx* c, int64_t cols, double* bo, int64_t ld
     sa.p = Y.p;
     sa.t = Y.t;
     sa.cols = cols;
-    sa.part = c->part;
+    sa.part = c->red;   // chunk totals of the partial sums
     sa.ldp = Y.dev_block;
-    sa.npb = Y.n_pad / c->shape.part_rows;
+    sa.npb = chunks_of(Y.n_pad / c->shape.part_rows);
     sa.Q = Y.Q;
     sa.xw = c->xw;
     sa.ldxw = Y.dev_block;
@@ -413,6 +415,9 @@ hipError_t finish_sub(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t 
                                    Y.n_pad, Y.Qc, c->xw, Y.dev_block, s);
         if (e != hipSuccess) return e;
     }
+    hipError_t e = partial_chunks(c->part, Y.dev_block, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
+                                  PART_CHUNK, c->red, Y.dev_block, s);
+    if (e != hipSuccess) return e;
     return snp_solve(solve_args_for(c, cols, bo, ldbo, vo, io), s);
 }
 
@@ -560,6 +565,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         c->ibuf[s] = (int*)(w + Y.off_i[s]);
     }
     c->part = (double*)(w + Y.off_part);
+    c->red = (double*)(w + Y.off_red);
     c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
     c->tmp = (double*)(w + Y.off_tmp);
 
@@ -1000,7 +1006,8 @@ int gwas_backward_begin(gwas_ctx* c) {
         size_t o = 0;
         std::vector<std::pair<double**, size_t>> parts = {
             {&B->Minv, (size_t)np * np}, {&B->W, (size_t)np * p}, {&B->GW, (size_t)(p - 1) * p},
-            {&B->part, (size_t)B->npb * (p + 1) * blk}, {&B->xw, (size_t)p * blk},
+            {&B->part, (size_t)B->npb * (p + 1) * blk}, {&B->red, (size_t)chunks_of(B->npb) * (p + 1) * blk},
+            {&B->xw, (size_t)p * blk},
             {&B->contrib, (size_t)(p + 1) * blk}, {&B->coef, (size_t)blk}, {&B->g, (size_t)np},
             {&B->acc, (size_t)(p + 1)}, {&B->v, (size_t)np}, {&B->gy, (size_t)np},
             {&B->sb, (size_t)p * blk}, {&B->sv, (size_t)blk}, {&B->sgb, (size_t)p * blk},
@@ -1113,12 +1120,13 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
         ta.full_k = 1;
         HIPCHK(c, trmm_stream(ta, s));
         HIPCHK(c, snp_cross_w(xt, xptr, xld, Y.n, cols, B->W, Y.n_pad, p, B->xw, blk, s));
+        HIPCHK(c, partial_chunks(B->part, blk, Y.n_pad / sh.part_rows, p + 1, cols, PART_CHUNK, B->red, blk, s));
         BackArgs ba{};
         ba.p = p;
         ba.cols = cols;
-        ba.part = B->part;
+        ba.part = B->red;   // chunk totals of the partial sums
         ba.ldp = blk;
-        ba.npb = Y.n_pad / sh.part_rows;
+        ba.npb = chunks_of(Y.n_pad / sh.part_rows);
         ba.xw = B->xw;
         ba.ldxw = blk;
         ba.consts = c->consts;

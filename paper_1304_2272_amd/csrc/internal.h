@@ -155,6 +155,15 @@ struct BackArgs {
 };
 hipError_t snp_backward(const BackArgs& a, hipStream_t s);
 
+// Partial sums of the triangular product reduced in chunks of `chunk`
+// slices: out[(g*Q + q)*ldo + j] = sum over pb in chunk g (ascending) of
+// part[(pb*Q + q)*ldp + j], for g < ceil(npb / chunk).  The per-SNP kernels
+// then sum the few chunk totals; the order depends on npb (n) alone.
+constexpr int PART_CHUNK = 32;
+hipError_t partial_chunks(const double* part, int64_t ldp, int64_t npb, int Q, int64_t cols, int chunk,
+                          double* out, int64_t ldo, hipStream_t s);
+inline int64_t chunks_of(int64_t npb) { return (npb + PART_CHUNK - 1) / PART_CHUNK; }
+
 // acc[k] += sum_j contrib[k*ldc + j] for k < rows (fixed summation order).
 hipError_t sum_columns(const double* contrib, int64_t ldc, int rows, int64_t cols, double* acc,
                        hipStream_t s);

@@ -832,6 +832,24 @@ __global__ __launch_bounds__(128) void snp_backward_kernel(BackArgs a) {
     (void)xwy;
 }
 
+// out[(g * Q + q) * ldo + j] = sum of part[(pb * Q + q) * ldp + j] over the
+// chunk pb in [g * chunk, min((g + 1) * chunk, npb)), in ascending pb: one
+// thread per (chunk, row, SNP), SNP fastest for coalesced loads.
+__global__ __launch_bounds__(256) void partial_chunks_kernel(const double* __restrict__ part, int64_t ldp,
+                                                             int64_t npb, int Q, int64_t cols, int chunk,
+                                                             int64_t G, double* __restrict__ out,
+                                                             int64_t ldo) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= cols * Q * G) return;
+    const int64_t j = id % cols;
+    const int64_t q = (id / cols) % Q;
+    const int64_t g = id / (cols * Q);
+    const int64_t pb1 = std::min<int64_t>(npb, (g + 1) * chunk);
+    double acc = 0.0;
+    for (int64_t pb = g * chunk; pb < pb1; ++pb) acc += part[(pb * Q + q) * ldp + j];
+    out[(g * Q + q) * ldo + j] = acc;
+}
+
 __global__ __launch_bounds__(256) void sum_columns_kernel(const double* __restrict__ c, int64_t ldc,
                                                           int64_t cols, double* __restrict__ acc) {
     __shared__ double red[256];
@@ -1070,6 +1088,17 @@ hipError_t sum_columns(const double* contrib, int64_t ldc, int rows, int64_t col
     if (cols <= 0 || rows <= 0) return hipSuccess;
     if (!contrib || !acc || ldc < cols) return hipErrorInvalidValue;
     hipLaunchKernelGGL(sum_columns_kernel, dim3(rows), dim3(256), 0, s, contrib, ldc, cols, acc);
+    return hipGetLastError();
+}
+
+hipError_t partial_chunks(const double* part, int64_t ldp, int64_t npb, int Q, int64_t cols, int chunk,
+                          double* out, int64_t ldo, hipStream_t s) {
+    if (cols <= 0) return hipSuccess;
+    if (!part || !out || npb < 1 || Q < 1 || chunk < 1 || ldp < cols || ldo < cols) return hipErrorInvalidValue;
+    const int64_t G = (npb + chunk - 1) / chunk;
+    const int64_t threads = cols * Q * G;
+    hipLaunchKernelGGL(partial_chunks_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, part, ldp,
+                       npb, Q, cols, chunk, G, out, ldo);
     return hipGetLastError();
 }
 
