@@ -56,7 +56,7 @@ def measured_traffic(leg, workload_name):
     rocprofv3 counter summary, or None once the kernel source has changed."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"trmm_{leg}_{workload_name}_traffic.json")
-    src = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "stream_kernels.hip")
+    src = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "trmm_kernels.hip")
     if not os.path.exists(path):
         return None, None
     rec = json.load(open(path))

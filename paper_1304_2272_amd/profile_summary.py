@@ -28,7 +28,7 @@ import json
 import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STREAM_SRC = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "stream_kernels.hip")
+STREAM_SRC = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "trmm_kernels.hip")
 
 
 def _per_dispatch(path, counter):
