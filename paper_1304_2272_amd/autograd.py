@@ -2,11 +2,12 @@
 
 ``GwasGLS.apply(y, h2, Phi, XL, XR, sigma2, options)`` returns (b, var) for
 every SNP row of XR under M = sigma2 (h2 Phi + (1 - h2) I), and its backward
-gives dl/dy and dl/dh2 for any scalar loss l built from b and var with torch.
-The covariance is assembled with torch (input marshalling); every step of the
-GLS solves and of their reverse pass runs in the HIP library.  dl/dh2 uses
-dM/dh2 = sigma2 (Phi - I) = (M - sigma2 I) / h2, so the library only needs
-the contractions <Mbar, M> and tr Mbar.  One trait (y is an n-vector).
+gives dl/dy, dl/dh2 and (when sigma2 is a tensor) dl/dsigma2 for any scalar
+loss l built from b and var with torch.  The covariance is assembled with
+torch (input marshalling); every step of the GLS solves and of their reverse
+pass runs in the HIP library.  With dM/dh2 = sigma2 (Phi - I) =
+(M - sigma2 I) / h2 (h2 > 0) and dM/dsigma2 = M / sigma2 the library only
+needs the contractions <Mbar, M> and tr Mbar.  One trait (y is an n-vector).
 """
 
 from __future__ import annotations
@@ -22,6 +23,10 @@ class GwasGLS(torch.autograd.Function):
         opts = dict(options or {})
         n = Phi.shape[0]
         h = float(h2)
+        if not h > 0.0:
+            raise ValueError("the reverse pass needs h2 > 0")
+        ctx.sigma2_is_tensor = torch.is_tensor(sigma2)
+        sigma2 = float(sigma2)
         M = Phi * (sigma2 * h)
         M.diagonal().add_(sigma2 * (1.0 - h))
         g = binding.GwasContext(M, XL, y.detach().reshape(n, 1), **opts)
@@ -47,6 +52,9 @@ class GwasGLS(torch.autograd.Function):
         gy = torch.empty(g.n, dtype=torch.float64, device=b.device)
         gy, tr, ip = g.backward_end(gy)
         dh2 = (ip - ctx.sigma2 * tr) / ctx.h2
+        dsigma2 = ip / ctx.sigma2
         g.close()
         ctx.g = None
-        return gy, torch.tensor(dh2, dtype=torch.float64, device=b.device), None, None, None, None, None
+        f64 = dict(dtype=torch.float64, device=b.device)
+        return (gy, torch.tensor(dh2, **f64), None, None, None,
+                torch.tensor(dsigma2, **f64) if ctx.sigma2_is_tensor else None, None)

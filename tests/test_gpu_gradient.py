@@ -57,16 +57,20 @@ def test_autograd_wald_loss_vs_oracle():
     dev = torch.device("cuda:0")
     yt = torch.tensor(y, device=dev, requires_grad=True)
     h2t = torch.tensor(h2, dtype=torch.float64, device=dev, requires_grad=True)
+    s2t = torch.tensor(s2, dtype=torch.float64, device=dev, requires_grad=True)
     b, var = GwasGLS.apply(yt, h2t, torch.tensor(Phi, device=dev), torch.tensor(XL, device=dev),
-                           torch.tensor(XR, device=dev), s2, {"dev_block": 512})
+                           torch.tensor(XR, device=dev), s2t, {"dev_block": 512})
     loss = (b[:, -1] ** 2 / var).sum()
     loss.backward()
     lo, gyo, gho = og.wald_gradient(Phi, s2, h2, XL, y, XR)
     gy = yt.grad.cpu().numpy()
-    _say(f"  loss {loss.item():.10e} vs {lo:.10e}; dh2 {h2t.grad.item():.10e} vs {gho:.10e}")
+    _say(f"  loss {loss.item():.10e} vs {lo:.10e}; dh2 {h2t.grad.item():.10e} vs {gho:.10e}; "
+         f"dsigma2 {s2t.grad.item():.10e} vs -loss/sigma2 {-lo / s2:.10e}")
     assert abs(loss.item() - lo) < 1e-10 * lo
     assert np.max(np.abs(gy - gyo)) < 1e-8 * np.max(np.abs(gyo))
     assert abs(h2t.grad.item() - gho) < 1e-8 * abs(gho)
+    # b does not depend on sigma2 and var scales with it: dl/dsigma2 = -l / sigma2
+    assert abs(s2t.grad.item() + lo / s2) < 1e-9 * abs(lo / s2)
 
 
 @pytest.mark.slow

@@ -81,3 +81,15 @@ def test_contracted_gradient_equals_dense():
     assert abs(l1 - l0) <= 1e-11 * abs(l0)
     assert np.max(np.abs(gy1 - gy0)) <= 1e-10 * np.max(np.abs(gy0))
     assert abs(gh1 - gh0) <= 1e-10 * abs(gh0)
+
+
+def test_scale_of_M_closed_form():
+    """b does not change when M is scaled and var scales with it, so the
+    Wald loss is l(c M) = l(M) / c and <dl/dM, M> = d l(c M)/dc at c = 1 = -l."""
+    Phi, s2, h2, XL, y, XR = _case(seed=11)
+    M = og.model_covariance(Phi, s2, h2)
+    b, var, _ = og.GLSOracle(M, XL, y).solve(XR)
+    gb, gv = og.wald_loss_cotangents(b, var)
+    _, Mbar = og.reverse(M, XL, y, XR, gb, gv)
+    loss = og.wald_loss(M, XL, y, XR)
+    assert abs(np.sum(Mbar * M) + loss) < 1e-9 * loss
