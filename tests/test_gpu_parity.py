@@ -65,6 +65,28 @@ def test_ragged_shapes(x_dtype, n, p, m, dev_block):
     assert err < TOL_FP64
 
 
+@pytest.mark.parametrize("n,p,m,dev_block", [(777, 3, 1500, 256), (130, 5, 300, 128),
+                                               (4, 4, 37, 128), (1283, 20, 400, 384), (2049, 4, 531, 512)])
+def test_ragged_shapes_int8_slices(n, p, m, dev_block):
+    # interior stages stream straight to LDS; the last column tile of a
+    # sub-block and the stages crossing n take the zero-filled edge path
+    seed = 17 + n
+    _say(f"ragged int8 slices n={n} p={p} m={m} dev_block={dev_block}")
+    prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    b, var, info = run(prob, XR, precision="int8", x_dtype="i8", dev_block=dev_block)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    ok = io == 0
+    assert np.array_equal(info, io)
+    err = normwise(b[ok], bo[ok])
+    _say(f"  err {err:.3e}")
+    # tiny n (n = p) cancels most of S_BR in s = S_BR - u^T u, which
+    # magnifies the slices' 1e-14 truncation; a misplaced chunk or row
+    # would be off by O(1).  The mixed-precision bar applies here; the
+    # float64-level check of the slices is test_int8_slices.
+    assert err < 1e-8
+
+
 def test_partition_independence_and_device_io():
     import torch
     n, p, m, seed = 900, 4, 2000, 31
