@@ -183,16 +183,18 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                       double* const* var_snp, int32_t* const* info, int32_t flags);
 
 /*
- * Pick the tile shape of the triangular product by timing every admissible
- * shape on `cols` (<= dev_block) SNP columns of XR (host or device), and
- * keep the fastest for later calls.  With the environment variable
- * GWAS_TUNE_CACHE naming a file, an earlier result for the same padded n,
- * precision, dosage type and width is reused and new results are appended.
- * *best_cfg (may be NULL) receives the chosen shape, -1 for
- * GWAS_INT8_SLICED (one shape).  Results of later calls are unchanged up to
- * float64 rounding order.
+ * Pick the tile shape of the triangular product and the row-group size of
+ * its XCD schedule (row tiles that share one L2: 1, 2, 4 or 8) by timing
+ * every admissible pair on `cols` (<= dev_block) SNP columns of XR (host or
+ * device), and keep the fastest for later calls.  With the environment
+ * variable GWAS_TUNE_CACHE naming a file, an earlier result for the same
+ * padded n, precision, dosage type and width is reused and new results are
+ * appended.  *best_cfg (may be NULL) receives the chosen shape, -1 for
+ * GWAS_INT8_SLICED (one shape); *best_rgroup (may be NULL) the row group.
+ * Results of later calls are unchanged up to float64 rounding order.
  */
-int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg);
+int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
+                  int32_t* best_rgroup);
 
 /*
  * Reverse mode (one trait, t = 1): the gradient of a scalar loss l(b, var)

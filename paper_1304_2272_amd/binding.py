@@ -102,7 +102,7 @@ def load():
                                     ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                     ctypes.POINTER(vp), i32]
     L.gwas_autotune.restype = ctypes.c_int
-    L.gwas_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32)]
+    L.gwas_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.gwas_backward_begin.restype = ctypes.c_int
     L.gwas_backward_begin.argtypes = [vp]
     L.gwas_backward_block.restype = ctypes.c_int
@@ -251,14 +251,15 @@ class GwasContext:
         return np.empty((m, self.t, self.p)), np.empty(m), np.empty(m, dtype=np.int32)
 
     def autotune(self, XR, cols=None):
-        """Time every tile shape on the first ``cols`` SNPs of XR; keep the fastest."""
+        """Time every tile shape and schedule row group on the first ``cols``
+        SNPs of XR; keep the fastest.  Returns (shape, row group)."""
         xdt = np.int8 if self.x_dtype == "i8" else np.float64
         xp, ldx, keep, _ = _ptr_ld(XR, xdt, "XR")
         cols = XR.shape[0] if cols is None else cols
-        best = ctypes.c_int32()
-        self._check(self._lib.gwas_autotune(self._h, xp, ldx, cols, ctypes.byref(best)))
+        best, rg = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.gwas_autotune(self._h, xp, ldx, cols, ctypes.byref(best), ctypes.byref(rg)))
         del keep
-        return best.value
+        return best.value, rg.value
 
     def backward_begin(self):
         """Start a reverse pass (forms M^-1 and W on the first call)."""

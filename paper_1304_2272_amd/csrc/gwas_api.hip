@@ -95,14 +95,13 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     // the reverse pass runs the float64 product with its default shape
     L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
                                             trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0));
-    if (at == A_I8S) {
-        const TrmmShape sh = trmm_geom(at, xt, 0, slices);
-        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
-    }
-    for (int c = 0; c < trmm_num_cfgs() && at != A_I8S; ++c) {
-        if (!trmm_cfg_valid(at, xt, c)) continue;
-        const TrmmShape sh = trmm_geom(at, xt, c, slices);
-        L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
+    // every admissible shape with the model's and every candidate row group
+    for (int c = 0; c < trmm_num_cfgs(); ++c) {
+        if (at == A_I8S ? c > 0 : !trmm_cfg_valid(at, xt, c)) continue;
+        for (int r : {0, 1, 2, 4, 8}) {
+            const TrmmShape sh = trmm_geom(at, xt, c, slices, r);
+            L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
+        }
     }
     L.off_sched = take(L.sched_len * 2 * 4);
     L.off_sched_tail = take(L.sched_len * 2 * 4);
@@ -148,6 +147,7 @@ struct gwas_ctx {
     int64_t tail_cols = -1;
     int at = A_F64;
     int cfg = 0;
+    int rgroup = 0;                 // schedule row group (0: the traffic model's choice)
     char* xbuf[2] = {nullptr, nullptr};
     double* part = nullptr;
     double* red = nullptr;          // chunk totals of part
@@ -378,6 +378,7 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.part = c->part;
     ta.ldp = Y.dev_block;
     ta.sched = c->sched;
+    ta.rgroup = c->rgroup;
     ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape);
     return ta;
 }
@@ -903,15 +904,12 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
     return GWAS_OK;
 }
 
-int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg) {
+int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
+                  int32_t* best_rgroup) {
     if (!live(c)) return GWAS_E_STATE;
     const Layout& Y = c->lay;
     if (!XR || ldx < Y.n || cols < 1) return GWAS_E_INVALID;
     cols = std::min<int64_t>(cols, Y.dev_block);
-    if (c->at == A_I8S) {   // one tile shape
-        if (best_cfg) *best_cfg = -1;
-        return GWAS_OK;
-    }
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, join_user(c, c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
@@ -920,21 +918,23 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     char keyline[160];
     snprintf(keyline, sizeof(keyline), "gfx950 n_pad=%lld precision=%d x_dtype=%d cols=%lld",
              (long long)Y.n_pad, Y.precision, Y.x_dtype, (long long)cols);
-    int best = -1;
+    int best = -1, best_rg = 0;
     if (cache) {
         if (FILE* f = fopen(cache, "r")) {
             char line[256];
             while (fgets(line, sizeof(line), f)) {
                 const size_t kl = strlen(keyline);
-                int v = -1;
-                if (strncmp(line, keyline, kl) == 0 && sscanf(line + kl, " cfg=%d", &v) == 1 &&
-                    trmm_cfg_valid(c->at, xt, v))
+                int v = -1, r = 0;
+                if (strncmp(line, keyline, kl) == 0 && sscanf(line + kl, " cfg=%d rgroup=%d", &v, &r) == 2 &&
+                    (c->at == A_I8S ? v == -1 : trmm_cfg_valid(c->at, xt, v)) && r >= 1 && r <= 32) {
                     best = v;
+                    best_rg = r;
+                }
             }
             fclose(f);
         }
     }
-    if (best < 0) {
+    if (best_rg == 0) {
         const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
         const void* xptr = XR;
         int64_t xld = ldx;
@@ -947,41 +947,49 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
         float best_ms = 0.f;
-        for (int cfg = 0; cfg < trmm_num_cfgs(); ++cfg) {
-            if (!trmm_cfg_valid(c->at, xt, cfg)) continue;
-            c->cfg = cfg;
-            c->shape = trmm_geom(c->at, xt, cfg, Y.slices);
-            int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
-            if (rc) return rc;
-            TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
-            ta.sched = c->sched_tail;
-            HIPCHK(c, trmm_stream(ta, c->s_comp));                  // warm-up
-            HIPCHK(c, hipEventRecord(e0, c->s_comp));
-            HIPCHK(c, trmm_stream(ta, c->s_comp));
-            HIPCHK(c, hipEventRecord(e1, c->s_comp));
-            HIPCHK(c, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (best < 0 || ms < best_ms) {
-                best = cfg;
-                best_ms = ms;
+        // every admissible tile shape (the int8-slice product has one) with
+        // every candidate row group of the schedule
+        for (int cfg = (c->at == A_I8S ? -1 : 0); cfg < (c->at == A_I8S ? 0 : trmm_num_cfgs()); ++cfg) {
+            if (c->at != A_I8S && !trmm_cfg_valid(c->at, xt, cfg)) continue;
+            for (int rg : RGROUP_CANDIDATES) {
+                c->cfg = cfg < 0 ? 0 : cfg;
+                c->rgroup = rg;
+                c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, rg);
+                int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
+                if (rc) return rc;
+                TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
+                ta.sched = c->sched_tail;
+                HIPCHK(c, trmm_stream(ta, c->s_comp));                  // warm-up
+                HIPCHK(c, hipEventRecord(e0, c->s_comp));
+                HIPCHK(c, trmm_stream(ta, c->s_comp));
+                HIPCHK(c, hipEventRecord(e1, c->s_comp));
+                HIPCHK(c, hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                if (best_rg == 0 || ms < best_ms) {
+                    best = cfg;
+                    best_rg = rg;
+                    best_ms = ms;
+                }
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (cache) {
             if (FILE* f = fopen(cache, "a")) {
-                fprintf(f, "%s cfg=%d ms=%.3f\n", keyline, best, best_ms);
+                fprintf(f, "%s cfg=%d rgroup=%d ms=%.3f\n", keyline, best, best_rg, best_ms);
                 fclose(f);
             }
         }
     }
-    c->cfg = best;
-    c->shape = trmm_geom(c->at, xt, best, Y.slices);
+    c->cfg = best < 0 ? 0 : best;
+    c->rgroup = best_rg;
+    c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, best_rg);
     c->tail_cols = -1;
     int rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    if (best_rgroup) *best_rgroup = best_rg;
     if (best_cfg) *best_cfg = best;
     return GWAS_OK;
 }

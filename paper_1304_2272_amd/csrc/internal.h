@@ -100,6 +100,7 @@ struct TrmmArgs {
     double* part; int64_t ldp;
     const int* sched; int64_t n_sched;
     int full_k;                 // A is a full (not lower-triangular) n_pad x n_pad matrix
+    int rgroup;                 // row tiles per L2 group of the schedule (0: the model's choice)
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
@@ -110,8 +111,10 @@ bool trmm_cfg_valid(int at, int xt, int cfg);
 int trmm_default_cfg(int at, int xt);
 constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of the floating-point shapes
 TrmmShape trmm_sliced_shape();       // tile of the int8-slice product (part_rows 16)
-// shape of the kernel that runs (at, xt, cfg, slices), with its schedule grouping
-TrmmShape trmm_geom(int at, int xt, int cfg, int slices);
+// shape of the kernel that runs (at, xt, cfg, slices), with its schedule
+// grouping: rgroup row tiles per group, or the traffic model's choice for 0
+TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup = 0);
+constexpr int RGROUP_CANDIDATES[] = {1, 2, 4, 8};   // what the autotuner tries
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
 // and S int8 slices A_s(r,k) with L^-1(r,k)/rscale[r] = sum_s A_s(r,k) 2^(-6-7s)

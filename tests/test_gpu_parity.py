@@ -17,6 +17,10 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def torch_equal(x, y):
+    return bool(np.array_equal(np.asarray(x), np.asarray(y)))
+
+
 def normwise(b, bref):
     num = np.linalg.norm((b - bref).reshape(b.shape[0], -1), axis=1)
     den = np.linalg.norm(bref.reshape(b.shape[0], -1), axis=1)
@@ -282,19 +286,21 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
     bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("GWAS_TUNE_CACHE", str(cache))
-    for precision, tol in [("fp64", TOL_FP64), ("fp32", TOL_FP32)]:
+    for precision, tol in [("fp64", TOL_FP64), ("fp32", TOL_FP32), ("int8", TOL_FP64)]:
         with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
                                  dev_block=1024) as ctx:
             best = ctx.autotune(XR, 1024)
-            _say(f"autotune {precision}: tile shape {best}")
-            assert best in TILE_SHAPES[precision]
+            _say(f"autotune {precision}: tile shape {best[0]}, row group {best[1]}")
+            assert best[0] in TILE_SHAPES.get(precision, [-1]) and best[1] in (1, 2, 4, 8)
             b, _, _ = ctx.stream_block(XR)
             assert normwise(b, bo) < tol
         with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
                                  dev_block=1024) as ctx:
             assert ctx.autotune(XR, 1024) == best          # read back from the cache
+            b2, _, _ = ctx.stream_block(XR)
+            assert torch_equal(b, b2)                      # same shape and schedule: same bits
     lines = cache.read_text().splitlines()
-    assert len(lines) == 2 and all("cfg=" in ln for ln in lines)
+    assert len(lines) == 3 and all("cfg=" in ln and "rgroup=" in ln for ln in lines)
 
 
 def test_many_traits():
