@@ -32,6 +32,8 @@
  *     exception crosses this interface.  Every call that takes a context
  *     returns GWAS_E_STATE for a NULL, freed or poisoned context.
  *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Calls switch to the context's device while they run and restore the
+ *     caller's current device before they return.
  */
 #ifndef GWAS_H
 #define GWAS_H

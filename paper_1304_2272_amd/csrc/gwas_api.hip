@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <string>
 #include <vector>
@@ -129,8 +130,14 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
 
 }  // namespace
 
+// Serial number of each context, never reused in a process: grouped-launch
+// state (schedules, captured graphs) is keyed by these, not by addresses a
+// freed context's successor could take over.
+static std::atomic<uint64_t> next_ctx_id{1};
+
 struct gwas_ctx {
     uint64_t magic = CTX_MAGIC;
+    uint64_t id = next_ctx_id.fetch_add(1);
     bool poisoned = false;
     int device = 0;
     Layout lay{};
@@ -188,7 +195,7 @@ struct Back {
 // context: the combined tile schedule, per-context kernel arguments (pinned
 // host and device copies, double buffered) and an optional captured graph.
 struct Group {
-    std::vector<const gwas_ctx*> key;
+    std::vector<uint64_t> key;      // ids of the contexts the schedule was built for
     int64_t sched_cols = -1;
     int* d_sched = nullptr;
     size_t sched_cap = 0;
@@ -198,7 +205,7 @@ struct Group {
     std::vector<int> host_sched;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<const gwas_ctx*> graph_key;
+    std::vector<uint64_t> graph_key;  // ids of the contexts the graph was captured for
     // the graph's own argument array and schedule, never rewritten after capture
     TrmmArgs* h_args_graph = nullptr;
     TrmmArgs* d_args_graph = nullptr;
@@ -222,6 +229,20 @@ int fail_hip(gwas_ctx* c, hipError_t e, const char* what) {
     } while (0)
 
 bool live(const gwas_ctx* c) { return c && c->magic == CTX_MAGIC && !c->poisoned; }
+
+// The caller's current device is restored when an entry point returns.
+struct DeviceScope {
+    int prev = -1;
+    DeviceScope() {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            (void)hipGetLastError();
+            prev = -1;
+        }
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // make `s` wait for everything the caller queued on its own stream so far
 hipError_t join_user(gwas_ctx* c, hipStream_t s) {
@@ -534,6 +555,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         delete c;
         return code;
     };
+    DeviceScope scope;
     if (hipSetDevice(d->device) != hipSuccess) return bail(GWAS_E_NO_DEVICE);
     if (d->workspace) {
         if (d->workspace_bytes < Y.total) return bail(GWAS_E_WORKSPACE);
@@ -605,6 +627,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     if (mblk < 0) return GWAS_E_INVALID;
     if (mblk == 0) return GWAS_OK;
     if (!XR || !b || ldx < Y.n || ldb < (int64_t)Y.p * Y.t) return GWAS_E_INVALID;
+    DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
 
     HIPCHK(c, join_user(c, c->s_comp));
@@ -723,6 +746,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
             if (ctxs[j] == c) return GWAS_E_INVALID;
     }
     if (mblk == 0) return GWAS_OK;
+    DeviceScope scope;
     HIPCHK(c0, hipSetDevice(c0->device));
     if (!c0->grp) c0->grp = new (std::nothrow) Group();
     Group* g = c0->grp;
@@ -732,7 +756,8 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         if (!g->d_args[sl]) HIPCHK(c0, hipMalloc((void**)&g->d_args[sl], MAX_GROUP * sizeof(TrmmArgs)));
     }
     std::vector<gwas_ctx*> cs(ctxs, ctxs + nctx);
-    std::vector<const gwas_ctx*> key(cs.begin(), cs.end());
+    std::vector<uint64_t> key;
+    for (const gwas_ctx* c : cs) key.push_back(c->id);
     hipStream_t s = c0->s_comp;
     for (int i = 0; i < nctx; ++i) HIPCHK(c0, join_user(cs[i], s));
     const int64_t blk = c0->lay.dev_block;
@@ -910,6 +935,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     const Layout& Y = c->lay;
     if (!XR || ldx < Y.n || cols < 1) return GWAS_E_INVALID;
     cols = std::min<int64_t>(cols, Y.dev_block);
+    DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, join_user(c, c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
@@ -998,6 +1024,7 @@ int gwas_backward_begin(gwas_ctx* c) {
     if (!live(c)) return GWAS_E_STATE;
     const Layout& Y = c->lay;
     if (Y.t != 1) return GWAS_E_INVALID;
+    DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = c->s_comp;
     if (!c->back) {
@@ -1068,6 +1095,7 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
         ldgb < p)
         return GWAS_E_INVALID;
     if (mblk == 0) return GWAS_OK;
+    DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
     Back* B = c->back;
     hipStream_t s = c->s_comp;
@@ -1164,6 +1192,7 @@ int gwas_backward_end(gwas_ctx* c, double* gy, double* tr_mbar, double* ip_mbar_
     const Layout& Y = c->lay;
     Back* B = c->back;
     hipStream_t s = c->s_comp;
+    DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, join_user(c, s));
     const int p = Y.p;
@@ -1186,6 +1215,7 @@ int gwas_backward_end(gwas_ctx* c, double* gy, double* tr_mbar, double* ip_mbar_
 int gwas_free(gwas_ctx* c) {
     if (!c) return GWAS_OK;
     if (c->magic != CTX_MAGIC) return GWAS_E_STATE;
+    DeviceScope scope;
     (void)hipSetDevice(c->device);
     release(c);
     c->magic = CTX_DEAD;
