@@ -279,6 +279,35 @@ def test_group_graph_replays_match_eager():
             c.close()
 
 
+def test_group_graph_after_a_member_is_replaced():
+    # A captured group graph must not be replayed for a new context, even one
+    # created at the freed member's address: the new member's buffers differ.
+    import torch
+    dev = torch.device("cuda:0")
+    blk, m = 256, 512
+    probs, ctxs = _cohort_contexts("fp64", dev_block=blk)
+    try:
+        XRs = [synth.snp_block_device(pr["n"], 21, 0, m, dev, cohort=i) for i, pr in enumerate(probs)]
+        binding.stream_group(ctxs, XRs, graph=True)
+        torch.cuda.synchronize()
+        old = ctxs[1]._h.value
+        ctxs[1].close()
+        pr = probs[1]
+        ctxs[1] = binding.GwasContext(pr["M"], pr["XL"], pr["Y"] * 2.0, x_dtype="i8", dev_block=blk)
+        _say(f"replaced member at {old:#x} by one at {ctxs[1]._h.value:#x}")
+        eager = binding.stream_group(ctxs, XRs)
+        torch.cuda.synchronize()
+        replay = binding.stream_group(ctxs, XRs, graph=True)
+        torch.cuda.synchronize()
+        for (be, ve, ie), (bg, vg, ig) in zip(eager, replay):
+            assert torch.equal(be, bg) and torch.equal(ve, vg) and torch.equal(ie, ig)
+        single = ctxs[1].stream_block(XRs[1])[0]
+        assert torch.equal(single, replay[1][0])
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_autotune_and_cache(tmp_path, monkeypatch):
     n, p, m, seed = 1500, 4, 2048, 61
     prob = synth.make_problem(n, p, seed)
