@@ -106,6 +106,7 @@ hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
 
 int trmm_num_cfgs();
+bool trmm_shape_sum32(int cfg);   // shape keeps float32 sums only (reduced precision)
 TrmmShape trmm_shape(int cfg);
 bool trmm_cfg_valid(int at, int xt, int cfg);
 int trmm_default_cfg(int at, int xt);

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace gwas {
@@ -105,8 +106,11 @@ __device__ __forceinline__ double wave_sum16(double v) {
 }
 
 // Workgroup shape: WGM x WGN waves, each wave WTM x WTN blocks of 16 x 16.
-template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_> struct Shape {
+// SUM32: the reduced-precision products keep float32 sums only, with no
+// float64 sums beside them (whose registers limit a wave to 64 x 64).
+template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_, bool SUM32_ = false> struct Shape {
     static constexpr int WGM = WGM_, WGN = WGN_, WTM = WTM_, WTN = WTN_, MINB = MINB_;
+    static constexpr bool SUM32 = SUM32_;
     static constexpr int TM = WGM * WTM * 16;     // rows of L^-1 / Z per tile
     static constexpr int TN = WGN * WTN * 16;     // SNP columns per tile
     static constexpr int NT = 64 * WGM * WGN;     // threads
@@ -122,6 +126,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     typedef MM<AT> T;
     constexpr int BK = T::BK;
     constexpr bool LOWP = sizeof(AT) < 8;
+    // reduced-precision sums move to float64 registers every FLUSH_STAGES
+    // stages unless the shape keeps float32 sums only
+    constexpr bool SUM64 = LOWP && !S::SUM32;
     constexpr int TM = S::TM, TN = S::TN, NT = S::NT, WTM = S::WTM, WTN = S::WTN;
     constexpr int A_CHUNKS = TM * (ROW_BYTES / 16);              // 16-byte chunks per stage
     constexpr int CA = (A_CHUNKS + NT - 1) / NT;
@@ -132,15 +139,17 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     constexpr int CB = (B_CHUNKS + NT - 1) / NT;
     static_assert(XB % 16 == 0, "a column stage must be whole 16-byte chunks");
 
-    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
-    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
+    // the tile coordinates are the workgroup's: scalar registers, so that
+    // every quantity derived from them (K range, addresses, loop bound) is
+    const int e0 = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x]);
+    const int J = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x + 1]);
     if (e0 < 0) return;
     const int I = e0 & SCHED_ROW_MASK;
     // grouped launches carry one argument set per context; the schedule
     // entry names the context in its high bits.  The set is copied into
     // registers once: read through a reference, every field would be loaded
     // again after each barrier (a barrier is a memory fence).
-    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+    const TrmmArgs a = GROUPED ? la.group[e0 >> SCHED_CTX_SHIFT] : la;
 
     __shared__ __attribute__((aligned(16))) char As[2][TM * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
@@ -155,23 +164,75 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     // L^-1 is lower triangular: its rows r0.. end at column r0 + TM; a full
     // matrix (M^-1 in the reverse pass) runs the whole K range
     const int64_t kend = a.full_k ? a.n_pad : std::min<int64_t>(r0 + TM, a.n_pad);
-    const int64_t nk = kend / BK;
+    // stage index: 32-bit where registers are short (SUM32 shapes)
+    typedef typename std::conditional<S::SUM32, int, int64_t>::type kidx_t;
+    const kidx_t nk = (kidx_t)(kend / BK);
     const char* Ut = reinterpret_cast<const char*>(a.Ut);
     const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
     const XT* X = reinterpret_cast<const XT*>(a.X);
 
     typename T::acc_t acc[WTM][WTN];
-    d4_t acc64[WTM][WTN];
+    d4_t acc64[SUM64 ? WTM : 1][SUM64 ? WTN : 1];
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-            acc[i][j] = typename T::acc_t{0, 0, 0, 0};
-            acc64[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-        }
+        for (int j = 0; j < WTN; ++j) acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+    if constexpr (SUM64) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) acc64[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
 
     u4_t ra[CA], rb[CB];
-    auto load = [&](int64_t kt) {
+    // Buffer loads (SUM32 shapes, whose registers are short): 32-bit
+    // offsets from a per-tile base.  L^-1 takes its chunk and stage offsets
+    // in scalar registers and never leaves the tile's rows.  The dosage
+    // offset is all in the vector operand, which the descriptor's range
+    // check covers: columns past the block read as zero (a column is whole
+    // 16-byte chunks, since ldx bytes are a multiple of 16), and elements
+    // k >= n of the last stages are cleared here.
+    constexpr bool BUF = S::SUM32;
+    __amdgpu_buffer_rsrc_t rsA, rsB;
+    int voA = 0, voB = 0;
+    if constexpr (BUF) {
+        static_assert(A_CHUNKS % NT == 0 && B_CHUNKS % NT == 0 && NT % CPC == 0, "whole chunks per lane");
+        rsA = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(Ut + r0 * row_bytes), (short)0,
+                                                (int)(TM * row_bytes), 0x00020000);
+        const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
+        rsB = __builtin_amdgcn_make_buffer_rsrc(const_cast<XT*>(X + c0 * a.ldx), (short)0,
+                                                (int)(xcols * a.ldx * (int64_t)sizeof(XT)), 0x00020000);
+        voA = (tid >> 3) * (int)row_bytes + (tid & 7) * 16;
+        voB = (tid / CPC) * (int)(a.ldx * (int64_t)sizeof(XT)) + (tid % CPC) * 16;
+    }
+    auto load_buf = [&](int kt) {
+#pragma unroll
+        for (int c = 0; c < CA; ++c)
+            ra[c] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rsA, voA, (int)(c * (NT / 8) * row_bytes + kt * ROW_BYTES), 0));
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            rb[c] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rsB, voB + (int)(c * (NT / CPC) * a.ldx * (int64_t)sizeof(XT)) + kt * XB, 0, 0));
+        if ((kt + 1) * BK > (int)a.n) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                // bytes of this chunk below n
+                const int k0 = kt * BK + ((tid + c * NT) % CPC) * EPC;
+                const int vb = std::min(16, std::max(0, ((int)a.n - k0) * (int)sizeof(XT)));
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int keep = std::min(4, std::max(0, vb - 4 * w));
+                    rb[c][w] &= keep >= 4 ? 0xffffffffu : ((1u << (8 * keep)) - 1u);
+                }
+            }
+        }
+    };
+    auto load = [&](kidx_t kt) {
+        if constexpr (BUF) {
+            load_buf(kt);
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < CA; ++c) {
             const int idx = tid + c * NT;
@@ -240,14 +301,21 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     };
 
     auto flush = [&]() {
+        if constexpr (SUM64) {
 #pragma unroll
-        for (int i = 0; i < WTM; ++i)
+            for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int j = 0; j < WTN; ++j) {
+                for (int j = 0; j < WTN; ++j) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
-                acc[i][j] = typename T::acc_t{0, 0, 0, 0};
-            }
+                    for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+                    acc[i][j] = typename T::acc_t{0, 0, 0, 0};
+                }
+        }
+    };
+    // the product's value at accumulator (i, j, v), in float64
+    auto zval = [&](int i, int j, int v) -> double {
+        if constexpr (SUM64) return acc64[i][j][v];
+        else return (double)acc[i][j][v];
     };
     // A lane's K slice of a stage (32 bytes of A and of B per 16-row block)
     // is read in NQ pieces into two alternating register sets: piece q + 1
@@ -258,9 +326,15 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     // no registers to spare).
     // 64 x 64 waves of the reduced-precision products carry float64 sums
     // besides their float32 ones; two of them per SIMD leave no registers
-    // for a second set
+    // for a second set.
+    // 64 x 128 waves (SUM32) keep the pieces of a stage inside it (a set
+    // carried over the barrier spills): float32 in 8-byte pieces with two
+    // sets, bfloat16 (whose instruction takes 16 bytes) in 16-byte pieces
+    // with one set.
     constexpr bool TIGHT = (NT / 64) * S::MINB > 4;
-    constexpr int NQ = (LOWP && TIGHT && WTM * WTN >= 16) ? 1 : T::NQ;
+    constexpr int NQ = S::SUM32 ? (sizeof(AT) == 4 ? 4 : 2)
+                                : ((SUM64 && TIGHT && WTM * WTN >= 16) ? 1 : T::NQ);
+    constexpr int SETS = (S::SUM32 && sizeof(AT) != 4) ? 1 : 2;
     constexpr int PB = NQ == 1 ? 16 : 32 / NQ;                   // bytes per piece
     constexpr int IPP = PB / (int)(sizeof(AT) * T::KPL);         // instructions per piece
     typedef typename Piece<PB>::type piece_t;
@@ -285,8 +359,36 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     load(0);
     store(0);
     __syncthreads();
-    if constexpr (NQ == 1) {
-        for (int64_t kt = 0; kt < nk; ++kt) {
+    if constexpr (S::SUM32) {
+        for (kidx_t kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) load(kt + 1);
+            piece_t pa[SETS][WTM], pb[SETS][WTN];
+            read_piece(buf, 0, pa[0], pb[0]);
+            // piece 0's reads stay apart from piece 1's (not merged into
+            // wider reads), so its first instructions wait for their own
+            // operands only
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if constexpr (SETS == 2) {
+                    if (q + 1 < NQ) read_piece(buf, q + 1, pa[(q + 1) & 1], pb[(q + 1) & 1]);
+                } else {
+                    if (q > 0) read_piece(buf, q, pa[0], pb[0]);
+                }
+                mma_piece(pa[q % SETS], pb[q % SETS]);
+                // the other buffer held stage kt - 1, which every wave
+                // finished reading before the previous barrier; writing it
+                // early leaves the writes complete by this stage's barrier
+                if (q == 0 && more) store(buf ^ 1);
+                // one piece's reads and instructions at a time
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+        }
+    } else if constexpr (NQ == 1) {
+        for (kidx_t kt = 0; kt < nk; ++kt) {
             const int buf = kt & 1;
             const bool more = kt + 1 < nk;
             if (more) load(kt + 1);
@@ -295,7 +397,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             read_piece(buf, 1, fa[1], fb[1]);
             mma_piece(fa[0], fb[0]);
             mma_piece(fa[1], fb[1]);
-            if constexpr (LOWP) {
+            if constexpr (SUM64) {
                 if ((kt + 1) % FLUSH_STAGES == 0 || !more) flush();
             }
             // the other buffer held stage kt - 1, which every wave finished
@@ -306,7 +408,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     } else {
         piece_t pa[2][WTM], pb[2][WTN];
         read_piece(0, 0, pa[0], pb[0]);
-        for (int64_t kt = 0; kt < nk; ++kt) {
+        for (kidx_t kt = 0; kt < nk; ++kt) {
             const int buf = kt & 1;
             const bool more = kt + 1 < nk;
             if (more) load(kt + 1);
@@ -318,7 +420,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                     // the other buffer held stage kt - 1, which every wave
                     // finished reading before the previous barrier
                     if (more) store(buf ^ 1);
-                    if constexpr (LOWP) {
+                    if constexpr (SUM64) {
                         if (kt % FLUSH_STAGES == FLUSH_STAGES - 1) flush();
                     }
                     __syncthreads();
@@ -327,13 +429,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 mma_piece(pa[q & 1], pb[q & 1]);
             }
         }
-        if constexpr (LOWP) flush();
-    }
-    if constexpr (!LOWP) {
-#pragma unroll
-        for (int i = 0; i < WTM; ++i)
-#pragma unroll
-            for (int j = 0; j < WTN; ++j) acc64[i][j] = acc[i][j];
+        if constexpr (SUM64) flush();
     }
 
     // Epilogue: per column, sums over this wave's WTM*16 rows.  Rows of lane
@@ -343,6 +439,39 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     const int64_t rw = r0 + wr * WTM * 16;
     const int64_t pb = rw / (WTM * 16);
     const int64_t cbase = c0 + wc * WTN * 16 + li;
+    if constexpr (S::SUM32) {
+        // one column block at a time: its values in float64 (32 registers)
+        // rather than all of them at once (256)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            double z[WTM][4];
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) z[i][v] = (double)acc[i][j][v];
+            const int64_t col = cbase + j * 16;
+            if (a.with_cross) {
+                for (int q = 0; q < a.Qc; ++q) {
+                    const double* Cq = a.C + q * a.ldc + rw + T::ROW_G * lg;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) sum += z[i][v] * Cq[i * 16 + T::ROW_V * v];
+                    sum = wave_sum16(sum);
+                    if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
+                }
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum += z[i][v] * z[i][v];
+            sum = wave_sum16(sum);
+            if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+        }
+        return;
+    }
     if (a.with_cross) {
         for (int q = 0; q < a.Qc; ++q) {
             const double* Cq = a.C + q * a.ldc + rw + T::ROW_G * lg;
@@ -357,7 +486,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 #pragma unroll
                 for (int i = 0; i < WTM; ++i)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) sum += acc64[i][j][v] * cv[i][v];
+                    for (int v = 0; v < 4; ++v) sum += zval(i, j, v) * cv[i][v];
                 sum = wave_sum16(sum);
                 const int64_t col = cbase + j * 16;
                 if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
@@ -370,7 +499,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 #pragma unroll
         for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sum += acc64[i][j][v] * acc64[i][j][v];
+            for (int v = 0; v < 4; ++v) sum += zval(i, j, v) * zval(i, j, v);
         sum = wave_sum16(sum);
         const int64_t col = cbase + j * 16;
         if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
@@ -576,6 +705,7 @@ typedef Shape<4, 2, 2, 4, 1> Cfg2;   // 128 x 128, 512 threads, waves of 32 x 64
 typedef Shape<2, 4, 4, 4, 1> Cfg3;   // 128 x 256, 512 threads, waves of 64 x 64
 typedef Shape<4, 2, 4, 4, 1> Cfg4;   // 256 x 128, 512 threads, waves of 64 x 64
 typedef Shape<2, 2, 4, 4, 1> Cfg5;   // as Cfg0, one workgroup per CU
+typedef Shape<4, 2, 4, 8, 1, true> Cfg6;   // 256 x 256, 512 threads, waves of 64 x 128, float32 sums
 
 template <typename S> TrmmShape shape_of() { return TrmmShape{S::TM, S::TN, S::WTM * 16, S::NT, 1, 32}; }
 
@@ -606,13 +736,18 @@ hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
         case 4:
             if constexpr (F64) return launch_trmm<AT, XT, Cfg4>(a, s);
             else return hipErrorInvalidValue;
+        case 6:
+            if constexpr (!F64 && I8) return launch_trmm<AT, XT, Cfg6>(a, s);
+            else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int trmm_num_cfgs() { return 6; }
+int trmm_num_cfgs() { return 7; }
+
+bool trmm_shape_sum32(int cfg) { return cfg == 6; }
 
 TrmmShape trmm_shape(int cfg) {
     switch (cfg) {
@@ -622,12 +757,15 @@ TrmmShape trmm_shape(int cfg) {
         case 3: return shape_of<Cfg3>();
         case 4: return shape_of<Cfg4>();
         case 5: return shape_of<Cfg5>();
+        case 6: return shape_of<Cfg6>();
         default: return TrmmShape{0, 0, 0, 0, 0, 0};
     }
 }
 
 bool trmm_cfg_valid(int at, int xt, int cfg) {
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
+    // 64 x 128 waves fit two per SIMD only with float32 sums and int8 dosages
+    if (cfg == 6) return at != A_F64 && xt == X_I8;
     if (at == A_F64) return true;
     // The reduced-precision products also carry float64 partial sums; 64 x 64
     // waves of them only fit two waves per SIMD without spilling when the
@@ -636,12 +774,17 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
     return cfg == 3 && xt == X_I8;
 }
 
-// Measured on MI355X at n = 50,000 with int8 dosages (SNPs per second of the
-// whole block, 32768-SNP sub-blocks): the 128 x 256 tile is fastest for
-// every element type; with float64 dosages the reduced-precision products
-// take the 128 x 128 tile of 64 x 32 waves.
+// Measured on MI355X at n = 50,000 with int8 dosages (one 50,000-SNP block):
+// float64 is fastest in the 128 x 256 tile; float32 and bfloat16 in the
+// 256 x 256 tile of 64 x 128 waves with float32 sums (141 and 1,190
+// TFLOP/s, against 131 and 870 in the 128 x 256 tile with float64 sums;
+// b moves from 6e-11 to 4e-10 of the float64 path for float32, and not
+// measurably for bfloat16, whose rounding of L^-1 dominates).  With float64
+// dosages the reduced-precision products take the 128 x 128 tile of
+// 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
-    if (at == A_F64 || xt == X_I8) return 3;
+    if (at == A_F64) return 3;
+    if (xt == X_I8) return 6;
     return 1;
 }
 
@@ -691,6 +834,13 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     }
     const TrmmShape sh = trmm_geom(a.at, a.xt, a.cfg, a.slices, a.rgroup);
     if (a.n_pad % sh.tm) return hipErrorInvalidValue;
+    // 32-bit buffer offsets of the SUM32 shapes: a tile's rows of L^-1 and
+    // its dosage columns
+    if (a.at != A_I8S && trmm_shape_sum32(a.cfg)) {
+        const int64_t asz = a.at == A_F32 ? 4 : 2;
+        if ((int64_t)sh.tm * a.ldu * asz > INT32_MAX || (int64_t)sh.tn * a.ldx * (int64_t)xs > INT32_MAX)
+            return hipErrorInvalidValue;
+    }
     if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh)))
         return hipErrorInvalidValue;
     if (a.n_sched > 0x7fffffff) return hipErrorInvalidValue;

@@ -179,7 +179,7 @@ def test_reduced_precision_vs_oracle(precision, tol):
     assert err < tol
 
 
-TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5], "bf16": [1, 2, 3, 5]}
+TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6]}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
@@ -203,6 +203,57 @@ def test_every_tile_shape(precision, monkeypatch):
             # float64 sums differ between shapes only in rounding order
             ref = b if ref is None else ref
             assert normwise(b, ref) < 1e-13
+
+
+def rounding_bound(prob, XR, b_ref, u_store, u_acc):
+    """First-order bound of each SNP's normwise error of b when z = L^-1 x
+    is formed from L^-1 rounded with unit roundoff u_store and summed with
+    unit roundoff u_acc (any order), and every other quantity is exact:
+    |dz_r| <= (u_store + n u_acc) (|L^-1| |x|)_r, dS_BR <= 2 sum_r |z_r| |dz_r|,
+    and a change d of S_BR moves b by -d b_p S^-1 e_p."""
+    M, XL = prob["M"], prob["XL"]
+    n = M.shape[0]
+    Li = np.linalg.inv(np.linalg.cholesky(M))
+    X = XR.astype(np.float64)
+    Z = Li @ X.T
+    dz = (u_store + n * u_acc) * (np.abs(Li) @ np.abs(X).T)
+    dS = 2.0 * np.sum(np.abs(Z) * dz, axis=0)
+    Minv = np.linalg.inv(M)
+    out = np.zeros(X.shape[0])
+    for i in range(X.shape[0]):
+        Xi = np.column_stack([XL, X[i]])
+        S = Xi.T @ Minv @ Xi
+        col = np.linalg.solve(S, np.eye(S.shape[0])[:, -1])
+        bi = b_ref[i, 0]
+        out[i] = np.linalg.norm(col) * dS[i] * abs(bi[-1]) / np.linalg.norm(bi)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("cfg", [3, 6])
+@pytest.mark.parametrize("n,p,m,dev_block", [(17, 3, 60, 128), (130, 5, 300, 128), (255, 4, 300, 256),
+                                               (257, 4, 531, 512), (777, 3, 1500, 256)])
+def test_reduced_precision_ragged_within_rounding_bound(precision, cfg, n, p, m, dev_block, monkeypatch):
+    # n below one stage, one tile and just past a tile; ragged column tiles.
+    # At small n the cancellation in S_BR - u^T S_TL^-1 u magnifies the
+    # rounding of L^-1 past the 1e-8 bar of large n, so each SNP is held to
+    # twice the first-order rounding bound instead; a lost or misplaced
+    # chunk of the product is off by O(1).
+    seed = 29 + n
+    monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
+    _say(f"{precision} tile shape {cfg} n={n} p={p} m={m} dev_block={dev_block}")
+    prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    b, var, info = run(prob, XR, precision=precision, x_dtype="i8", dev_block=dev_block)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert np.array_equal(info, io)
+    ok = io == 0
+    u = 2.0 ** -24 if precision == "fp32" else 2.0 ** -8
+    bound = rounding_bound(prob, XR[ok], bo[ok], u, 2.0 ** -24)
+    num = np.linalg.norm((b[ok] - bo[ok]).reshape(int(ok.sum()), -1), axis=1)
+    err = num / np.linalg.norm(bo[ok].reshape(int(ok.sum()), -1), axis=1)
+    _say(f"  err {err.max():.3e}, worst err / bound {np.max(err / (bound + 1e-300)):.3f}")
+    assert np.all(err <= 2.0 * bound + 1e-13)
 
 
 @pytest.mark.parametrize("slices,tol", [(4, 1e-8), (5, 1e-9), (6, TOL_FP64)])
