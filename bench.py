@@ -56,11 +56,16 @@ def measured_traffic(leg, workload_name):
     rocprofv3 counter summary, or None once the kernel source has changed."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"trmm_{leg}_{workload_name}_traffic.json")
-    src = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "trmm_kernels.hip")
     if not os.path.exists(path):
         return None, None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    h = hashlib.sha256()
+    for src in rec.get("kernel_sources", []):
+        full = os.path.join(ROOT, src)
+        if not os.path.exists(full):
+            return None, "kernel changed since the counters were taken"
+        h.update(open(full, "rb").read())
+    if not rec.get("kernel_sources") or rec.get("kernel_source_sha256") != h.hexdigest():
         return None, "kernel changed since the counters were taken"
     return rec["traffic_bytes_per_launch"], (
         f"FETCH_SIZE+WRITE_SIZE per launch over the {rec['launches']} launches of one step, calibrated on a "

@@ -103,6 +103,8 @@ struct TrmmArgs {
     int rgroup;                 // row tiles per L2 group of the schedule (0: the model's choice)
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
+// the int8-slice kernel (a.at == A_I8S); called by trmm_stream
+hipError_t trmm_sliced_launch(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
 
 int trmm_num_cfgs();

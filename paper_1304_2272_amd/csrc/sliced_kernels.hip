@@ -1,0 +1,230 @@
+// The int8-slice form of the streaming triangular product (Algorithm 2,
+// loop body): L^-1 X_blk from int8 digit slices of L^-1 and int8 dosages
+// with exact int32 sums on the matrix cores, the slices combined in float64
+// in the epilogue, which forms the same partial sums as the floating-point
+// product (S_BL, bbar_B and S_BR of Algorithm 2 per wave row slice).
+#include "internal.h"
+#include "trmm_common.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace gwas {
+namespace {
+
+// Accumulator layout of the 16x16x64 int8 instruction: element v of a lane
+// holds column lane%16 and row 4*(lane/16) + v.
+constexpr int I8_ROW_G = 4, I8_ROW_V = 1;
+
+// L^-1 X from int8 slices of L^-1 and int8 dosages.  Real row r of L^-1 is
+// rscale[r] * sum_s 2^(-6-7s) * A_s(r, :) with int8 slices A_s; sliced row
+// R = (r/16)*16*S + s*16 + r%16 holds A_s(r, :) (row-major, K contiguous).
+// Every int32 sum A_s(r, :) x is exact (|sum| <= 64 * 2 * n < 2^31), so the
+// float64 combination in the epilogue is the only rounding of the product.
+// Each wave owns 16 real rows with all S slices (block i = slice i) and
+// WTN * 16 SNP columns; the workgroup is WGM x WGN waves.
+template <int S, int WGM, int WGN, int WTN, bool GROUPED>
+__global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la) {
+    constexpr int BK = ROW_BYTES;                 // int8 K per stage row
+    constexpr int TMR = WGM * 16;                 // real rows per tile
+    constexpr int TMS = TMR * S;                  // sliced rows per tile
+    constexpr int TN = WGN * WTN * 16;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int A_CHUNKS = TMS * (ROW_BYTES / 16);
+    constexpr int CA = (A_CHUNKS + NT - 1) / NT;
+    constexpr int B_CHUNKS = TN * (ROW_BYTES / 16);
+    constexpr int CB = (B_CHUNKS + NT - 1) / NT;
+
+    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
+    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
+    if (e0 < 0) return;
+    const int I = e0 & SCHED_ROW_MASK;
+    // grouped launches carry one argument set per context; the schedule
+    // entry names the context in its high bits.  The set is copied into
+    // registers once: read through a reference, every field would be loaded
+    // again after each barrier (a barrier is a memory fence).
+    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+
+    __shared__ __attribute__((aligned(16))) char As[2][TMS * ROW_STRIDE];
+    __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WGN, wc = wave % WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    const int64_t r0 = (int64_t)I * TMR;                          // first real row
+    const int64_t kend = std::min<int64_t>(r0 + TMR, a.n_pad);
+    const int64_t nk = (kend + BK - 1) / BK;
+    const char* A = reinterpret_cast<const char*>(a.Ut) + (int64_t)I * TMS * a.ldu;
+    const int8_t* X = reinterpret_cast<const int8_t*>(a.X);
+    const int64_t c0 = (int64_t)J * TN;
+
+    i4_t acc[S][WTN];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = i4_t{0, 0, 0, 0};
+
+    // Staged operands of the next stage: loaded at the top of a stage,
+    // written to the other LDS buffer before its barrier.
+    u4_t ra[CA], rb[CB];
+    auto load = [&](int64_t kt) {
+#pragma unroll
+        for (int c = 0; c < CA; ++c) {
+            const int idx = tid + c * NT;
+            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
+                ra[c] = *reinterpret_cast<const u4_t*>(A + (int64_t)(idx >> 3) * a.ldu + kt * BK + (idx & 7) * 16);
+        }
+        // whole tile inside the block and the stage inside n: one branch for
+        // the workgroup, plain 16-byte loads
+        if (c0 + TN <= a.cols && (kt + 1) * BK <= a.n) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int idx = tid + c * NT;
+                if (B_CHUNKS % NT == 0 || idx < B_CHUNKS)
+                    rb[c] = *reinterpret_cast<const u4_t*>(X + (c0 + (idx >> 3)) * a.ldx + kt * BK + (idx & 7) * 16);
+            }
+            return;
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int idx = tid + c * NT;
+            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
+                const int col = idx >> 3, ch = idx & 7;
+                const int64_t gcol = c0 + col;
+                const int64_t k0 = kt * BK + ch * 16;
+                const int8_t* src = X + gcol * a.ldx + k0;
+                if (gcol < a.cols && k0 + 16 <= a.n) {
+                    rb[c] = *reinterpret_cast<const u4_t*>(src);
+                } else {
+                    int8_t tmp[16] __attribute__((aligned(16)));
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) tmp[e] = (gcol < a.cols && k0 + e < a.n) ? src[e] : (int8_t)0;
+                    rb[c] = *reinterpret_cast<const u4_t*>(tmp);
+                }
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < CA; ++c) {
+            const int idx = tid + c * NT;
+            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
+                *reinterpret_cast<u4_t*>(As[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int idx = tid + c * NT;
+            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS)
+                *reinterpret_cast<u4_t*>(Bs[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = rb[c];
+        }
+    };
+    // Fragments of one 64-deep K step (h = 0, 1 of a stage).  (Reading the
+    // second step behind the first step's instructions, as the floating-point
+    // product does, measured slower here.)
+    auto read_step = [&](int buf, int h, u4_t (&fa)[S], u4_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            fa[i] = *reinterpret_cast<const u4_t*>(As[buf] + (wr * S * 16 + i * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+            fb[j] = *reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
+    };
+    auto mma_step = [&](const u4_t (&fa)[S], const u4_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reinterpret_cast<const i4_t&>(fa[i]),
+                                                                 reinterpret_cast<const i4_t&>(fb[j]), acc[i][j], 0, 0, 0);
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) load(kt + 1);
+        u4_t a0[S], b0[WTN], a1[S], b1[WTN];
+        read_step(buf, 0, a0, b0);
+        read_step(buf, 1, a1, b1);
+        mma_step(a0, b0);
+        mma_step(a1, b1);
+        // the other buffer held stage kt - 1, which every wave finished
+        // reading before the previous barrier
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: z(r, col) = rscale[r] * sum_i 2^(-6-7i) acc_i, then sums over
+    // this wave's 16 real rows per column.
+    const int Q = a.with_cross ? a.Qc + 1 : 1;
+    const int64_t rw = r0 + wr * 16;
+    const int64_t pb = rw / 16;
+    const int64_t cbase = c0 + wc * WTN * 16 + li;
+    double sc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sc[v] = a.rscale[rw + I8_ROW_G * lg + I8_ROW_V * v];
+    double z[WTN][4];
+#pragma unroll
+    for (int j = 0; j < WTN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = S - 1; i >= 0; --i) t += ldexp((double)acc[i][j][v], -6 - 7 * i);
+            z[j][v] = sc[v] * t;
+        }
+    if (a.with_cross) {
+        for (int q = 0; q < a.Qc; ++q) {
+            double cv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cv[v] = a.C[q * a.ldc + rw + I8_ROW_G * lg + I8_ROW_V * v];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+                double sum = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum += z[j][v] * cv[v];
+                sum = wave_sum16(sum);
+                const int64_t col = cbase + j * 16;
+                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum += z[j][v] * z[j][v];
+        sum = wave_sum16(sum);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+    }
+}
+
+}  // namespace
+
+TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512, 1, 32}; }
+
+// Arguments were checked by trmm_check (single launches) or by the caller
+// (grouped launches).
+hipError_t trmm_sliced_launch(const TrmmArgs& a, hipStream_t s) {
+    switch (a.slices) {
+#define GWAS_SLICED_CASE(S)                                                                       \
+    case S:                                                                                       \
+        if (a.group)                                                                              \
+            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, true>), dim3((unsigned)a.n_sched),  \
+                               dim3(512), 0, s, a);                                               \
+        else                                                                                      \
+            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, false>), dim3((unsigned)a.n_sched), \
+                               dim3(512), 0, s, a);                                               \
+        return hipGetLastError();
+        GWAS_SLICED_CASE(4) GWAS_SLICED_CASE(5) GWAS_SLICED_CASE(6)
+#undef GWAS_SLICED_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gwas

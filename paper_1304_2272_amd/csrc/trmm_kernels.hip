@@ -2,9 +2,10 @@
 // loop body): Xbar_blk = L^-1 X_blk on matrix cores, never stored, with the
 // cross products of Algorithm 2 fused into its epilogue (S_BL = xbar^T
 // Xbar_L, bbar_B = xbar^T ybar, S_BR = xbar^T xbar) as partial sums per
-// wave row slice; the int8-slice form of the same product; tile shapes,
-// their XCD schedule and the launchers.
+// wave row slice; tile shapes, their XCD schedule, argument checks and the
+// launcher (the int8-slice form of the product has its own source).
 #include "internal.h"
+#include "trmm_common.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -16,23 +17,12 @@
 namespace gwas {
 namespace {
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
-typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
-typedef int i4_t __attribute__((ext_vector_type(4)));
-
-// Each LDS row of a stage holds 128 bytes of K (BK elements) plus 16 bytes of
-// padding, so the 16 rows read together by one instruction fall on
-// distinct banks and every row stays 16-byte aligned.
-constexpr int ROW_BYTES = 128;
-constexpr int ROW_STRIDE = ROW_BYTES + 16;
-// Reduced-precision sums move to float64 every FLUSH_STAGES stages.  At
-// n = 50,000 the float32 error of b against the float64 path is 5.5e-11
-// flushing every 4 stages, 6.3e-11 every 16 and 2.0e-10 with float32 sums
-// only: rounding L^-1 to float32 dominates.  16 stages saves 2% of the
-// float32 product's time over 4.
+// Reduced-precision sums move to float64 every FLUSH_STAGES stages in the
+// shapes that keep float64 sums.  At n = 50,000 the float32 error of b
+// against the float64 path is 5.5e-11 flushing every 4 stages, 6.3e-11
+// every 16 and 2.0e-10 to 4e-10 with float32 sums only: rounding L^-1 to
+// float32 dominates.  16 stages saves 2% of the float32 product's time
+// over 4.
 constexpr int FLUSH_STAGES = 16;
 
 // Accumulator layout of the 16x16 instructions: element v of a lane holds
@@ -97,13 +87,6 @@ __device__ __forceinline__ typename MM<AT>::frag_t frag(const u2_t& f, int s) {
 }
 template <int BYTES> struct Piece { typedef u4_t type; };
 template <> struct Piece<8> { typedef u2_t type; };
-
-__device__ __forceinline__ double wave_sum16(double v) {
-    // sum over the four lane groups (lanes l, l+16, l+32, l+48)
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
 
 // Workgroup shape: WGM x WGN waves, each wave WTM x WTN blocks of 16 x 16.
 // SUM32: the reduced-precision products keep float32 sums only, with no
@@ -379,9 +362,11 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 }
                 mma_piece(pa[q % SETS], pb[q % SETS]);
                 // the other buffer held stage kt - 1, which every wave
-                // finished reading before the previous barrier; writing it
-                // early leaves the writes complete by this stage's barrier
-                if (q == 0 && more) store(buf ^ 1);
+                // finished reading before the previous barrier.  Float32
+                // writes it after the first piece (141 against 138 TFLOP/s
+                // after the last at n = 50,000); bfloat16 after the last
+                // (1,180 against 1,090), as does the float64 product.
+                if (q == (SETS == 2 ? 0 : NQ - 1) && more) store(buf ^ 1);
                 // one piece's reads and instructions at a time
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -506,197 +491,6 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     }
 }
 
-// Accumulator layout of the 16x16x64 int8 instruction: element v of a lane
-// holds column lane%16 and row 4*(lane/16) + v.
-constexpr int I8_ROW_G = 4, I8_ROW_V = 1;
-
-// L^-1 X from int8 slices of L^-1 and int8 dosages.  Real row r of L^-1 is
-// rscale[r] * sum_s 2^(-6-7s) * A_s(r, :) with int8 slices A_s; sliced row
-// R = (r/16)*16*S + s*16 + r%16 holds A_s(r, :) (row-major, K contiguous).
-// Every int32 sum A_s(r, :) x is exact (|sum| <= 64 * 2 * n < 2^31), so the
-// float64 combination in the epilogue is the only rounding of the product.
-// Each wave owns 16 real rows with all S slices (block i = slice i) and
-// WTN * 16 SNP columns; the workgroup is WGM x WGN waves.
-template <int S, int WGM, int WGN, int WTN, bool GROUPED>
-__global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la) {
-    constexpr int BK = ROW_BYTES;                 // int8 K per stage row
-    constexpr int TMR = WGM * 16;                 // real rows per tile
-    constexpr int TMS = TMR * S;                  // sliced rows per tile
-    constexpr int TN = WGN * WTN * 16;
-    constexpr int NT = 64 * WGM * WGN;
-    constexpr int A_CHUNKS = TMS * (ROW_BYTES / 16);
-    constexpr int CA = (A_CHUNKS + NT - 1) / NT;
-    constexpr int B_CHUNKS = TN * (ROW_BYTES / 16);
-    constexpr int CB = (B_CHUNKS + NT - 1) / NT;
-
-    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
-    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
-    if (e0 < 0) return;
-    const int I = e0 & SCHED_ROW_MASK;
-    // grouped launches carry one argument set per context; the schedule
-    // entry names the context in its high bits.  The set is copied into
-    // registers once: read through a reference, every field would be loaded
-    // again after each barrier (a barrier is a memory fence).
-    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
-
-    __shared__ __attribute__((aligned(16))) char As[2][TMS * ROW_STRIDE];
-    __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / WGN, wc = wave % WGN;
-    const int li = lane & 15, lg = lane >> 4;
-
-    const int64_t r0 = (int64_t)I * TMR;                          // first real row
-    const int64_t kend = std::min<int64_t>(r0 + TMR, a.n_pad);
-    const int64_t nk = (kend + BK - 1) / BK;
-    const char* A = reinterpret_cast<const char*>(a.Ut) + (int64_t)I * TMS * a.ldu;
-    const int8_t* X = reinterpret_cast<const int8_t*>(a.X);
-    const int64_t c0 = (int64_t)J * TN;
-
-    i4_t acc[S][WTN];
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-        for (int j = 0; j < WTN; ++j) acc[i][j] = i4_t{0, 0, 0, 0};
-
-    // Staged operands of the next stage: loaded at the top of a stage,
-    // written to the other LDS buffer before its barrier.
-    u4_t ra[CA], rb[CB];
-    auto load = [&](int64_t kt) {
-#pragma unroll
-        for (int c = 0; c < CA; ++c) {
-            const int idx = tid + c * NT;
-            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
-                ra[c] = *reinterpret_cast<const u4_t*>(A + (int64_t)(idx >> 3) * a.ldu + kt * BK + (idx & 7) * 16);
-        }
-        // whole tile inside the block and the stage inside n: one branch for
-        // the workgroup, plain 16-byte loads
-        if (c0 + TN <= a.cols && (kt + 1) * BK <= a.n) {
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int idx = tid + c * NT;
-                if (B_CHUNKS % NT == 0 || idx < B_CHUNKS)
-                    rb[c] = *reinterpret_cast<const u4_t*>(X + (c0 + (idx >> 3)) * a.ldx + kt * BK + (idx & 7) * 16);
-            }
-            return;
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int idx = tid + c * NT;
-            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
-                const int col = idx >> 3, ch = idx & 7;
-                const int64_t gcol = c0 + col;
-                const int64_t k0 = kt * BK + ch * 16;
-                const int8_t* src = X + gcol * a.ldx + k0;
-                if (gcol < a.cols && k0 + 16 <= a.n) {
-                    rb[c] = *reinterpret_cast<const u4_t*>(src);
-                } else {
-                    int8_t tmp[16] __attribute__((aligned(16)));
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) tmp[e] = (gcol < a.cols && k0 + e < a.n) ? src[e] : (int8_t)0;
-                    rb[c] = *reinterpret_cast<const u4_t*>(tmp);
-                }
-            }
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < CA; ++c) {
-            const int idx = tid + c * NT;
-            if (A_CHUNKS % NT == 0 || idx < A_CHUNKS)
-                *reinterpret_cast<u4_t*>(As[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = ra[c];
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int idx = tid + c * NT;
-            if (B_CHUNKS % NT == 0 || idx < B_CHUNKS)
-                *reinterpret_cast<u4_t*>(Bs[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = rb[c];
-        }
-    };
-    // Fragments of one 64-deep K step (h = 0, 1 of a stage).  (Reading the
-    // second step behind the first step's instructions, as the floating-point
-    // product does, measured slower here.)
-    auto read_step = [&](int buf, int h, u4_t (&fa)[S], u4_t (&fb)[WTN]) {
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-            fa[i] = *reinterpret_cast<const u4_t*>(As[buf] + (wr * S * 16 + i * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
-#pragma unroll
-        for (int j = 0; j < WTN; ++j)
-            fb[j] = *reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32 + h * 16);
-    };
-    auto mma_step = [&](const u4_t (&fa)[S], const u4_t (&fb)[WTN]) {
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-#pragma unroll
-            for (int j = 0; j < WTN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reinterpret_cast<const i4_t&>(fa[i]),
-                                                                 reinterpret_cast<const i4_t&>(fb[j]), acc[i][j], 0, 0, 0);
-    };
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) load(kt + 1);
-        u4_t a0[S], b0[WTN], a1[S], b1[WTN];
-        read_step(buf, 0, a0, b0);
-        read_step(buf, 1, a1, b1);
-        mma_step(a0, b0);
-        mma_step(a1, b1);
-        // the other buffer held stage kt - 1, which every wave finished
-        // reading before the previous barrier
-        if (more) store(buf ^ 1);
-        __syncthreads();
-    }
-
-    // Epilogue: z(r, col) = rscale[r] * sum_i 2^(-6-7i) acc_i, then sums over
-    // this wave's 16 real rows per column.
-    const int Q = a.with_cross ? a.Qc + 1 : 1;
-    const int64_t rw = r0 + wr * 16;
-    const int64_t pb = rw / 16;
-    const int64_t cbase = c0 + wc * WTN * 16 + li;
-    double sc[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sc[v] = a.rscale[rw + I8_ROW_G * lg + I8_ROW_V * v];
-    double z[WTN][4];
-#pragma unroll
-    for (int j = 0; j < WTN; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double t = 0.0;
-#pragma unroll
-            for (int i = S - 1; i >= 0; --i) t += ldexp((double)acc[i][j][v], -6 - 7 * i);
-            z[j][v] = sc[v] * t;
-        }
-    if (a.with_cross) {
-        for (int q = 0; q < a.Qc; ++q) {
-            double cv[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) cv[v] = a.C[q * a.ldc + rw + I8_ROW_G * lg + I8_ROW_V * v];
-#pragma unroll
-            for (int j = 0; j < WTN; ++j) {
-                double sum = 0.0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sum += z[j][v] * cv[v];
-                sum = wave_sum16(sum);
-                const int64_t col = cbase + j * 16;
-                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < WTN; ++j) {
-        double sum = 0.0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sum += z[j][v] * z[j][v];
-        sum = wave_sum16(sum);
-        const int64_t col = cbase + j * 16;
-        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
-    }
-}
-
 // Tile shapes of the triangular product.  MINB is the workgroups per CU
 // the register budget is sized for.
 typedef Shape<2, 2, 4, 4, 2> Cfg0;   // 128 x 128, 256 threads, waves of 64 x 64
@@ -776,7 +570,7 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 
 // Measured on MI355X at n = 50,000 with int8 dosages (one 50,000-SNP block):
 // float64 is fastest in the 128 x 256 tile; float32 and bfloat16 in the
-// 256 x 256 tile of 64 x 128 waves with float32 sums (141 and 1,190
+// 256 x 256 tile of 64 x 128 waves with float32 sums (141 and 1,180
 // TFLOP/s, against 131 and 870 in the 128 x 256 tile with float64 sums;
 // b moves from 6e-11 to 4e-10 of the float64 path for float32, and not
 // measurably for bfloat16, whose rounding of L^-1 dominates).  With float64
@@ -815,8 +609,6 @@ int64_t trmm_schedule(int64_t n_pad, int64_t cols, const TrmmShape& sh, int* out
     std::copy(v.begin(), v.end(), out);
     return total;
 }
-
-TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512, 1, 32}; }
 
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.cols <= 0) return hipSuccess;
@@ -857,22 +649,7 @@ hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
     } else if (!a.sched || a.n_sched <= 0 || a.n_sched > 0x7fffffff) {
         return hipErrorInvalidValue;
     }
-    if (a.at == A_I8S) {
-        switch (a.slices) {
-#define GWAS_SLICED_CASE(S)                                                                       \
-    case S:                                                                                       \
-        if (a.group)                                                                              \
-            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, true>), dim3((unsigned)a.n_sched),  \
-                               dim3(512), 0, s, a);                                               \
-        else                                                                                      \
-            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, false>), dim3((unsigned)a.n_sched), \
-                               dim3(512), 0, s, a);                                               \
-        return hipGetLastError();
-            GWAS_SLICED_CASE(4) GWAS_SLICED_CASE(5) GWAS_SLICED_CASE(6)
-#undef GWAS_SLICED_CASE
-            default: return hipErrorInvalidValue;
-        }
-    }
+    if (a.at == A_I8S) return trmm_sliced_launch(a, s);
     if (a.xt == X_F64) {
         if (a.at == A_F64) return launch_cfg<double, double>(a, s);
         if (a.at == A_F32) return launch_cfg<float, double>(a, s);

@@ -9,7 +9,7 @@ library does not use it).
              kernel of known size in the same run (``torch.bitwise_not`` over
              ``--copy-bytes`` bytes: it reads and writes that many bytes).
              Writes a JSON record that bench.py reports as ``roofline.traffic``
-             while the kernel source keeps the recorded SHA-256.
+             while the kernel's sources keep the recorded SHA-256.
 
     python -m paper_1304_2272_amd.profile_summary traffic \\
         --fetch <FETCH_SIZE counter_collection.csv> --write <WRITE_SIZE csv> \\
@@ -28,7 +28,21 @@ import json
 import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STREAM_SRC = os.path.join(ROOT, "paper_1304_2272_amd", "csrc", "trmm_kernels.hip")
+CSRC = os.path.join("paper_1304_2272_amd", "csrc")
+
+
+def kernel_sources(kernel):
+    """Source files (relative to the repository root) whose text decides the
+    named kernel's code."""
+    own = "sliced_kernels.hip" if "sliced" in kernel else "trmm_kernels.hip"
+    return [os.path.join(CSRC, own), os.path.join(CSRC, "trmm_common.h")]
+
+
+def sources_sha256(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
 
 
 def _per_dispatch(path, counter):
@@ -79,7 +93,8 @@ def traffic(args):
         "algorithmic_bytes_per_launch": alg / launches,
         "fetch_calibration": f_cal,
         "write_calibration": w_cal,
-        "kernel_source_sha256": hashlib.sha256(open(STREAM_SRC, "rb").read()).hexdigest(),
+        "kernel_sources": kernel_sources(args.kernel),
+        "kernel_source_sha256": sources_sha256(kernel_sources(args.kernel)),
     }
     json.dump(rec, open(args.out, "w"), indent=1)
     print(json.dumps(rec, indent=1))
