@@ -348,6 +348,11 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             const bool more = kt + 1 < nk;
             if (more) load(kt + 1);
             piece_t pa[SETS][WTM], pb[SETS][WTN];
+            // lgkmcnt(0), already met after the previous barrier: it tells
+            // the compiler no scalar load is outstanding at the top of the
+            // loop, so the waits for piece 0's reads count them one by one
+            // instead of waiting for all of them
+            __builtin_amdgcn_s_waitcnt(0xc07f);
             read_piece(buf, 0, pa[0], pb[0]);
             // piece 0's reads stay apart from piece 1's (not merged into
             // wider reads), so its first instructions wait for their own
