@@ -63,18 +63,33 @@ __device__ __forceinline__ void load_slab(Slab<R, NT>& sl, const double* __restr
     }
 }
 
+// LDS image of one operand's stage.  kcontig operands keep rows of K
+// (R x GLD); the others keep their global layout, rows of R at fixed k
+// (GBK x (R + 2)), so both are written in 16-byte chunks and a lane's
+// fragment is one 16-byte read (kcontig) or two 8-byte reads of
+// consecutive k, 16 lanes over consecutive r (the others).
+template <int R, bool kcontig> struct Lds {
+    static constexpr int SIZE = kcontig ? R * GLD : GBK * (R + 2);
+    __device__ static d2_t frag(const double* S, int r, int k) {
+        if constexpr (kcontig) {
+            return *reinterpret_cast<const d2_t*>(S + r * GLD + k);
+        } else {
+            return d2_t{S[k * (R + 2) + r], S[(k + 1) * (R + 2) + r]};
+        }
+    }
+};
+
 template <int R, int NT, bool kcontig>
-__device__ __forceinline__ void store_slab(const Slab<R, NT>& sl, double (*S)[GLD], int tid) {
+__device__ __forceinline__ void store_slab(const Slab<R, NT>& sl, double* S, int tid) {
 #pragma unroll
     for (int c = 0; c < Slab<R, NT>::PER; ++c) {
         const int idx = tid + c * NT;
         if (Slab<R, NT>::CH % NT != 0 && idx >= Slab<R, NT>::CH) break;
         if constexpr (kcontig) {
-            *reinterpret_cast<d2_t*>(&S[idx / (GBK / 2)][(idx % (GBK / 2)) * 2]) = sl.v[c];
+            *reinterpret_cast<d2_t*>(S + (idx / (GBK / 2)) * GLD + (idx % (GBK / 2)) * 2) = sl.v[c];
         } else {
             const int k = idx / (R / 2), r = (idx % (R / 2)) * 2;
-            S[r][k] = sl.v[c][0];
-            S[r + 1][k] = sl.v[c][1];
+            *reinterpret_cast<d2_t*>(S + k * (R + 2) + r) = sl.v[c];
         }
     }
 }
@@ -99,8 +114,10 @@ __global__ __launch_bounds__(128 * WGN, (WGN == 2 ? 2 : 1)) void gemm_f64_kernel
     if (g.kflags & KR_B_LOWER) kbeg = max(kbeg, n0);
     kbeg = (kbeg / GBK) * GBK;
 
-    __shared__ __attribute__((aligned(16))) double As[2][TILE_M][GLD];
-    __shared__ __attribute__((aligned(16))) double Bs[2][TN][GLD];
+    typedef Lds<TILE_M, A_KC> LA;
+    typedef Lds<TN, B_KC> LB;
+    __shared__ __attribute__((aligned(16))) double As[2][LA::SIZE];
+    __shared__ __attribute__((aligned(16))) double Bs[2][LB::SIZE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -136,8 +153,8 @@ __global__ __launch_bounds__(128 * WGN, (WGN == 2 ? 2 : 1)) void gemm_f64_kernel
             d2_t av[4], bv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                av[i] = *reinterpret_cast<const d2_t*>(&As[buf][wr * 64 + i * 16 + li][4 * lg + 2 * h]);
-                bv[i] = *reinterpret_cast<const d2_t*>(&Bs[buf][wc * 64 + i * 16 + li][4 * lg + 2 * h]);
+                av[i] = LA::frag(As[buf], wr * 64 + i * 16 + li, 4 * lg + 2 * h);
+                bv[i] = LB::frag(Bs[buf], wc * 64 + i * 16 + li, 4 * lg + 2 * h);
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s)
