@@ -36,6 +36,21 @@ template <int R, int NT, bool kcontig>
 __device__ __forceinline__ void load_slab(Slab<R, NT>& sl, const double* __restrict__ P, int64_t ld,
                                           bool vec, int64_t r0, int64_t rlim, int64_t k0,
                                           int64_t klim, int tid) {
+    // Whole slab inside the operand: one branch for the workgroup and plain
+    // 16-byte loads (the per-chunk checks below keep the compiler from
+    // overlapping the loads).
+    if (vec && r0 + R <= rlim && k0 + GBK <= klim) {
+#pragma unroll
+        for (int c = 0; c < Slab<R, NT>::PER; ++c) {
+            const int idx = tid + c * NT;
+            if (Slab<R, NT>::CH % NT != 0 && idx >= Slab<R, NT>::CH) break;
+            if constexpr (kcontig)
+                sl.v[c] = *reinterpret_cast<const d2_t*>(P + (r0 + idx / (GBK / 2)) * ld + k0 + (idx % (GBK / 2)) * 2);
+            else
+                sl.v[c] = *reinterpret_cast<const d2_t*>(P + (k0 + idx / (R / 2)) * ld + r0 + (idx % (R / 2)) * 2);
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < Slab<R, NT>::PER; ++c) {
         const int idx = tid + c * NT;
@@ -143,6 +158,10 @@ __global__ __launch_bounds__(128 * WGN, (WGN == 2 ? 2 : 1)) void gemm_f64_kernel
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
+        // vmcnt(0), already met: the previous stage's loads went to LDS before
+        // its barrier.  Without it the compiler assumes loads of other paths
+        // may be in flight and waits between this stage's loads.
+        __builtin_amdgcn_s_waitcnt(0x0f70);
         if (more) {
             const int64_t k0 = kbeg + (kt + 1) * GBK;
             load_slab<TILE_M, NT, A_KC>(ra, g.A, g.lda, avec, m0, g.M, k0, kend, tid);

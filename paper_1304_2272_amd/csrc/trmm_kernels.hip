@@ -172,9 +172,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     // offsets from a per-tile base.  L^-1 takes its chunk and stage offsets
     // in scalar registers and never leaves the tile's rows.  The dosage
     // offset is all in the vector operand, which the descriptor's range
-    // check covers: columns past the block read as zero (a column is whole
-    // 16-byte chunks, since ldx bytes are a multiple of 16), and elements
-    // k >= n of the last stages are cleared here.
+    // check covers: chunks past the block's data read as zero (chunks are
+    // 16-byte aligned in every column, since ldx bytes are a multiple of
+    // 16), and elements k >= n of the last stages are cleared here.
     constexpr bool BUF = S::SUM32;
     __amdgpu_buffer_rsrc_t rsA, rsB;
     int voA = 0, voB = 0;
@@ -182,9 +182,13 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         static_assert(A_CHUNKS % NT == 0 && B_CHUNKS % NT == 0 && NT % CPC == 0, "whole chunks per lane");
         rsA = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(Ut + r0 * row_bytes), (short)0,
                                                 (int)(TM * row_bytes), 0x00020000);
+        // the range ends with the 16-byte chunk that holds element n - 1 of
+        // the tile's last column: the caller's array need not extend to ldx
+        // there
         const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
+        const int64_t xbytes = ((xcols - 1) * a.ldx + a.n) * (int64_t)sizeof(XT);
         rsB = __builtin_amdgcn_make_buffer_rsrc(const_cast<XT*>(X + c0 * a.ldx), (short)0,
-                                                (int)(xcols * a.ldx * (int64_t)sizeof(XT)), 0x00020000);
+                                                (int)((xbytes + 15) / 16 * 16), 0x00020000);
         voA = (tid >> 3) * (int)row_bytes + (tid & 7) * 16;
         voB = (tid / CPC) * (int)(a.ldx * (int64_t)sizeof(XT)) + (tid % CPC) * 16;
     }
@@ -249,7 +253,25 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 const int64_t gcol = c0 + col;
                 const int64_t k0 = kt * BK + ch * EPC;
                 const XT* src = X + gcol * a.ldx + k0;
-                if (gcol < a.cols && k0 + EPC <= a.n) {
+                if constexpr (sizeof(AT) == 8) {
+                    // A chunk whose column is in the block and whose first
+                    // element is below n lies inside the caller's array (ldx
+                    // bytes are a multiple of 16): load it whole and clear its
+                    // elements k >= n in registers, so the chunk stays one
+                    // 16-byte value on every path and the compiler need not
+                    // unpack it (and wait for it) right after the load.
+                    u4_t v = u4_t{0u, 0u, 0u, 0u};
+                    if (gcol < a.cols && k0 < a.n) v = *reinterpret_cast<const u4_t*>(src);
+                    if (k0 + EPC > a.n) {
+                        const int vb = (int)std::min<int64_t>(16, std::max<int64_t>(0, (a.n - k0) * (int64_t)sizeof(XT)));
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const int keep = std::min(4, std::max(0, vb - 4 * w));
+                            v[w] &= keep >= 4 ? 0xffffffffu : ((1u << (8 * keep)) - 1u);
+                        }
+                    }
+                    rb[c] = v;
+                } else if (gcol < a.cols && k0 + EPC <= a.n) {
                     rb[c] = *reinterpret_cast<const u4_t*>(src);
                 } else {
                     XT tmp[EPC] __attribute__((aligned(16)));
@@ -269,6 +291,12 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         }
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
+            // An empty register-only asm: the float64 product's dosage chunk
+            // is taken apart here, not right after its load, where the
+            // compiler would otherwise move the unpacking and wait for the
+            // load (+2%; the reduced-precision shapes measured slower or
+            // spilled with it).
+            if constexpr (sizeof(AT) == 8) asm volatile("" : "+v"(rb[c]));
             const int idx = tid + c * NT;
             if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
                 const int col = idx / CPC, ch = idx % CPC;
