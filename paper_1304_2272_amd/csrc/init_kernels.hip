@@ -229,6 +229,8 @@ __global__ __launch_bounds__(64) void chol_leaf_kernel(double* L, double* U, int
         __syncthreads();
         if (i > j) {
             const double lij = A[i][j];
+            // iterations are independent: unrolled, their LDS reads overlap
+#pragma unroll 8
             for (int k = j + 1; k <= i; ++k) A[i][k] -= lij * A[k][j];
         }
         __syncthreads();
@@ -240,6 +242,7 @@ __global__ __launch_bounds__(64) void chol_leaf_kernel(double* L, double* U, int
             double x = 0.0;
             if (r >= c) {
                 double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll 8
                 for (int k = c; k < r; ++k) s -= A[r][k] * X[k][c];
                 x = s / A[r][r];
             }
