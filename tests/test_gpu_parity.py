@@ -117,6 +117,33 @@ def test_partition_independence_and_device_io():
     assert np.array_equal(vd.cpu().numpy(), v1)
 
 
+@pytest.mark.parametrize("precision,x_dtype", [("fp64", "i8"), ("fp64", "f64"), ("fp32", "i8"), ("bf16", "i8"),
+                                               ("int8", "i8"), ("fp32", "f64")])
+def test_strided_device_dosages_ignore_padding(precision, x_dtype):
+    # dosages read straight from a device array whose columns are ldx > n
+    # apart, with garbage between element n-1 and the next column: the
+    # products load whole 16-byte chunks and clear (or range-check) what lies
+    # past n, so the result equals the compact input bit for bit
+    import torch
+    n, p, m, seed = 777, 4, 700, 41
+    _say(f"strided {precision} x={x_dtype} n={n} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    dt = np.int8 if x_dtype == "i8" else np.float64
+    XR = synth.snp_block(n, seed, 0, m, dtype=dt)
+    dev = torch.device("cuda:0")
+    ldx = (n + 15) // 16 * 16 + 32
+    big = torch.full((m, ldx), 99 if x_dtype == "i8" else 1e300, dtype=torch.from_numpy(XR).dtype, device=dev)
+    big[:, :n] = torch.from_numpy(XR).to(dev)
+    strided = big[:, :n]
+    assert strided.stride(0) == ldx
+    kw = dict(precision=precision, x_dtype=x_dtype, dev_block=256)
+    b0, v0, i0 = run(prob, torch.from_numpy(XR).to(dev).contiguous(), **kw)
+    b1, v1, i1 = run(prob, strided, **kw)
+    torch.cuda.synchronize()
+    assert torch_equal(i0.cpu(), i1.cpu())
+    assert torch_equal(b0.cpu(), b1.cpu()) and torch_equal(v0.cpu(), v1.cpu())
+
+
 def test_traits_and_max_p():
     n, p, t, m, seed = 600, 20, 5, 700, 44
     _say(f"traits n={n} p={p} t={t} m={m}")
