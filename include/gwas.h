@@ -193,7 +193,17 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * padded n, precision, dosage type and width is reused and new results are
  * appended.  *best_cfg (may be NULL) receives the chosen shape, -1 for
  * GWAS_INT8_SLICED (one shape); *best_rgroup (may be NULL) the row group.
- * Results of later calls are unchanged up to float64 rounding order.
+ * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged
+ * up to float64 rounding order.  For the float32 and bfloat16 products a
+ * shape also decides how their sums are kept: the 256 x 256 shape (6, the
+ * default with int8 dosages) keeps float32 sums, the others move them to
+ * float64 every 16 stages; b stays within the precision's stated error
+ * either way.
+ *
+ * The environment variable GWAS_TRMM_CFG (read by gwas_init) overrides the
+ * default shape with one the autotuner would try (0..6; ignored when the
+ * shape does not apply to the precision and dosage type): a measurement
+ * and test aid.
  */
 int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
                   int32_t* best_rgroup);

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 
     // the tile coordinates are the workgroup's: scalar registers, so that
     // every quantity derived from them (K range, addresses, loop bound) is
+    // scalar too
     const int e0 = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x]);
     const int J = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x + 1]);
     if (e0 < 0) return;
@@ -396,9 +397,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 mma_piece(pa[q % SETS], pb[q % SETS]);
                 // the other buffer held stage kt - 1, which every wave
                 // finished reading before the previous barrier.  Float32
-                // writes it after the first piece (141 against 138 TFLOP/s
-                // after the last at n = 50,000); bfloat16 after the last
-                // (1,180 against 1,090), as does the float64 product.
+                // writes it after the first piece (141.1 against 139.8
+                // TFLOP/s after the last at n = 50,000); bfloat16 after the
+                // last (1,180 against 1,090), as does the float64 product.
                 if (q == (SETS == 2 ? 0 : NQ - 1) && more) store(buf ^ 1);
                 // one piece's reads and instructions at a time
                 __builtin_amdgcn_sched_barrier(0);
