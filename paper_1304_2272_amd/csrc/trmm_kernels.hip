@@ -603,15 +603,17 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 }
 
 // Measured on MI355X at n = 50,000 with int8 dosages (one 50,000-SNP block):
-// float64 is fastest in the 128 x 256 tile; float32 and bfloat16 in the
-// 256 x 256 tile of 64 x 128 waves with float32 sums (141 and 1,180
-// TFLOP/s, against 131 and 870 in the 128 x 256 tile with float64 sums;
-// b moves from 6e-11 to 4e-10 of the float64 path for float32, and not
-// measurably for bfloat16, whose rounding of L^-1 dominates).  With float64
-// dosages the reduced-precision products take the 128 x 128 tile of
-// 64 x 32 waves.
+// float64 is fastest in the 128 x 128 tile of 32 x 64 waves (67.5 TFLOP/s,
+// against 66.0 in the 128 x 256 tile, 67.3 in the 256 x 128 tile); float32
+// and bfloat16 in the 256 x 256 tile of 64 x 128 waves with float32 sums
+// (141 and 1,180 TFLOP/s, against 131 and 870 in the 128 x 256 tile with
+// float64 sums; b moves from 6e-11 to 4e-10 of the float64 path for
+// float32, and not measurably for bfloat16, whose rounding of L^-1
+// dominates).  With float64 dosages the float64 product keeps the
+// 128 x 256 tile and the reduced-precision products take the 128 x 128
+// tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
-    if (at == A_F64) return 3;
+    if (at == A_F64) return xt == X_I8 ? 2 : 3;
     if (xt == X_I8) return 6;
     return 1;
 }
