@@ -34,7 +34,7 @@ struct Layout {
     int p, t, q1, Qc, precision, x_dtype, slices;
     size_t off_L, off_U, off_Ulow, off_rscale, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
-    size_t off_xbuf[2], off_part, off_red, off_xw, off_b[2], off_v[2], off_i[2];
+    size_t off_xbuf[2], off_part, off_red, off_xw, off_xwpart, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
     size_t sched_len;
     size_t total;
@@ -116,6 +116,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_part = rtake((size_t)L.npb_max * L.Q * L.dev_block * 8);
     L.off_red = rtake((size_t)chunks_of(L.npb_max) * L.Q * L.dev_block * 8);
     L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
+    L.off_xwpart = (precision != GWAS_FP64) ? rtake((size_t)xw_splits(n) * L.Qc * L.dev_block * 8) : 0;
     for (int s = 0; s < 2; ++s) {
         L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
         L.off_v[s] = rtake((size_t)L.dev_block * 8);
@@ -159,6 +160,7 @@ struct gwas_ctx {
     double* part = nullptr;
     double* red = nullptr;          // chunk totals of part
     double* xw = nullptr;
+    double* xwpart = nullptr;       // split-K partial sums of xw
     double* bbuf[2] = {nullptr, nullptr};
     double* vbuf[2] = {nullptr, nullptr};
     int* ibuf[2] = {nullptr, nullptr};
@@ -434,7 +436,8 @@ hipError_t finish_sub(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t 
     const Layout& Y = c->lay;
     if (Y.precision != GWAS_FP64) {
         hipError_t e = snp_cross_w((Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64, xptr, xld, Y.n, cols, c->W,
-                                   Y.n_pad, Y.Qc, c->xw, Y.dev_block, s);
+                                   Y.n_pad, Y.Qc, c->xw, Y.dev_block, c->xwpart,
+                                   (int64_t)xw_splits(Y.n) * Y.Qc * Y.dev_block, s);
         if (e != hipSuccess) return e;
     }
     hipError_t e = partial_chunks(c->part, Y.dev_block, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
@@ -590,6 +593,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->part = (double*)(w + Y.off_part);
     c->red = (double*)(w + Y.off_red);
     c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
+    c->xwpart = Y.off_xwpart ? (double*)(w + Y.off_xwpart) : nullptr;
     c->tmp = (double*)(w + Y.off_tmp);
 
     // The library computes on streams of its own (default priority); work the
@@ -1155,7 +1159,7 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
         ta.n_sched = ns;
         ta.full_k = 1;
         HIPCHK(c, trmm_stream(ta, s));
-        HIPCHK(c, snp_cross_w(xt, xptr, xld, Y.n, cols, B->W, Y.n_pad, p, B->xw, blk, s));
+        HIPCHK(c, snp_cross_w(xt, xptr, xld, Y.n, cols, B->W, Y.n_pad, p, B->xw, blk, nullptr, 0, s));
         HIPCHK(c, partial_chunks(B->part, blk, Y.n_pad / sh.part_rows, p + 1, cols, PART_CHUNK, B->red, blk, s));
         BackArgs ba{};
         ba.p = p;

@@ -134,10 +134,14 @@ int64_t trmm_schedule(int64_t n_pad, int64_t cols, const TrmmShape& sh, int* out
 int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, const TrmmShape& sh);
 // (trmm_schedule_multi, the multi-context form, is in schedule.h)
 
-// xw[q * ldxw + j] = x_j^T W[:, q] for q < Qc (float64 accumulation).
+// xw[q * ldxw + j] = x_j^T W[:, q] for q < Qc (float64 matrix cores).  W has
+// ldw >= n rounded up to 16 rows, zero past n.  With part (room for
+// part_cap doubles, at least xw_splits(n) * Qc * cols) K is split in chunks
+// fixed by n and the partial sums are added in order; without it, one split.
+int xw_splits(int64_t n);
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw,
-                       int64_t ldxw, hipStream_t s);
+                       int64_t ldxw, double* part, int64_t part_cap, hipStream_t s);
 
 // Reverse mode through the per-SNP solves (one trait).  For SNP j, with the
 // Cholesky factor of S_j from R = chol(S_TL), S_BL = x^T W_L and s = 1/var,

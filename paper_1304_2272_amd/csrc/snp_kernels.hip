@@ -16,47 +16,159 @@
 namespace gwas {
 namespace {
 
-// x_j^T W[:, q]: each wave takes 8 SNP columns, lanes stride over k.
-constexpr int XW_COLS = 8;
-constexpr int XW_Q = 8;
-template <typename XT>
-__global__ __launch_bounds__(256) void snp_cross_w_kernel(const XT* __restrict__ X, int64_t ldx,
-                                                          int64_t n, int64_t cols,
-                                                          const double* __restrict__ W, int64_t ldw,
-                                                          int Qc, double* __restrict__ xw,
-                                                          int64_t ldxw) {
-    const int lane = threadIdx.x & 63;
-    const int64_t colbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * XW_COLS;
-    if (colbase >= cols) return;
-    for (int q0 = 0; q0 < Qc; q0 += XW_Q) {
-        double s[XW_COLS][XW_Q];
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
+
+// x_j^T W[:, q] on the float64 matrix cores: C (SNPs x Qc) = X^T W with K = n.
+// A workgroup of 4 waves takes 256 SNPs (a wave 64, as 4 blocks of 16) and
+// WQ blocks of 16 columns of W, over one K split of klen rows (XW_KSPLIT,
+// or all of n in a single split).  The splits depend on n alone, so the sums
+// of a SNP do not depend on the block it comes in; with several splits each
+// writes its partial sums and xw_reduce_kernel adds them in split order.  Stages of 16 k go through
+// LDS: a thread's dosage chunk is one SNP's 16 k, loaded whole when its
+// first element is below n (inside the array, since ldx bytes are a
+// multiple of 16) and cleared past n in registers.
+constexpr int XW_BK = 16;
+constexpr int XW_KSPLIT = 2048;
+constexpr int XW_WAVES = 4;
+constexpr int XW_QMAX = 80;         // columns of W per workgroup (5 blocks)
+
+template <typename XT, int WQ>
+__global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
+                                                           int64_t cols, const double* __restrict__ W,
+                                                           int64_t ldw, int Qc, double* __restrict__ out,
+                                                           int64_t ldo, int64_t split_stride, int64_t klen) {
+    constexpr int NT = 64 * XW_WAVES;
+    constexpr int TC = 64 * XW_WAVES;               // SNPs per workgroup, one per thread
+    constexpr int TQ = 16 * WQ;
+    constexpr int XLD = sizeof(XT) == 1 ? XW_BK : XW_BK + 1;   // LDS row of a SNP (elements)
+    constexpr int WLD = XW_BK + 1;                  // LDS row of a column of W (doubles)
+    constexpr int CPC = XW_BK * (int)sizeof(XT) / 16;          // 16-byte chunks per SNP per stage
+    constexpr int EPC = 16 / (int)sizeof(XT);
+    __shared__ __attribute__((aligned(16))) XT Xs[2][TC * XLD];
+    __shared__ double Ws[2][TQ * WLD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t c0 = (int64_t)blockIdx.x * TC;
+    const int split = blockIdx.y;
+    const int q0 = blockIdx.z * TQ;
+    const int64_t kbeg = (int64_t)split * klen;
+    const int64_t kend = std::min<int64_t>(n, kbeg + klen);
+    const int nst = (int)((kend - kbeg + XW_BK - 1) / XW_BK);
+
+    u4_t rx[CPC];
+    double rw[(TQ * XW_BK / 2 + NT - 1) / NT][2];
+    auto load = [&](int st) {
+        const int64_t k0 = kbeg + (int64_t)st * XW_BK;
+        const int64_t col = c0 + tid;
 #pragma unroll
-        for (int c = 0; c < XW_COLS; ++c)
+        for (int c = 0; c < CPC; ++c) {
+            const int64_t kc = k0 + c * EPC;
+            u4_t v = u4_t{0u, 0u, 0u, 0u};
+            if (col < cols && kc < n) v = *reinterpret_cast<const u4_t*>(X + col * ldx + kc);
+            if (kc + EPC > n) {
+                const int vb = (int)std::min<int64_t>(16, std::max<int64_t>(0, (n - kc) * (int64_t)sizeof(XT)));
 #pragma unroll
-            for (int q = 0; q < XW_Q; ++q) s[c][q] = 0.0;
-        for (int64_t k = lane; k < n; k += 64) {
-            double w[XW_Q];
+                for (int w = 0; w < 4; ++w) {
+                    const int keep = std::min(4, std::max(0, vb - 4 * w));
+                    v[w] &= keep >= 4 ? 0xffffffffu : ((1u << (8 * keep)) - 1u);
+                }
+            }
+            rx[c] = v;
+        }
+        // W rows k0..k0+15 lie below n_pad = ldw, zero past n
 #pragma unroll
-            for (int q = 0; q < XW_Q; ++q) w[q] = (q0 + q < Qc) ? W[k + (q0 + q) * ldw] : 0.0;
+        for (int c = 0; c < (TQ * XW_BK / 2 + NT - 1) / NT; ++c) {
+            const int idx = tid + c * NT;
+            const int q = idx / (XW_BK / 2), kk = (idx % (XW_BK / 2)) * 2;
+            const bool ok = idx < TQ * XW_BK / 2 && q0 + q < Qc;
+            const double* src = W + (q0 + q) * ldw + k0 + kk;
+            rw[c][0] = ok ? src[0] : 0.0;
+            rw[c][1] = ok ? src[1] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
 #pragma unroll
-            for (int c = 0; c < XW_COLS; ++c) {
-                const int64_t col = colbase + c;
-                const double x = (col < cols) ? (double)X[col * ldx + k] : 0.0;
-#pragma unroll
-                for (int q = 0; q < XW_Q; ++q) s[c][q] += x * w[q];
+        for (int c = 0; c < CPC; ++c) {
+            if constexpr (sizeof(XT) == 1) {
+                *reinterpret_cast<u4_t*>(Xs[buf] + tid * XLD + c * EPC) = rx[c];
+            } else {
+                // the chunk's two doubles, by value (elements copied to
+                // scalars before the bit cast)
+                const uint32_t w0 = rx[c][0], w1 = rx[c][1], w2 = rx[c][2], w3 = rx[c][3];
+                Xs[buf][tid * XLD + c * EPC] = __builtin_bit_cast(double, u2_t{w0, w1});
+                Xs[buf][tid * XLD + c * EPC + 1] = __builtin_bit_cast(double, u2_t{w2, w3});
             }
         }
 #pragma unroll
-        for (int c = 0; c < XW_COLS; ++c)
-#pragma unroll
-            for (int q = 0; q < XW_Q; ++q) {
-                double v = s[c][q];
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-                const int64_t col = colbase + c;
-                if (lane == 0 && col < cols && q0 + q < Qc) xw[(q0 + q) * ldxw + col] = v;
+        for (int c = 0; c < (TQ * XW_BK / 2 + NT - 1) / NT; ++c) {
+            const int idx = tid + c * NT;
+            if (idx < TQ * XW_BK / 2) {
+                const int q = idx / (XW_BK / 2), kk = (idx % (XW_BK / 2)) * 2;
+                Ws[buf][q * WLD + kk] = rw[c][0];
+                Ws[buf][q * WLD + kk + 1] = rw[c][1];
             }
+        }
+    };
+
+    d4_t acc[4][WQ];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int qb = 0; qb < WQ; ++qb) acc[cb][qb] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nst;
+        if (more) load(st + 1);
+        // lane group g supplies k = 4 step + g of the stage to both operands
+#pragma unroll
+        for (int step = 0; step < XW_BK / 4; ++step) {
+            const int k = 4 * step + lg;
+            double a[4], b[WQ];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) a[cb] = (double)Xs[buf][(wave * 64 + cb * 16 + li) * XLD + k];
+#pragma unroll
+            for (int qb = 0; qb < WQ; ++qb) b[qb] = Ws[buf][(qb * 16 + li) * WLD + k];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int qb = 0; qb < WQ; ++qb)
+                    acc[cb][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cb], b[qb], acc[cb][qb], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
     }
+    // element v of a lane: SNP (A row) lane/16 + 4v of the block, column of
+    // W (B column) lane%16
+    double* o = out + (int64_t)split * split_stride;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int qb = 0; qb < WQ; ++qb) {
+            const int q = q0 + qb * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + wave * 64 + cb * 16 + lg + 4 * v;
+                if (q < Qc && col < cols) o[(int64_t)q * ldo + col] = acc[cb][qb][v];
+            }
+        }
+}
+
+// xw[q * ldxw + j] = sum over splits, in split order, of the partial sums.
+__global__ __launch_bounds__(256) void xw_reduce_kernel(const double* __restrict__ part, int splits, int Qc,
+                                                        int64_t cols, double* __restrict__ xw, int64_t ldxw) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)Qc * cols) return;
+    const int64_t q = i / cols, j = i % cols;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += part[((int64_t)sp * Qc + q) * cols + j];
+    xw[q * ldxw + j] = s;
 }
 
 // One thread per SNP.  With R = chol(S_TL) fixed, the Cholesky factor of
@@ -330,19 +442,50 @@ __global__ __launch_bounds__(256) void dosage_gemv_kernel(const XT* __restrict__
 
 }  // namespace
 
+int xw_splits(int64_t n) { return (int)std::max<int64_t>(1, (n + XW_KSPLIT - 1) / XW_KSPLIT); }
+
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw, int64_t ldxw,
-                       hipStream_t s) {
+                       double* part, int64_t part_cap, hipStream_t s) {
     if (cols <= 0) return hipSuccess;
-    if (!X || !W || !xw || ldx < n || ldw < n || ldxw < cols || Qc < 1) return hipErrorInvalidValue;
-    const int64_t waves = (cols + XW_COLS - 1) / XW_COLS;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
-    if (xt == X_I8)
-        hipLaunchKernelGGL(snp_cross_w_kernel<int8_t>, dim3(grid), dim3(256), 0, s,
-                           (const int8_t*)X, ldx, n, cols, W, ldw, Qc, xw, ldxw);
-    else
-        hipLaunchKernelGGL(snp_cross_w_kernel<double>, dim3(grid), dim3(256), 0, s,
-                           (const double*)X, ldx, n, cols, W, ldw, Qc, xw, ldxw);
+    if (!X || !W || !xw || n < 1 || ldx < n || ldw < (n + XW_BK - 1) / XW_BK * XW_BK || ldxw < cols || Qc < 1)
+        return hipErrorInvalidValue;
+    const size_t xs = xt == X_I8 ? 1 : 8;
+    if ((reinterpret_cast<uintptr_t>(X) % 16) || ((ldx * (int64_t)xs) % 16)) return hipErrorInvalidValue;
+    // K splits: from n alone when there is room for the partial sums
+    const int splits = part ? xw_splits(n) : 1;
+    if (splits > 1 && part_cap < (int64_t)splits * Qc * cols) return hipErrorInvalidValue;
+    const int qchunks = (Qc + XW_QMAX - 1) / XW_QMAX;
+    const int wq = qchunks > 1 ? XW_QMAX / 16 : (Qc + 15) / 16;
+    const dim3 grid((unsigned)((cols + 64 * XW_WAVES - 1) / (64 * XW_WAVES)), (unsigned)splits, (unsigned)qchunks);
+    double* out = splits > 1 ? part : xw;
+    const int64_t ldo = splits > 1 ? cols : ldxw;
+    const int64_t stride = splits > 1 ? (int64_t)Qc * cols : 0;
+    // rows of X per split: a multiple of XW_BK, so only the last split is ragged
+    const int64_t klen = splits > 1 ? (int64_t)XW_KSPLIT : (n + XW_BK - 1) / XW_BK * XW_BK;
+#define GWAS_XW(T, WQ)                                                                                 \
+    hipLaunchKernelGGL((xw_kernel<T, WQ>), grid, dim3(64 * XW_WAVES), 0, s, (const T*)X, ldx, n, cols, \
+                       W, ldw, Qc, out, ldo, stride, klen)
+#define GWAS_XW_T(T)                        \
+    switch (wq) {                           \
+        case 1: GWAS_XW(T, 1); break;       \
+        case 2: GWAS_XW(T, 2); break;       \
+        case 3: GWAS_XW(T, 3); break;       \
+        case 4: GWAS_XW(T, 4); break;       \
+        default: GWAS_XW(T, 5); break;      \
+    }
+    if (xt == X_I8) {
+        GWAS_XW_T(int8_t)
+    } else {
+        GWAS_XW_T(double)
+    }
+#undef GWAS_XW_T
+#undef GWAS_XW
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splits == 1) return e;
+    const int64_t total = (int64_t)Qc * cols;
+    hipLaunchKernelGGL(xw_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, part, splits, Qc,
+                       cols, xw, ldxw);
     return hipGetLastError();
 }
 
