@@ -421,3 +421,21 @@ def test_many_traits():
         err = normwise(b, bo)
         _say(f"  {precision}: err {err:.3e}")
         assert b.shape == (m, t, p) and err < tol
+
+
+@pytest.mark.parametrize("precision,x_dtype,tol", [("fp32", "f64", TOL_FP32), ("fp32", "i8", TOL_FP32),
+                                                   ("int8", "i8", TOL_FP64)])
+def test_cross_products_k_splits_and_wide_w(precision, x_dtype, tol):
+    # The reduced-precision modes form x_i^T [W_L | w_y] on their own: odd n
+    # past two K splits of 2,048 rows (the last one ragged), p-1+t = 82
+    # columns of W (past the 80 one workgroup takes) and a ragged SNP tile.
+    n, p, t, m, seed = 4099, 3, 80, 300, 83
+    _say(f"cross products {precision} x={x_dtype} n={n} p={p} t={t} m={m}")
+    prob = synth.make_problem(n, p, seed, t=t)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    b, var, info = run(prob, XR, precision=precision, x_dtype=x_dtype, dev_block=512)
+    assert np.array_equal(info, io)
+    err = normwise(b, bo)
+    _say(f"  err {err:.3e}")
+    assert b.shape == (m, t, p) and err < tol
