@@ -640,7 +640,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     const char* xr = static_cast<const char*>(XR);
     const bool x_dev = on_device(XR);
     const bool direct_x = x_dev && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
-                          ((ldx * (int64_t)elem) % 16 == 0);
+                          ((ldx * (int64_t)elem) % 16 == 0) && ldx * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES;
     const bool direct_out = on_device(b) && (!var_snp || on_device(var_snp)) &&
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
@@ -769,7 +769,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
     std::vector<char> direct_x(nctx), direct_out(nctx);
     for (int i = 0; i < nctx; ++i) {
         direct_x[i] = on_device(XR[i]) && (reinterpret_cast<uintptr_t>(XR[i]) % 16 == 0) &&
-                      ((ldx[i] * (int64_t)elem) % 16 == 0);
+                      ((ldx[i] * (int64_t)elem) % 16 == 0) && ldx[i] * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES;
         direct_out[i] = on_device(b[i]) && (!var_snp || !var_snp[i] || on_device(var_snp[i])) &&
                         (!info || !info[i] || on_device(info[i]));
     }
@@ -1109,7 +1109,7 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
     const int cfg = trmm_default_cfg(A_F64, xt);
     const TrmmShape sh = trmm_geom(A_F64, xt, cfg, 0);
     const bool direct_x = on_device(XR) && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
-                          ((ldx * (int64_t)elem) % 16 == 0);
+                          ((ldx * (int64_t)elem) % 16 == 0) && ldx * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES;
     const int64_t blk = Y.dev_block;
     for (int64_t col0 = 0; col0 < mblk; col0 += blk) {
         const int64_t cols = std::min<int64_t>(blk, mblk - col0);

@@ -71,6 +71,12 @@ __host__ __device__ inline int64_t consts_bT(int q1, int t) { return 2 * (int64_
 __host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64_t)q1 * q1 + 2 * (int64_t)q1 * t; }
 
 // ---- streaming kernels ---------------------------------------------------
+// Dosage columns are read in place only with a column stride of at most this
+// many bytes: a tile of up to 256 columns then spans less than 2^31 bytes,
+// which the 32-bit offsets of the products' buffer loads need.  Wider
+// strides go through the library's staging buffer.
+constexpr int64_t X_DIRECT_MAX_LD_BYTES = int64_t(4) << 20;
+
 enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2, A_I8S = 3 };
 enum XType : int { X_F64 = 0, X_I8 = 1 };
 

@@ -663,10 +663,10 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     const TrmmShape sh = trmm_geom(a.at, a.xt, a.cfg, a.slices, a.rgroup);
     if (a.n_pad % sh.tm) return hipErrorInvalidValue;
     // 32-bit buffer offsets of the SUM32 shapes: a tile's rows of L^-1 and
-    // its dosage columns
+    // its dosage columns up to the last stage
     if (a.at != A_I8S && trmm_shape_sum32(a.cfg)) {
         const int64_t asz = a.at == A_F32 ? 4 : 2;
-        if ((int64_t)sh.tm * a.ldu * asz > INT32_MAX || (int64_t)sh.tn * a.ldx * (int64_t)xs > INT32_MAX)
+        if ((int64_t)sh.tm * a.ldu * asz > INT32_MAX || ((int64_t)sh.tn * a.ldx + a.n_pad) * (int64_t)xs > INT32_MAX)
             return hipErrorInvalidValue;
     }
     if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh)))

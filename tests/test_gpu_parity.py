@@ -439,3 +439,27 @@ def test_cross_products_k_splits_and_wide_w(precision, x_dtype, tol):
     err = normwise(b, bo)
     _say(f"  err {err:.3e}")
     assert b.shape == (m, t, p) and err < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "int8", "fp64"])
+def test_wide_stride_device_dosages_are_staged(precision):
+    # A device array whose columns are 9 MB apart: 256 such columns span
+    # more than 2^31 bytes, past the 32-bit offsets of the products' buffer
+    # loads, so the library stages the block and gives the compact input's
+    # result bit for bit.
+    import torch
+    n, p, m, seed, ldx = 300, 4, 3, 47, 9_000_000
+    _say(f"wide stride {precision} n={n} m={m} ldx={ldx}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    dev = torch.device("cuda:0")
+    big = torch.zeros((m, ldx), dtype=torch.int8, device=dev)
+    big[:, :n] = torch.from_numpy(XR).to(dev)
+    wide = big[:, :n]
+    assert wide.stride(0) == ldx
+    kw = dict(precision=precision, x_dtype="i8")
+    b0, v0, i0 = run(prob, torch.from_numpy(XR).to(dev).contiguous(), **kw)
+    b1, v1, i1 = run(prob, wide, **kw)
+    torch.cuda.synchronize()
+    assert torch_equal(i0.cpu(), i1.cpu())
+    assert torch_equal(b0.cpu(), b1.cpu()) and torch_equal(v0.cpu(), v1.cpu())
