@@ -140,6 +140,9 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d);
  * double-buffered between host-to-device copies and compute).
  *
  *   XR       n x mblk dosages (x_dtype), column i = SNP i, host or device.
+ *            Device dosages are read in place when XR is 16-byte aligned
+ *            and ldx spans a multiple of 16 bytes, at most 4 MiB; otherwise
+ *            each sub-block is first copied into the library's buffer.
  *   ldx      >= n, elements between consecutive SNP columns.
  *   b        output, p*t doubles per SNP at b + i*ldb (host or device).
  *   ldb      >= p*t.
