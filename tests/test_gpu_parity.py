@@ -463,3 +463,22 @@ def test_wide_stride_device_dosages_are_staged(precision):
     torch.cuda.synchronize()
     assert torch_equal(i0.cpu(), i1.cpu())
     assert torch_equal(b0.cpu(), b1.cpu()) and torch_equal(v0.cpu(), v1.cpu())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "int8"])
+def test_reduced_precision_partition_independence(precision):
+    # A SNP lands at a different row of the matrix-core tiles (product and
+    # cross products) depending on its offset in the block; its bits must
+    # not change.  n spans two K splits of the cross products.
+    n, p, m, seed = 2500, 4, 1200, 37
+    _say(f"partition {precision} n={n} p={p} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    kw = dict(precision=precision, x_dtype="i8")
+    b1, v1, i1 = run(prob, XR, dev_block=256, **kw)
+    b2, v2, i2 = run(prob, XR, dev_block=1024, **kw)
+    assert np.array_equal(i1, i2)
+    assert np.array_equal(b1, b2) and np.array_equal(v1, v2)
+    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], dev_block=512, **kw) as ctx:
+        parts = [ctx.stream_block(XR[a:b_])[0] for a, b_ in [(0, 1), (1, 333), (333, m)]]
+    assert np.array_equal(np.concatenate(parts), b1)
