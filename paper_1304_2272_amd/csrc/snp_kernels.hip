@@ -1,6 +1,7 @@
 // Per-SNP kernels of the per-block hot path (Algorithm 2, loop body) and of
 // its reverse pass:
-//   snp_cross_w     x^T W with W = M^-1 [X_L | y] (reduced-precision paths);
+//   snp_cross_w     x^T W with W = M^-1 [X_L | y] on the float64 matrix cores
+//                   (reduced-precision paths and the reverse pass);
 //   partial_chunks  the triangular product's partial sums reduced in chunks;
 //   snp_solve       per-SNP p x p Cholesky solve (Algorithm 1, last two lines
 //                   of the loop) with optional float64 refinement;
