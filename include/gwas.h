@@ -154,7 +154,9 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d);
  * Returns after every output has been written (synchronous for the caller,
  * pipelined inside).  mblk = 0 is a no-op.  Results for a SNP do not depend
  * on the block it arrives in.  On a device error the context is poisoned and
- * later calls return GWAS_E_STATE.
+ * later calls return GWAS_E_STATE; the work the failed call queued is
+ * finished before it returns, so no copy into the caller's buffers is still
+ * running.
  */
 int gwas_stream_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
                       double* b, int64_t ldb, double* var_snp, int32_t* info);
@@ -245,6 +247,17 @@ int gwas_backward_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk
                         const int32_t* info, const double* gb, int64_t ldgb,
                         const double* gvar);
 int gwas_backward_end(gwas_ctx* ctx, double* gy, double* tr_mbar, double* ip_mbar_m);
+
+/*
+ * Test hook for the error paths.  The k-th HIP status that later calls on
+ * ctx check (k >= 1; 0 turns the hook off) is reported as failed
+ * (hipErrorUnknown), as a real HIP error would be: that call returns
+ * GWAS_E_HIP, the context is poisoned, gwas_last_error names the check and
+ * ends in "(injected)", and the work the call had queued is finished before
+ * it returns.  Nothing fails on the device.  Returns GWAS_E_STATE for a
+ * NULL, freed or poisoned context and GWAS_E_INVALID for k < 0.
+ */
+int gwas_test_inject_fault(gwas_ctx* ctx, int64_t k);
 
 /* Release a context (NULL is accepted).  Later use returns GWAS_E_STATE. */
 int gwas_free(gwas_ctx* ctx);

@@ -32,7 +32,8 @@ X_DTYPES = {"f64": 0, "i8": 1}
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
              "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
-             "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe")
+             "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe",
+             "gwas_test_inject_fault")
 GROUP_GRAPH = 1
 
 
@@ -111,6 +112,8 @@ def load():
     L.gwas_backward_end.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.gwas_peak_probe.restype = ctypes.c_int
     L.gwas_peak_probe.argtypes = [i32, i32, i64, ctypes.POINTER(ctypes.c_double)]
+    L.gwas_test_inject_fault.restype = ctypes.c_int
+    L.gwas_test_inject_fault.argtypes = [vp, i64]
     _lib = L
     return L
 
@@ -314,6 +317,11 @@ class GwasContext:
         self._check(self._lib.gwas_query(self._h, ctypes.byref(npad), ctypes.byref(blk),
                                          ctypes.byref(dev)))
         return {"n_pad": npad.value, "dev_block": blk.value, "device": dev.value}
+
+    def inject_fault(self, k):
+        """Test hook: the k-th HIP status later calls check is reported as a
+        failure (0 turns it off); see gwas_test_inject_fault."""
+        self._check(self._lib.gwas_test_inject_fault(self._h, int(k)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

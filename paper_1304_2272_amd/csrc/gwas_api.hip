@@ -140,6 +140,8 @@ struct gwas_ctx {
     uint64_t magic = CTX_MAGIC;
     uint64_t id = next_ctx_id.fetch_add(1);
     bool poisoned = false;
+    int64_t inject_at = 0;        // test hook: the inject_at-th checked HIP status fails (0 = off)
+    bool injected = false;
     int device = 0;
     Layout lay{};
     char* ws = nullptr;
@@ -216,17 +218,50 @@ struct Group {
 
 namespace {
 
+// Waits for the work a failed call left queued on the context's streams, so
+// that no copy into a caller's buffer is still running when the call
+// returns.  A stream that is being captured is left alone (the capture ends
+// with an error of its own).
+void drain(gwas_ctx* c) {
+    const hipStream_t ss[3] = {c->s_comp, c->s_h2d, c->s_d2h};
+    for (hipStream_t st : ss) {
+        if (!st) continue;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+            (void)hipStreamSynchronize(st);
+    }
+    (void)hipGetLastError();
+}
+
 int fail_hip(gwas_ctx* c, hipError_t e, const char* what) {
     if (c) {
-        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        c->err = std::string(what) + ": " + hipGetErrorString(e) + (c->injected ? " (injected)" : "");
         c->poisoned = true;
+        drain(c);
     }
     return (e == hipErrorOutOfMemory) ? GWAS_E_OOM : GWAS_E_HIP;
+}
+
+// Releases a device object and forgets it before its status is checked, so
+// an object is never released twice, whatever the check reports.
+template <typename T, typename F> hipError_t drop(T*& p, F release_fn) {
+    if (!p) return hipSuccess;
+    const hipError_t e = release_fn(p);
+    p = nullptr;
+    return e;
+}
+
+// the fault-injection test hook counts every checked HIP status
+bool inject_now(gwas_ctx* c) {
+    if (!c || c->inject_at <= 0 || --c->inject_at > 0) return false;
+    c->injected = true;
+    return true;
 }
 
 #define HIPCHK(ctx, expr)                                                         \
     do {                                                                          \
         hipError_t e_ = (expr);                                                   \
+        if (e_ == hipSuccess && inject_now(ctx)) e_ = hipErrorUnknown;            \
         if (e_ != hipSuccess) return fail_hip((ctx), e_, #expr);                  \
     } while (0)
 
@@ -729,7 +764,8 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     return GWAS_OK;
 }
 
-int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR, const int64_t* ldx,
+namespace {
+int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR, const int64_t* ldx,
                       int64_t mblk, double* const* b, const int64_t* ldb, double* const* var_snp,
                       int32_t* const* info, int32_t flags) {
     if (!ctxs || nctx < 1 || nctx > MAX_GROUP || !XR || !ldx || !b || !ldb || mblk < 0)
@@ -788,7 +824,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         const size_t bytes = g->host_sched.size() * sizeof(int);
         HIPCHK(c0, hipStreamSynchronize(s));   // no launch may still read the old schedule
         if (bytes > g->sched_cap) {
-            if (g->d_sched) HIPCHK(c0, hipFree(g->d_sched));
+            HIPCHK(c0, drop(g->d_sched, hipFree));
             g->d_sched = nullptr;
             HIPCHK(c0, hipMalloc((void**)&g->d_sched, bytes));
             g->sched_cap = bytes;
@@ -866,12 +902,9 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         if (use_graph) {
             if (!g->exec || g->graph_key != key) {
                 HIPCHK(c0, hipStreamSynchronize(s));
-                if (g->exec) HIPCHK(c0, hipGraphExecDestroy(g->exec));
-                if (g->graph) HIPCHK(c0, hipGraphDestroy(g->graph));
-                g->exec = nullptr;
-                g->graph = nullptr;
-                if (g->d_sched_graph) HIPCHK(c0, hipFree(g->d_sched_graph));
-                g->d_sched_graph = nullptr;
+                HIPCHK(c0, drop(g->exec, hipGraphExecDestroy));
+                HIPCHK(c0, drop(g->graph, hipGraphDestroy));
+                HIPCHK(c0, drop(g->d_sched_graph, hipFree));
                 if (!g->h_args_graph)
                     HIPCHK(c0, hipHostMalloc((void**)&g->h_args_graph, MAX_GROUP * sizeof(TrmmArgs), 0));
                 if (!g->d_args_graph) HIPCHK(c0, hipMalloc((void**)&g->d_args_graph, MAX_GROUP * sizeof(TrmmArgs)));
@@ -889,14 +922,16 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                 }
                 HIPCHK(c0, hipMemcpy(g->d_args_graph, g->h_args_graph, nctx * sizeof(TrmmArgs),
                                      hipMemcpyHostToDevice));
-                HIPCHK(c0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                // (checked directly: a capture must never be left open)
+                if (const hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal))
+                    return fail_hip(c0, eb, "hipStreamBeginCapture");
                 const int erc = enqueue(g->h_args_graph, g->d_args_graph, g->d_sched_graph, g->n_sched, xp, xl,
                                         bo, lb, vo, io, cols, false, true);
                 hipGraph_t graph = nullptr;
                 const hipError_t ec = hipStreamEndCapture(s, &graph);
+                g->graph = graph;   // owned by the group from here on, whatever fails below
                 if (erc) return erc;
                 HIPCHK(c0, ec);
-                g->graph = graph;
                 HIPCHK(c0, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
                 g->graph_key = key;
             }
@@ -931,6 +966,19 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         }
     }
     return GWAS_OK;
+}
+}  // namespace
+
+int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR, const int64_t* ldx,
+                      int64_t mblk, double* const* b, const int64_t* ldb, double* const* var_snp,
+                      int32_t* const* info, int32_t flags) {
+    const int rc = stream_group_impl(ctxs, nctx, XR, ldx, mblk, b, ldb, var_snp, info, flags);
+    // a device error poisons the first context; the others' queued copies
+    // are waited for too
+    if (rc == GWAS_E_HIP || rc == GWAS_E_OOM)
+        for (int i = 1; i < nctx; ++i)
+            if (ctxs[i] && ctxs[i]->magic == CTX_MAGIC) drain(ctxs[i]);
+    return rc;
 }
 
 int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
@@ -1213,6 +1261,14 @@ int gwas_backward_end(gwas_ctx* c, double* gy, double* tr_mbar, double* ip_mbar_
     HIPCHK(c, hipStreamSynchronize(s));
     if (tr_mbar) *tr_mbar = acc2[0];
     if (ip_mbar_m) *ip_mbar_m = acc2[1];
+    return GWAS_OK;
+}
+
+int gwas_test_inject_fault(gwas_ctx* c, int64_t k) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (k < 0) return GWAS_E_INVALID;
+    c->inject_at = k;
+    c->injected = false;
     return GWAS_OK;
 }
 
