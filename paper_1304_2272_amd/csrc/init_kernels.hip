@@ -216,7 +216,14 @@ __global__ __launch_bounds__(64) void chol_leaf_kernel(double* L, double* U, int
     __shared__ double A[LEAF][LEAF + 1];
     __shared__ double X[LEAF][LEAF + 1];
     const int i = threadIdx.x;
-    for (int c = 0; c < LEAF; ++c) A[i][c] = (c <= i) ? L[i + c * ld] : 0.0;
+    // The whole LEAF x LEAF block lies inside the matrix: its loads are issued
+    // together and waited for once (a load per element behind its own branch
+    // waited for each in turn), then the lower triangle is kept.
+    double v[LEAF];
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c) v[c] = L[i + c * ld];
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c) A[i][c] = (c <= i) ? v[c] : 0.0;
     __syncthreads();
     for (int j = 0; j < LEAF; ++j) {
         const double d = A[j][j];
