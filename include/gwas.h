@@ -60,9 +60,12 @@ extern "C" {
 
 /* ---- arithmetic of the per-block triangular solve ----------------------- */
 #define GWAS_FP64          0   /* everything in float64                     */
-#define GWAS_FP32_REFINE   1   /* L^-1 x_i on float32 matrix cores, float64
-                                  accumulation between K panels; the SNP
-                                  cross products and the p x p solve in
+#define GWAS_FP32_REFINE   1   /* L^-1 x_i on float32 matrix cores (float32
+                                  sums over K in the default tile with int8
+                                  dosages; the other tiles move them to
+                                  float64 every 16 stages of K); the column
+                                  sums, the
+                                  SNP cross products and the p x p solve in
                                   float64 with two refinement steps          */
 #define GWAS_BF16_REFINE   2   /* as above with bfloat16 operands           */
 #define GWAS_INT8_SLICED   3   /* L^-1 held as `slices` int8 digits per entry
