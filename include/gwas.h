@@ -64,9 +64,9 @@ extern "C" {
                                   sums over K in the default tile with int8
                                   dosages; the other tiles move them to
                                   float64 every 16 stages of K); the column
-                                  sums, the
-                                  SNP cross products and the p x p solve in
-                                  float64 with two refinement steps          */
+                                  sums, the SNP cross products and the p x p
+                                  solve in float64 with two refinement
+                                  steps                                      */
 #define GWAS_BF16_REFINE   2   /* as above with bfloat16 operands           */
 #define GWAS_INT8_SLICED   3   /* L^-1 held as `slices` int8 digits per entry
                                   with a power-of-two scale per row; the
