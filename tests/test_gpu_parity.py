@@ -482,3 +482,33 @@ def test_reduced_precision_partition_independence(precision):
     with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], dev_block=512, **kw) as ctx:
         parts = [ctx.stream_block(XR[a:b_])[0] for a, b_ in [(0, 1), (1, 333), (333, m)]]
     assert np.array_equal(np.concatenate(parts), b1)
+
+
+@pytest.mark.parametrize("precision,x_dtype,tol", [("fp64", "f64", TOL_FP64), ("fp64", "i8", TOL_FP64),
+                                                   ("fp32", "i8", TOL_FP32), ("int8", "i8", TOL_FP64)])
+def test_p2_intercept_only(precision, x_dtype, tol):
+    # p = 2: X_L is the intercept alone, the smallest instance of every
+    # per-SNP kernel (one covariate, one cross term, a 2 x 2 solve).
+    n, p, m, seed = 513, 2, 300, 89
+    _say(f"p=2 {precision} x={x_dtype} n={n} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    b, var, info = run(prob, XR, precision=precision, x_dtype=x_dtype, dev_block=256)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert np.array_equal(info, io) and b.shape == (m, 1, p)
+    if precision == "fp32":
+        # at n this small the float32 rounding of L^-1, magnified by the
+        # cancellation in S_BR - S_BL S_TL^-1 S_BL^T, reaches 1e-8 (2e-8 at
+        # n = 130): each SNP is held to twice its first-order rounding bound,
+        # as in the ragged small-n test, and the block to 5e-8
+        ok = io == 0
+        bound = rounding_bound(prob, XR[ok], bo[ok], 2.0 ** -24, 2.0 ** -24)
+        num = np.linalg.norm((b[ok] - bo[ok]).reshape(int(ok.sum()), -1), axis=1)
+        rel = num / np.linalg.norm(bo[ok].reshape(int(ok.sum()), -1), axis=1)
+        _say(f"  err {rel.max():.3e}, worst err / bound {np.max(rel / (bound + 1e-300)):.3f}")
+        assert np.all(rel <= 2.0 * bound + 1e-13) and rel.max() < 5e-8
+        return
+    err = normwise(b, bo)
+    verr = float(np.max(np.abs(var - vo) / np.abs(vo)))
+    _say(f"  err {err:.3e} var err {verr:.3e}")
+    assert err < tol and verr < 1e-10
