@@ -26,9 +26,10 @@ def _lib():
     binding.load()
 
 
-@pytest.mark.parametrize("x_dtype", ["f64", "i8"])
-def test_reverse_generic_cotangents_vs_oracle(x_dtype):
-    n, p, m = 300, 4, 700
+@pytest.mark.parametrize("x_dtype,p", [("f64", 4), ("i8", 4), ("f64", 2), ("i8", 7)])
+def test_reverse_generic_cotangents_vs_oracle(x_dtype, p):
+    # p = 2 is the smallest instance of the per-SNP reverse kernel
+    n, m = 300, 700
     _say(f"reverse pass, random cotangents, n={n} p={p} m={m} x={x_dtype}")
     Phi, s2, h2, XL, y, XR = _case(n, p, m, 21, dtype=np.int8 if x_dtype == "i8" else np.float64)
     M = og.model_covariance(Phi, s2, h2)
