@@ -334,12 +334,15 @@ def test_group_matches_single_contexts(precision):
             c.close()
 
 
-def test_group_graph_replays_match_eager():
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "int8"])
+def test_group_graph_replays_match_eager(precision):
+    # the reduced modes' graphs also hold the cross products and, for the
+    # cohort of n = 2,100 (two K splits), the reduction of their partial sums
     import torch
     dev = torch.device("cuda:0")
     blk, m = 256, 1024
-    _say(f"group graph: 3 cohorts, {m // blk} full sub-blocks per call, two calls")
-    probs, ctxs = _cohort_contexts("fp64", dev_block=blk)
+    _say(f"group graph {precision}: 3 cohorts, {m // blk} full sub-blocks per call, two calls")
+    probs, ctxs = _cohort_contexts(precision, dev_block=blk)
     try:
         for call in range(2):
             XRs = [synth.snp_block_device(pr["n"], 10 + call, 0, m, dev, cohort=i)
