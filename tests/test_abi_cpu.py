@@ -107,3 +107,56 @@ def test_peak_probe_validates_before_device(lib):
     import torch
     if not torch.cuda.is_available():
         assert lib.gwas_peak_probe(0, 0, 100, ctypes.byref(out)) == 4  # GWAS_E_NO_DEVICE
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include "gwas.h"
+
+int main(void) {
+    enum { N = 64, P = 3 };
+    static double M[N * N], XL[N * (P - 1)], y[N];
+    for (int i = 0; i < N; ++i) {
+        M[i + i * N] = 2.0;
+        XL[i] = 1.0;
+        XL[i + N] = (double)(i % 7) - 3.0;
+        y[i] = (double)(i % 5);
+    }
+    size_t ws = gwas_workspace_bytes(N, P, 1, 0, GWAS_FP32_REFINE, GWAS_X_I8);
+    gwas_desc d = {0};
+    d.n = N; d.p = P; d.t = 1;
+    d.M = M; d.ldm = N; d.XL = XL; d.ldxl = N; d.Y = y; d.ldy = N;
+    d.precision = GWAS_FP32_REFINE;
+    d.x_dtype = GWAS_X_I8;
+    gwas_ctx* ctx = NULL;
+    int rc = gwas_init(&ctx, &d);
+    printf("%zu %d %d %d\n", ws, rc, ctx == NULL, gwas_test_inject_fault(NULL, 1));
+    if (ctx) gwas_free(ctx);
+    return 0;
+}
+"""
+
+
+def test_header_compiles_as_c_and_links(lib, tmp_path):
+    # The header is plain C99 and a C program links against the library.
+    # Without a device, init reports GWAS_E_NO_DEVICE and leaves the handle
+    # NULL; on a GPU it succeeds.
+    import shutil
+    import subprocess
+    import torch
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_gwas.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "use_gwas"
+    libdir = os.path.dirname(binding.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-L", libdir, "-lgwas", f"-Wl,-rpath,{libdir}", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    ws, rc, null_ctx, inject_rc = int(out[0]), int(out[1]), int(out[2]), int(out[3])
+    assert ws > 0 and inject_rc == 7
+    if torch.cuda.is_available():
+        assert rc == 0 and null_ctx == 0
+    else:
+        assert rc == 4 and null_ctx == 1
