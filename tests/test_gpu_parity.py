@@ -53,8 +53,10 @@ def test_fp64_n1000_p4_all_snps():
 
 @pytest.mark.parametrize("x_dtype", ["f64", "i8"])
 @pytest.mark.parametrize("n,p,m,dev_block", [(777, 3, 1500, 256), (130, 5, 300, 128),
-                                               (4, 4, 37, 128), (1283, 20, 400, 384)])
+                                               (4, 4, 37, 128), (2, 2, 41, 128), (1283, 20, 400, 384)])
 def test_ragged_shapes(x_dtype, n, p, m, dev_block):
+    # n = p: X_i is square, singular when its dosage column is a multiple of
+    # the intercept (n = p = 2: equal dosages), which both sides must flag
     seed = 7 + n
     _say(f"ragged x={x_dtype} n={n} p={p} m={m} dev_block={dev_block}")
     prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
@@ -70,7 +72,8 @@ def test_ragged_shapes(x_dtype, n, p, m, dev_block):
 
 
 @pytest.mark.parametrize("n,p,m,dev_block", [(777, 3, 1500, 256), (130, 5, 300, 128),
-                                               (4, 4, 37, 128), (1283, 20, 400, 384), (2049, 4, 531, 512)])
+                                               (4, 4, 37, 128), (2, 2, 41, 128), (1283, 20, 400, 384),
+                                               (2049, 4, 531, 512)])
 def test_ragged_shapes_int8_slices(n, p, m, dev_block):
     # interior stages stream straight to LDS; the last column tile of a
     # sub-block and the stages crossing n take the zero-filled edge path
