@@ -165,6 +165,28 @@ int gwas_stream_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
                       double* b, int64_t ldb, double* var_snp, int32_t* info);
 
 /*
+ * Queue a block as gwas_stream_block does and return at once: Algorithm 2's
+ * load and store of a block without their waits.  The block's copies in,
+ * products, solves and copies out run on the context's streams behind the
+ * blocks queued before it, so a caller that queues its blocks one after
+ * another has the next block's copies overlap this block's products.  XR
+ * must stay allocated and unchanged, and b, var_snp and info allocated and
+ * untouched, until gwas_stream_wait returns.  Arguments and errors are
+ * those of gwas_stream_block; a device error may surface here or in
+ * gwas_stream_wait, and poisons the context.  Kernel timing
+ * (gwas_set_timing) covers synchronous calls only.
+ */
+int gwas_stream_block_async(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
+                            double* b, int64_t ldb, double* var_snp, int32_t* info);
+
+/*
+ * Wait for every block gwas_stream_block_async queued on ctx; their outputs
+ * are then written.  gwas_stream_block, gwas_stream_group, gwas_autotune and
+ * the gwas_backward_* calls wait for queued blocks themselves.
+ */
+int gwas_stream_wait(gwas_ctx* ctx);
+
+/*
  * Several cohorts at once (the multi-cohort, multi-trait workload): contexts
  * with their own M, X_L, y and n, sharing the SNP positions of a block of
  * mblk SNPs.  Each sub-block of every context goes into ONE grouped launch

@@ -33,7 +33,7 @@ FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_fre
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
              "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
              "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe",
-             "gwas_test_inject_fault")
+             "gwas_test_inject_fault", "gwas_stream_block_async", "gwas_stream_wait")
 GROUP_GRAPH = 1
 
 
@@ -114,6 +114,10 @@ def load():
     L.gwas_peak_probe.argtypes = [i32, i32, i64, ctypes.POINTER(ctypes.c_double)]
     L.gwas_test_inject_fault.restype = ctypes.c_int
     L.gwas_test_inject_fault.argtypes = [vp, i64]
+    L.gwas_stream_block_async.restype = ctypes.c_int
+    L.gwas_stream_block_async.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
+    L.gwas_stream_wait.restype = ctypes.c_int
+    L.gwas_stream_wait.argtypes = [vp]
     _lib = L
     return L
 
@@ -173,6 +177,7 @@ class GwasContext:
         self._lib = L
         self.precision = precision
         self.x_dtype = x_dtype
+        self._pending = []
         dev = _is_torch(M) and M.is_cuda
         if dev:
             import torch
@@ -244,6 +249,28 @@ class GwasContext:
         del keep
         self._check(rc)
         return b, var, info
+
+    def stream_block_async(self, XR, out):
+        """Queue a block and return at once (``gwas_stream_block_async``).
+        ``out`` = (b, var, info) as for :meth:`stream_block`; XR and ``out``
+        must stay unchanged until :meth:`wait`, and the binding keeps them
+        alive until then."""
+        xdt = np.int8 if self.x_dtype == "i8" else np.float64
+        xp, ldx, keep, _ = _ptr_ld(XR, xdt, "XR")
+        m = XR.shape[0] if XR.ndim == 2 else 1
+        b, var, info = out
+        ptr = (lambda a: a.data_ptr()) if _is_torch(b) else (lambda a: a.ctypes.data)
+        rc = self._lib.gwas_stream_block_async(self._h, xp, ldx, m, ptr(b), self.p * self.t,
+                                               ptr(var) if var is not None else None,
+                                               ptr(info) if info is not None else None)
+        self._pending.append((keep, XR, out))
+        self._check(rc)
+
+    def wait(self):
+        """Wait for the blocks queued by :meth:`stream_block_async`."""
+        rc = self._lib.gwas_stream_wait(self._h)
+        self._pending = []
+        self._check(rc)
 
     def _outputs(self, m, xdev, device):
         if xdev:
@@ -325,8 +352,9 @@ class GwasContext:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.gwas_free(self._h)
+            self._lib.gwas_free(self._h)   # waits for queued blocks before it releases anything
             self._h = ctypes.c_void_p()
+        self._pending = []
 
     def __enter__(self):
         return self

@@ -142,6 +142,12 @@ struct gwas_ctx {
     bool poisoned = false;
     int64_t inject_at = 0;        // test hook: the inject_at-th checked HIP status fails (0 = off)
     bool injected = false;
+    // staging slots of the streamed sub-blocks, alternating across calls: a
+    // slot reused waits for the events of its previous use
+    uint64_t seq = 0;
+    bool slot_used[2] = {false, false};
+    bool out_used[2] = {false, false};
+    int64_t pending = 0;          // blocks queued by gwas_stream_block_async, not yet waited for
     int device = 0;
     Layout lay{};
     char* ws = nullptr;
@@ -659,16 +665,28 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     return GWAS_OK;
 }
 
-int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
-                      int64_t ldb, double* var_snp, int32_t* info) {
-    if (!live(c)) return GWAS_E_STATE;
-    const Layout& Y = c->lay;
-    if (mblk < 0) return GWAS_E_INVALID;
-    if (mblk == 0) return GWAS_OK;
-    if (!XR || !b || ldx < Y.n || ldb < (int64_t)Y.p * Y.t) return GWAS_E_INVALID;
-    DeviceScope scope;
-    HIPCHK(c, hipSetDevice(c->device));
+namespace {
 
+// Waits for the blocks gwas_stream_block_async queued on the context.
+int settle(gwas_ctx* c) {
+    if (c->pending == 0) return GWAS_OK;
+    HIPCHK(c, hipStreamSynchronize(c->s_h2d));
+    HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    HIPCHK(c, hipStreamSynchronize(c->s_d2h));
+    c->pending = 0;
+    return GWAS_OK;
+}
+
+// One pass of Algorithm 2's loop for a block, queued on the context's
+// streams without waiting: per sub-block the copy in (when the dosages are
+// not read in place), the product, the per-SNP kernels and the copy out (when
+// the outputs are not on the device).  Sub-blocks alternate between two
+// staging slots across calls, so the next block's copies can run behind this
+// block's products.  With `timed`, events bracket each product (launch k uses
+// events 2k and 2k+1).
+int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b, int64_t ldb,
+                  double* var_snp, int32_t* info, bool timed) {
+    const Layout& Y = c->lay;
     HIPCHK(c, join_user(c, c->s_comp));
     HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_user, 0));
     const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
@@ -680,7 +698,7 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
     const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
-    if (c->timing && (int64_t)c->tev.size() < 2 * nsub) {
+    if (timed && (int64_t)c->tev.size() < 2 * nsub) {
         while ((int64_t)c->tev.size() < 2 * nsub) {
             hipEvent_t ev;
             HIPCHK(c, hipEventCreate(&ev));
@@ -691,14 +709,15 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     for (int64_t k = 0; k < nsub; ++k) {
         const int64_t col0 = k * Y.dev_block;
         const int64_t cols = std::min<int64_t>(Y.dev_block, mblk - col0);
-        const int slot = (int)(k & 1);
+        const int slot = (int)(c->seq++ & 1);
         const void* xptr;
         int64_t xld;
         if (direct_x) {
             xptr = xr + (size_t)col0 * ldx * elem;
             xld = ldx;
         } else {
-            if (k >= 2) HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_done[slot], 0));
+            // the slot's previous sub-block has finished reading it
+            if (c->slot_used[slot]) HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_done[slot], 0));
             HIPCHK(c, hipMemcpy2DAsync(c->xbuf[slot], Y.n_pad * elem, xr + (size_t)col0 * ldx * elem,
                                        ldx * elem, Y.n * elem, cols, hipMemcpyDefault, c->s_h2d));
             HIPCHK(c, hipEventRecord(c->ev_loaded[slot], c->s_h2d));
@@ -716,7 +735,8 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
             io = info ? info + col0 : nullptr;
             ldbo = ldb;
         } else {
-            if (k >= 2) HIPCHK(c, hipStreamWaitEvent(c->s_comp, c->ev_out[slot], 0));
+            // the slot's previous results have been copied out
+            if (c->out_used[slot]) HIPCHK(c, hipStreamWaitEvent(c->s_comp, c->ev_out[slot], 0));
             bo = c->bbuf[slot];
             vo = c->vbuf[slot];
             io = c->ibuf[slot];
@@ -725,6 +745,9 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         const int* sched = c->sched;
         if (cols != Y.dev_block) {
             if (cols != c->tail_cols) {
+                // the host copy of the tail schedule is rewritten: queued
+                // blocks may still be reading it
+                if (c->pending) HIPCHK(c, hipStreamSynchronize(c->s_comp));
                 int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
                 if (rc) return rc;
                 c->tail_cols = cols;
@@ -733,11 +756,12 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
         }
         TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
         ta.sched = sched;
-        if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
+        if (timed) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
         HIPCHK(c, trmm_stream(ta, c->s_comp));
-        if (c->timing) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
+        if (timed) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
         HIPCHK(c, finish_sub(c, xptr, xld, cols, bo, ldbo, vo, io, c->s_comp));
         HIPCHK(c, hipEventRecord(c->ev_done[slot], c->s_comp));
+        c->slot_used[slot] = true;
         if (!direct_out) {
             HIPCHK(c, hipStreamWaitEvent(c->s_d2h, c->ev_done[slot], 0));
             HIPCHK(c, hipMemcpy2DAsync(b + (size_t)col0 * ldb, ldb * 8, bo, pt * 8, pt * 8, cols,
@@ -747,21 +771,63 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
             if (info)
                 HIPCHK(c, hipMemcpyAsync(info + col0, io, cols * 4, hipMemcpyDefault, c->s_d2h));
             HIPCHK(c, hipEventRecord(c->ev_out[slot], c->s_d2h));
+            c->out_used[slot] = true;
         }
     }
+    return GWAS_OK;
+}
+
+int check_block_args(const gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, const double* b, int64_t ldb) {
+    const Layout& Y = c->lay;
+    if (mblk < 0) return GWAS_E_INVALID;
+    if (mblk > 0 && (!XR || !b || ldx < Y.n || ldb < (int64_t)Y.p * Y.t)) return GWAS_E_INVALID;
+    return GWAS_OK;
+}
+
+}  // namespace
+
+int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
+                      int64_t ldb, double* var_snp, int32_t* info) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (int rc = check_block_args(c, XR, ldx, mblk, b, ldb)) return rc;
+    if (mblk == 0) return GWAS_OK;
+    DeviceScope scope;
+    HIPCHK(c, hipSetDevice(c->device));
+    const int64_t nsub = (mblk + c->lay.dev_block - 1) / c->lay.dev_block;
+    if (int rc = enqueue_block(c, XR, ldx, mblk, b, ldb, var_snp, info, c->timing)) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_h2d));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_d2h));
+    c->pending = 0;
     if (c->timing) {
         for (int64_t k = 0; k < nsub; ++k) {
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]));
             c->t_ms += ms;
             c->t_launches += 1;
-            c->t_cols += std::min<int64_t>(Y.dev_block, mblk - k * Y.dev_block);
+            c->t_cols += std::min<int64_t>(c->lay.dev_block, mblk - k * c->lay.dev_block);
         }
     }
     return GWAS_OK;
+}
+
+int gwas_stream_block_async(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
+                            int64_t ldb, double* var_snp, int32_t* info) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (int rc = check_block_args(c, XR, ldx, mblk, b, ldb)) return rc;
+    if (mblk == 0) return GWAS_OK;
+    DeviceScope scope;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (int rc = enqueue_block(c, XR, ldx, mblk, b, ldb, var_snp, info, false)) return rc;
+    c->pending += 1;
+    return GWAS_OK;
+}
+
+int gwas_stream_wait(gwas_ctx* c) {
+    if (!live(c)) return GWAS_E_STATE;
+    DeviceScope scope;
+    HIPCHK(c, hipSetDevice(c->device));
+    return settle(c);
 }
 
 namespace {
@@ -788,6 +854,8 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
     if (mblk == 0) return GWAS_OK;
     DeviceScope scope;
     HIPCHK(c0, hipSetDevice(c0->device));
+    for (int i = 0; i < nctx; ++i)   // blocks queued by gwas_stream_block_async
+        if (int rc = settle(ctxs[i])) return rc;
     if (!c0->grp) c0->grp = new (std::nothrow) Group();
     Group* g = c0->grp;
     if (!g) return GWAS_E_OOM;
@@ -989,6 +1057,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     cols = std::min<int64_t>(cols, Y.dev_block);
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rc = settle(c)) return rc;   // blocks queued by gwas_stream_block_async
     HIPCHK(c, join_user(c, c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
@@ -1078,6 +1147,7 @@ int gwas_backward_begin(gwas_ctx* c) {
     if (Y.t != 1) return GWAS_E_INVALID;
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rc = settle(c)) return rc;   // blocks queued by gwas_stream_block_async
     hipStream_t s = c->s_comp;
     if (!c->back) {
         c->back = new (std::nothrow) Back();
@@ -1149,6 +1219,7 @@ int gwas_backward_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, 
     if (mblk == 0) return GWAS_OK;
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rc = settle(c)) return rc;   // blocks queued by gwas_stream_block_async
     Back* B = c->back;
     hipStream_t s = c->s_comp;
     HIPCHK(c, join_user(c, s));
@@ -1246,6 +1317,7 @@ int gwas_backward_end(gwas_ctx* c, double* gy, double* tr_mbar, double* ip_mbar_
     hipStream_t s = c->s_comp;
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rc = settle(c)) return rc;   // blocks queued by gwas_stream_block_async
     HIPCHK(c, join_user(c, s));
     const int p = Y.p;
     const int64_t np = Y.n_pad;
