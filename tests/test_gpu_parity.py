@@ -518,3 +518,64 @@ def test_p2_intercept_only(precision, x_dtype, tol):
     verr = float(np.max(np.abs(var - vo) / np.abs(vo)))
     _say(f"  err {err:.3e} var err {verr:.3e}")
     assert err < tol and verr < 1e-10
+
+
+def _random_configs(count=24, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        precision = ["fp64", "fp32", "int8"][k % 3]
+        n = int(rng.integers(2, 3001))
+        p = int(rng.integers(2, min(20, n) + 1))
+        t = int(rng.choice([1, 1, 2, 5]))
+        m = int(rng.integers(1, 1201))
+        dev_block = int(rng.choice([128, 256, 384, 512, 1024]))
+        x_dtype = "i8" if precision == "int8" else str(rng.choice(["f64", "i8"]))
+        on_device = bool(rng.integers(0, 2))
+        out.append((precision, n, p, t, m, dev_block, x_dtype, on_device))
+    return out
+
+
+@pytest.mark.parametrize("precision,n,p,t,m,dev_block,x_dtype,on_device", _random_configs())
+def test_random_shapes_vs_oracle(precision, n, p, t, m, dev_block, x_dtype, on_device):
+    # Seeded random shapes across precision, n, p, traits, block width,
+    # dosage type and host or device inputs and outputs.
+    import torch
+    seed = 1000 + n + 7 * p + m
+    _say(f"random {precision} n={n} p={p} t={t} m={m} dev_block={dev_block} x={x_dtype} device={on_device}")
+    prob = synth.make_problem(n, p, seed, t=t, k=max(50, n // 2))
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    kw = dict(precision=precision, x_dtype=x_dtype, dev_block=dev_block)
+    if on_device:
+        dev = torch.device("cuda:0")
+        with binding.GwasContext(torch.from_numpy(prob["M"]).to(dev), torch.from_numpy(prob["XL"]).to(dev),
+                                 torch.from_numpy(prob["Y"]).to(dev), **kw) as ctx:
+            b, var, info = ctx.stream_block(torch.from_numpy(XR).to(dev))
+            torch.cuda.synchronize()
+            b, var, info = b.cpu().numpy(), var.cpu().numpy(), info.cpu().numpy()
+    else:
+        b, var, info = run(prob, XR, **kw)
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert np.array_equal(info, io)
+    ok = io == 0
+    assert b.shape == (m, t, p)
+    if not ok.any():
+        return
+    num = np.linalg.norm((b[ok] - bo[ok]).reshape(int(ok.sum()), -1), axis=1)
+    rel = num / np.linalg.norm(bo[ok].reshape(int(ok.sum()), -1), axis=1)
+    if precision == "fp32":
+        # each trait against its own first-order rounding bound (small n)
+        worst = 0.0
+        for j in range(t):
+            bj, boj = b[ok][:, j, :], bo[ok][:, j, :]
+            relj = np.linalg.norm(bj - boj, axis=1) / np.linalg.norm(boj, axis=1)
+            bound = rounding_bound(prob, XR[ok], bo[ok][:, j:j + 1, :], 2.0 ** -24, 2.0 ** -24)
+            worst = max(worst, float(np.max(relj / (bound + 1e-300))))
+            assert np.all(relj <= 2.0 * bound + 1e-13)
+        _say(f"  err {rel.max():.3e}, worst err / bound {worst:.3f}")
+        if n >= 500:   # past the small-n cancellation the workload's bar holds
+            assert rel.max() < TOL_FP32
+    else:
+        tol = TOL_FP64 if (precision == "fp64" or n >= 100) else 1e-8
+        _say(f"  err {rel.max():.3e}")
+        assert rel.max() < tol
