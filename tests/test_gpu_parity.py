@@ -579,3 +579,51 @@ def test_random_shapes_vs_oracle(precision, n, p, t, m, dev_block, x_dtype, on_d
         tol = TOL_FP64 if (precision == "fp64" or n >= 100) else 1e-8
         _say(f"  err {rel.max():.3e}")
         assert rel.max() < tol
+
+
+def _random_groups(count=8, seed=2025):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        precision = ["fp64", "fp32", "int8"][k % 3]
+        nctx = int(rng.integers(2, 6))
+        shapes = []
+        for _ in range(nctx):
+            n = int(rng.integers(50, 3001))
+            shapes.append((n, int(rng.integers(2, 9)), int(rng.choice([1, 2, 3]))))
+        dev_block = int(rng.choice([128, 256, 512]))
+        graph = k % 2 == 1
+        # graph replay covers full-width sub-blocks: give those groups some
+        m = (dev_block * int(rng.integers(1, 4)) + int(rng.integers(0, dev_block))) if graph \
+            else int(rng.integers(1, 1500))
+        on_device = bool(rng.integers(0, 2))
+        out.append((precision, tuple(shapes), m, dev_block, graph, on_device))
+    return out
+
+
+@pytest.mark.parametrize("precision,shapes,m,dev_block,graph,on_device", _random_groups())
+def test_random_groups_match_single_contexts(precision, shapes, m, dev_block, graph, on_device):
+    # Seeded random groups: contexts of their own n, p and traits, one width,
+    # eager or graph replay, host or device data; each member's result equals
+    # its own single-context call bit for bit.
+    import torch
+    _say(f"random group {precision} shapes={shapes} m={m} dev_block={dev_block} graph={graph} device={on_device}")
+    dev = torch.device("cuda:0")
+    probs = [synth.make_problem(n, p, 300 + i, t=t, k=max(50, n // 2)) for i, (n, p, t) in enumerate(shapes)]
+    XRs = [synth.snp_block(pr["n"], 77, 0, m, dtype=np.int8, cohort=i) for i, pr in enumerate(probs)]
+    if on_device:
+        XRs = [torch.from_numpy(X).to(dev) for X in XRs]
+    ctxs = [binding.GwasContext(pr["M"], pr["XL"], pr["Y"], precision=precision, x_dtype="i8", dev_block=dev_block)
+            for pr in probs]
+    try:
+        single = [c.stream_block(X) for c, X in zip(ctxs, XRs)]
+        for rep in range(2 if graph else 1):
+            grouped = binding.stream_group(ctxs, XRs, graph=graph)
+            if on_device:
+                torch.cuda.synchronize()
+            for (bs, vs, is_), (bg, vg, ig) in zip(single, grouped):
+                eq = (torch.equal if on_device else np.array_equal)
+                assert eq(bs, bg) and eq(vs, vg) and eq(is_, ig)
+    finally:
+        for c in ctxs:
+            c.close()
