@@ -144,3 +144,39 @@ def test_n10000_gradient_vs_oracle_on_2000_snps():
     assert abs(loss.item() - lo) < 1e-10 * lo
     assert rel_y < 1e-8
     assert abs(h2t.grad.item() - gho) < 1e-8 * abs(gho)
+
+
+def _random_reverse(count=8, seed=2026):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(20, 2501))
+        p = int(rng.integers(2, min(10, n) + 1))
+        m = int(rng.integers(1, 801))
+        x_dtype = ["f64", "i8"][k % 2]
+        dev_block = int(rng.choice([128, 256, 512]))
+        out.append((n, p, m, x_dtype, dev_block))
+    return out
+
+
+@pytest.mark.parametrize("n,p,m,x_dtype,dev_block", _random_reverse())
+def test_random_reverse_vs_oracle(n, p, m, x_dtype, dev_block):
+    # Seeded random shapes through the reverse pass: dl/dy, tr Mbar and
+    # <Mbar, M> against the oracle's dense adjoint for random cotangents.
+    _say(f"random reverse n={n} p={p} m={m} x={x_dtype} dev_block={dev_block}")
+    Phi, s2, h2, XL, y, XR = _case(n, p, m, 500 + n, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    M = og.model_covariance(Phi, s2, h2)
+    rng = np.random.default_rng(n + m)
+    gb = rng.standard_normal((m, p))
+    gv = rng.standard_normal(m)
+    with binding.GwasContext(M, XL, y, x_dtype=x_dtype, dev_block=dev_block) as ctx:
+        b, var, info = ctx.stream_block(XR)
+        ctx.backward_begin()
+        ctx.backward_block(XR, b[:, 0, :], var, info, gb, gv)
+        gy, tr, ip = ctx.backward_end()
+    gy_o, Mbar = og.reverse(M, XL, y, XR, gb, gv)
+    rel = np.max(np.abs(gy - gy_o)) / np.max(np.abs(gy_o))
+    _say(f"  dl/dy rel err {rel:.2e}")
+    assert rel < 1e-9
+    assert abs(tr - np.trace(Mbar)) < 1e-9 * np.abs(Mbar).sum()
+    assert abs(ip - np.sum(Mbar * M)) < 1e-9 * max(1.0, np.abs(Mbar * M).sum())
