@@ -627,3 +627,51 @@ def test_random_groups_match_single_contexts(precision, shapes, m, dev_block, gr
     finally:
         for c in ctxs:
             c.close()
+
+
+def _random_queues(count=6, seed=2027):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        precision = ["fp64", "fp32", "int8"][k % 3]
+        n = int(rng.integers(50, 3001))
+        p = int(rng.integers(2, 9))
+        m = int(rng.integers(200, 2500))
+        cuts = tuple(sorted(int(x) for x in rng.choice(np.arange(1, m), size=int(rng.integers(1, 7)), replace=False)))
+        x_dtype = "i8" if precision == "int8" else str(rng.choice(["f64", "i8"]))
+        out.append((precision, n, p, m, cuts, int(rng.choice([128, 256, 512])), x_dtype, bool(rng.integers(0, 2))))
+    return out
+
+
+@pytest.mark.parametrize("precision,n,p,m,cuts,dev_block,x_dtype,on_device", _random_queues())
+def test_random_queued_blocks_match_one_call(precision, n, p, m, cuts, dev_block, x_dtype, on_device):
+    # A block cut at random points and handed over as queued blocks (every
+    # third one synchronously) gives the bits of one synchronous call.
+    import torch
+    _say(f"random queue {precision} n={n} p={p} m={m} cuts={cuts} dev_block={dev_block} x={x_dtype} "
+         f"device={on_device}")
+    prob = synth.make_problem(n, p, 600 + n)
+    XR = synth.snp_block(n, 600 + n, 0, m, dtype=np.int8 if x_dtype == "i8" else np.float64)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(XR).to(dev) if on_device else torch.from_numpy(XR).pin_memory()
+    kw = dict(precision=precision, x_dtype=x_dtype, dev_block=dev_block)
+    bounds = [0, *cuts, m]
+    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], **kw) as ctx:
+        ref = ctx.stream_block(X)
+        outs = []
+        for j, (a, e) in enumerate(zip(bounds[:-1], bounds[1:])):
+            o = ctx._outputs(e - a, on_device, dev)
+            if not on_device:
+                o = tuple(torch.from_numpy(t).pin_memory() for t in o)
+            if j % 3 == 2:
+                ctx.stream_block(X[a:e], out=o)
+            else:
+                ctx.stream_block_async(X[a:e], o)
+            outs.append(o)
+        ctx.wait()
+    if on_device:
+        torch.cuda.synchronize()
+    for k in range(3):
+        got = torch.cat([o[k] for o in outs]).cpu()
+        want = ref[k].cpu() if on_device else torch.from_numpy(np.asarray(ref[k]))
+        assert torch.equal(got, want)
