@@ -68,6 +68,21 @@ extern "C" {
                                   solve in float64 with two refinement
                                   steps                                      */
 #define GWAS_BF16_REFINE   2   /* as above with bfloat16 operands           */
+/*
+ * Stated error of the two *_REFINE modes against the float64 path.  S_BL =
+ * x_i^T M^-1 X_L and bbar_B = x_i^T M^-1 y are formed in float64 from
+ * W = M^-1 [X_L | y], so S_i and bbar_i are float64-exact except for
+ * S_BR = ||L^-1 x_i||^2, whose product runs in the reduced type.  The SNP
+ * coefficient b_SNP = c_i / s_i (c_i exact) and var_i = 1 / s_i therefore
+ * carry the relative error of s_i = S_BR - S_BL S_TL^-1 S_BL^T, which is at
+ * most 16 u kappa_i with u = 2^-24 (float32) or 2^-8 (bfloat16) and
+ * kappa_i = S_BR / s_i = 1 / (1 - R_i^2) >= 1 (R_i^2: whitened R^2 of x_i
+ * on X_L); measured float32 values on the workloads are about 1e-7
+ * (kappa_i <= 5).  The covariate coefficients change by |db_SNP| times
+ * |S_TL^-1 S_BL^T|, so b_i is within 1e-8 normwise only where |b_SNP| is
+ * small against ||b_i|| (as when the covariate effects dominate).  For
+ * float64-grade results from int8 dosages use GWAS_INT8_SLICED.
+ */
 #define GWAS_INT8_SLICED   3   /* L^-1 held as `slices` int8 digits per entry
                                   with a power-of-two scale per row; the
                                   product with int8 dosages runs on int8
@@ -174,7 +189,8 @@ int gwas_stream_block(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
  * untouched, until gwas_stream_wait returns.  Arguments and errors are
  * those of gwas_stream_block; a device error may surface here or in
  * gwas_stream_wait, and poisons the context.  Kernel timing
- * (gwas_set_timing) covers synchronous calls only.
+ * (gwas_set_timing) covers queued blocks too; their launches are counted
+ * once they have been waited for.
  */
 int gwas_stream_block_async(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
                             double* b, int64_t ldb, double* var_snp, int32_t* info);
@@ -227,8 +243,8 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * up to float64 rounding order.  For the float32 and bfloat16 products a
  * shape also decides how their sums are kept: the 256 x 256 shape (6, the
  * default with int8 dosages) keeps float32 sums, the others move them to
- * float64 every 16 stages; b stays within the precision's stated error
- * either way.
+ * float64 every 16 stages; b stays within the stated error of the *_REFINE
+ * modes (16 u kappa_i on the SNP coefficient and var) either way.
  *
  * The environment variable GWAS_TRMM_CFG (read by gwas_init) overrides the
  * default shape with one the autotuner would try (0..6; ignored when the
@@ -299,10 +315,14 @@ const char* gwas_last_error(const gwas_ctx* ctx);
 
 /*
  * Kernel timing for measurement: when enabled, HIP events bracket every
- * launch of the per-block triangular-product kernel on the compute stream.
- * gwas_kernel_time returns the number of timed launches and their summed
- * duration in milliseconds since timing was last enabled, and the sum of
- * the SNP columns those launches processed.
+ * launch of the per-block triangular-product kernel on the compute stream
+ * (synchronous and queued blocks, grouped launches).  gwas_kernel_time
+ * returns the number of timed launches and their summed duration in
+ * milliseconds since timing was last set, and the sum of the SNP columns
+ * those launches processed; launches of queued blocks count once
+ * gwas_stream_wait (or any call that waits for queued blocks) has returned.
+ * gwas_set_timing first waits for queued blocks, which are timed under the
+ * previous setting.
  */
 int gwas_set_timing(gwas_ctx* ctx, int32_t enable);
 int gwas_kernel_time(gwas_ctx* ctx, int64_t* launches, double* total_ms,

@@ -156,7 +156,9 @@ def _ptr_ld(a, want_dtype, what):
             a = a.reshape(1, -1)
         if a.stride(-1) != 1:
             a = a.contiguous()
-        return a.data_ptr(), a.stride(0) if a.shape[0] > 1 else a.shape[1], a, a.is_cuda
+        # a single row keeps its stride when that is a valid leading dimension
+        ld = a.stride(0) if (a.shape[0] > 1 or a.stride(0) >= a.shape[1]) else a.shape[1]
+        return a.data_ptr(), ld, a, a.is_cuda
     a = np.asarray(a)
     if a.dtype != want_dtype:
         raise TypeError(f"{what}: expected {np.dtype(want_dtype)}, got {a.dtype}")
@@ -164,7 +166,9 @@ def _ptr_ld(a, want_dtype, what):
         a = a.reshape(1, -1)
     if a.strides[-1] != a.itemsize:
         a = np.ascontiguousarray(a)
-    ld = a.strides[0] // a.itemsize if a.shape[0] > 1 else a.shape[1]
+    ld = a.strides[0] // a.itemsize
+    if a.shape[0] == 1 and ld < a.shape[1]:
+        ld = a.shape[1]
     return a.ctypes.data, ld, a, False
 
 

@@ -139,6 +139,7 @@ static std::atomic<uint64_t> next_ctx_id{1};
 struct gwas_ctx {
     uint64_t magic = CTX_MAGIC;
     uint64_t id = next_ctx_id.fetch_add(1);
+    uint64_t gen = 0;             // bumped whenever the tile shape or schedule grouping changes
     bool poisoned = false;
     int64_t inject_at = 0;        // test hook: the inject_at-th checked HIP status fails (0 = off)
     bool injected = false;
@@ -180,7 +181,8 @@ struct gwas_ctx {
     hipEvent_t ev_loaded[2] = {}, ev_done[2] = {}, ev_out[2] = {};
     std::vector<int> host_sched, host_tail;
     bool timing = false;
-    std::vector<hipEvent_t> tev;
+    std::vector<hipEvent_t> tev;    // event pairs around timed launches
+    std::vector<int64_t> tcols;     // columns of each timed launch not yet read back
     int64_t t_launches = 0, t_cols = 0;
     double t_ms = 0.0;
     int64_t info = 0;
@@ -205,7 +207,7 @@ struct Back {
 // context: the combined tile schedule, per-context kernel arguments (pinned
 // host and device copies, double buffered) and an optional captured graph.
 struct Group {
-    std::vector<uint64_t> key;      // ids of the contexts the schedule was built for
+    std::vector<uint64_t> key;      // (id, generation) of the contexts the schedule was built for
     int64_t sched_cols = -1;
     int* d_sched = nullptr;
     size_t sched_cap = 0;
@@ -215,7 +217,7 @@ struct Group {
     std::vector<int> host_sched;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<uint64_t> graph_key;  // ids of the contexts the graph was captured for
+    std::vector<uint64_t> graph_key;  // (id, generation) of the contexts the graph was captured for
     // the graph's own argument array and schedule, never rewritten after capture
     TrmmArgs* h_args_graph = nullptr;
     TrmmArgs* d_args_graph = nullptr;
@@ -272,6 +274,38 @@ bool inject_now(gwas_ctx* c) {
     } while (0)
 
 bool live(const gwas_ctx* c) { return c && c->magic == CTX_MAGIC && !c->poisoned; }
+
+// Kernel timing: an event pair around each timed launch, read back once the
+// stream has drained (after a synchronous call, or when queued blocks are
+// waited for).
+int timer_start(gwas_ctx* c, hipStream_t s) {
+    const size_t k = c->tcols.size();
+    while (c->tev.size() < 2 * (k + 1)) {
+        hipEvent_t ev;
+        HIPCHK(c, hipEventCreate(&ev));
+        c->tev.push_back(ev);
+    }
+    HIPCHK(c, hipEventRecord(c->tev[2 * k], s));
+    return GWAS_OK;
+}
+
+int timer_stop(gwas_ctx* c, hipStream_t s, int64_t cols) {
+    HIPCHK(c, hipEventRecord(c->tev[2 * c->tcols.size() + 1], s));
+    c->tcols.push_back(cols);
+    return GWAS_OK;
+}
+
+int collect_timing(gwas_ctx* c) {
+    for (size_t k = 0; k < c->tcols.size(); ++k) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]));
+        c->t_ms += ms;
+        c->t_launches += 1;
+        c->t_cols += c->tcols[k];
+    }
+    c->tcols.clear();
+    return GWAS_OK;
+}
 
 // The caller's current device is restored when an entry point returns.
 struct DeviceScope {
@@ -428,7 +462,7 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.cfg = c->cfg;
     ta.slices = Y.slices;
     ta.rscale = c->rscale;
-    ta.Ut = (Y.precision == GWAS_FP64) ? (const void*)c->U : c->Ulow;
+    ta.Ut = (c->at == A_F64) ? (const void*)c->U : c->Ulow;
     ta.ldu = Y.ld;
     ta.n_pad = Y.n_pad;
     ta.X = xptr;
@@ -447,18 +481,35 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     return ta;
 }
 
-SolveArgs solve_args_for(const gwas_ctx* c, int64_t cols, double* bo, int64_t ldbo, double* vo, int* io) {
+// Device scratch of the per-SNP stage of one sub-block: the product's
+// partial sums, their chunk totals and (reduced modes) the cross products
+// x^T W with their split-K partials, all with leading dimension ld (>= the
+// sub-block's columns).
+struct SubScratch {
+    double* part;
+    double* red;
+    double* xw;
+    double* xwpart;
+    int64_t ld;
+};
+
+SubScratch ctx_scratch(const gwas_ctx* c) {
+    return SubScratch{c->part, c->red, c->xw, c->xwpart, c->lay.dev_block};
+}
+
+SolveArgs solve_args_for(const gwas_ctx* c, const SubScratch& sc, int64_t cols, double* bo, int64_t ldbo,
+                         double* vo, int* io) {
     const Layout& Y = c->lay;
     SolveArgs sa{};
     sa.p = Y.p;
     sa.t = Y.t;
     sa.cols = cols;
-    sa.part = c->red;   // chunk totals of the partial sums
-    sa.ldp = Y.dev_block;
+    sa.part = sc.red;   // chunk totals of the partial sums
+    sa.ldp = sc.ld;
     sa.npb = chunks_of(Y.n_pad / c->shape.part_rows);
     sa.Q = Y.Q;
-    sa.xw = c->xw;
-    sa.ldxw = Y.dev_block;
+    sa.xw = sc.xw;
+    sa.ldxw = sc.ld;
     sa.consts = c->consts;
     sa.refine = (Y.precision == GWAS_FP64) ? 0 : REFINE_STEPS;
     sa.rank_tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
@@ -472,19 +523,19 @@ SolveArgs solve_args_for(const gwas_ctx* c, int64_t cols, double* bo, int64_t ld
 }
 
 // Cross products x^T W (reduced modes) and the per-SNP solves of one sub-block.
-hipError_t finish_sub(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, double* bo,
-                      int64_t ldbo, double* vo, int* io, hipStream_t s) {
+hipError_t finish_sub(const gwas_ctx* c, const SubScratch& sc, const void* xptr, int64_t xld, int64_t cols,
+                      double* bo, int64_t ldbo, double* vo, int* io, hipStream_t s) {
     const Layout& Y = c->lay;
     if (Y.precision != GWAS_FP64) {
         hipError_t e = snp_cross_w((Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64, xptr, xld, Y.n, cols, c->W,
-                                   Y.n_pad, Y.Qc, c->xw, Y.dev_block, c->xwpart,
-                                   (int64_t)xw_splits(Y.n) * Y.Qc * Y.dev_block, s);
+                                   Y.n_pad, Y.Qc, sc.xw, sc.ld, sc.xwpart,
+                                   (int64_t)xw_splits(Y.n) * Y.Qc * sc.ld, s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = partial_chunks(c->part, Y.dev_block, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
-                                  PART_CHUNK, c->red, Y.dev_block, s);
+    hipError_t e = partial_chunks(sc.part, sc.ld, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
+                                  PART_CHUNK, sc.red, sc.ld, s);
     if (e != hipSuccess) return e;
-    return snp_solve(solve_args_for(c, cols, bo, ldbo, vo, io), s);
+    return snp_solve(solve_args_for(c, sc, cols, bo, ldbo, vo, io), s);
 }
 
 // Combined tile schedule of several contexts with one tile shape: every
@@ -674,7 +725,7 @@ int settle(gwas_ctx* c) {
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_d2h));
     c->pending = 0;
-    return GWAS_OK;
+    return collect_timing(c);
 }
 
 // One pass of Algorithm 2's loop for a block, queued on the context's
@@ -698,13 +749,6 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
     const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
-    if (timed && (int64_t)c->tev.size() < 2 * nsub) {
-        while ((int64_t)c->tev.size() < 2 * nsub) {
-            hipEvent_t ev;
-            HIPCHK(c, hipEventCreate(&ev));
-            c->tev.push_back(ev);
-        }
-    }
 
     for (int64_t k = 0; k < nsub; ++k) {
         const int64_t col0 = k * Y.dev_block;
@@ -756,10 +800,14 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
         }
         TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
         ta.sched = sched;
-        if (timed) HIPCHK(c, hipEventRecord(c->tev[2 * k], c->s_comp));
+        if (timed) {
+            if (int rc = timer_start(c, c->s_comp)) return rc;
+        }
         HIPCHK(c, trmm_stream(ta, c->s_comp));
-        if (timed) HIPCHK(c, hipEventRecord(c->tev[2 * k + 1], c->s_comp));
-        HIPCHK(c, finish_sub(c, xptr, xld, cols, bo, ldbo, vo, io, c->s_comp));
+        if (timed) {
+            if (int rc = timer_stop(c, c->s_comp, cols)) return rc;
+        }
+        HIPCHK(c, finish_sub(c, ctx_scratch(c), xptr, xld, cols, bo, ldbo, vo, io, c->s_comp));
         HIPCHK(c, hipEventRecord(c->ev_done[slot], c->s_comp));
         c->slot_used[slot] = true;
         if (!direct_out) {
@@ -793,22 +841,12 @@ int gwas_stream_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, do
     if (mblk == 0) return GWAS_OK;
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
-    const int64_t nsub = (mblk + c->lay.dev_block - 1) / c->lay.dev_block;
     if (int rc = enqueue_block(c, XR, ldx, mblk, b, ldb, var_snp, info, c->timing)) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_h2d));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_d2h));
     c->pending = 0;
-    if (c->timing) {
-        for (int64_t k = 0; k < nsub; ++k) {
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * k], c->tev[2 * k + 1]));
-            c->t_ms += ms;
-            c->t_launches += 1;
-            c->t_cols += std::min<int64_t>(c->lay.dev_block, mblk - k * c->lay.dev_block);
-        }
-    }
-    return GWAS_OK;
+    return collect_timing(c);
 }
 
 int gwas_stream_block_async(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
@@ -818,7 +856,7 @@ int gwas_stream_block_async(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mb
     if (mblk == 0) return GWAS_OK;
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
-    if (int rc = enqueue_block(c, XR, ldx, mblk, b, ldb, var_snp, info, false)) return rc;
+    if (int rc = enqueue_block(c, XR, ldx, mblk, b, ldb, var_snp, info, c->timing)) return rc;
     c->pending += 1;
     return GWAS_OK;
 }
@@ -865,7 +903,12 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
     }
     std::vector<gwas_ctx*> cs(ctxs, ctxs + nctx);
     std::vector<uint64_t> key;
-    for (const gwas_ctx* c : cs) key.push_back(c->id);
+    // a context's generation changes with its tile shape or schedule
+    // grouping (gwas_autotune): the schedule and graph are then rebuilt
+    for (const gwas_ctx* c : cs) {
+        key.push_back(c->id);
+        key.push_back(c->gen);
+    }
     hipStream_t s = c0->s_comp;
     for (int i = 0; i < nctx; ++i) HIPCHK(c0, join_user(cs[i], s));
     const int64_t blk = c0->lay.dev_block;
@@ -879,13 +922,6 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
     }
     const bool want_graph = (flags & GWAS_GROUP_GRAPH) != 0;
     const int64_t nsub = (mblk + blk - 1) / blk;
-    if (c0->timing && (int64_t)c0->tev.size() < 2 * nsub) {
-        while ((int64_t)c0->tev.size() < 2 * nsub) {
-            hipEvent_t ev;
-            HIPCHK(c0, hipEventCreate(&ev));
-            c0->tev.push_back(ev);
-        }
-    }
     auto ensure_schedule = [&](int64_t cols) -> int {
         if (g->key == key && g->sched_cols == cols) return GWAS_OK;
         const int64_t len = group_schedule(cs, cols, g->host_sched);
@@ -920,13 +956,20 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
             else
                 HIPCHK(c0, hipMemcpy(d, h, nctx * sizeof(TrmmArgs), hipMemcpyHostToDevice));
         }
+        // the schedule must be the one of the contexts' current shape
+        std::vector<int64_t> nrb(cs.size());
+        for (size_t i = 0; i < cs.size(); ++i) nrb[i] = cs[i]->lay.n_pad / cs[0]->shape.tm;
+        if (trmm_schedule_multi(nrb.data(), (int)cs.size(), cols, cs[0]->shape, nullptr) != n_sched) {
+            c0->err = "grouped schedule does not match the contexts' tile shape";
+            return GWAS_E_INVALID;
+        }
         TrmmArgs la = h[0];
         la.group = d;
         la.sched = sched;
         la.n_sched = n_sched;
         HIPCHK(c0, trmm_stream(la, s));
         for (int i = 0; i < nctx; ++i)
-            HIPCHK(c0, finish_sub(cs[i], xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], s));
+            HIPCHK(c0, finish_sub(cs[i], ctx_scratch(cs[i]), xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], s));
         return GWAS_OK;
     };
 
@@ -966,7 +1009,9 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                 io[i] = c->ibuf[bslot];
             }
         }
-        if (c0->timing) HIPCHK(c0, hipEventRecord(c0->tev[2 * k], s));
+        if (c0->timing) {
+            if (int trc = timer_start(c0, s)) return trc;
+        }
         if (use_graph) {
             if (!g->exec || g->graph_key != key) {
                 HIPCHK(c0, hipStreamSynchronize(s));
@@ -1010,7 +1055,9 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                                     vo, io, cols, true, false);
             if (erc) return erc;
         }
-        if (c0->timing) HIPCHK(c0, hipEventRecord(c0->tev[2 * k + 1], s));
+        if (c0->timing) {
+            if (int trc = timer_stop(c0, s, cols * nctx)) return trc;
+        }
         for (int i = 0; i < nctx; ++i) {
             if (direct_out[i] && !use_graph) continue;
             const int64_t pt = (int64_t)cs[i]->lay.p * cs[i]->lay.t;
@@ -1024,16 +1071,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         HIPCHK(c0, hipEventRecord(c0->ev_done[slot], s));
     }
     HIPCHK(c0, hipStreamSynchronize(s));
-    if (c0->timing) {
-        for (int64_t k = 0; k < nsub; ++k) {
-            float ms = 0.f;
-            HIPCHK(c0, hipEventElapsedTime(&ms, c0->tev[2 * k], c0->tev[2 * k + 1]));
-            c0->t_ms += ms;
-            c0->t_launches += 1;
-            c0->t_cols += std::min<int64_t>(blk, mblk - k * blk) * nctx;
-        }
-    }
-    return GWAS_OK;
+    return collect_timing(c0);
 }
 }  // namespace
 
@@ -1085,7 +1123,8 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
         const void* xptr = XR;
         int64_t xld = ldx;
-        if (!(on_device(XR) && reinterpret_cast<uintptr_t>(XR) % 16 == 0 && (ldx * (int64_t)elem) % 16 == 0)) {
+        if (!(on_device(XR) && reinterpret_cast<uintptr_t>(XR) % 16 == 0 && (ldx * (int64_t)elem) % 16 == 0 &&
+              ldx * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES)) {
             HIPCHK(c, hipMemcpy2D(c->xbuf[0], Y.n_pad * elem, XR, ldx * elem, Y.n * elem, cols, hipMemcpyDefault));
             xptr = c->xbuf[0];
             xld = Y.n_pad;
@@ -1099,6 +1138,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         for (int cfg = (c->at == A_I8S ? -1 : 0); cfg < (c->at == A_I8S ? 0 : trmm_num_cfgs()); ++cfg) {
             if (c->at != A_I8S && !trmm_cfg_valid(c->at, xt, cfg)) continue;
             for (int rg : RGROUP_CANDIDATES) {
+                c->gen += 1;
                 c->cfg = cfg < 0 ? 0 : cfg;
                 c->rgroup = rg;
                 c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, rg);
@@ -1129,6 +1169,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
             }
         }
     }
+    c->gen += 1;
     c->cfg = best < 0 ? 0 : best;
     c->rgroup = best_rg;
     c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, best_rg);
@@ -1382,6 +1423,11 @@ const char* gwas_last_error(const gwas_ctx* c) {
 
 int gwas_set_timing(gwas_ctx* c, int32_t enable) {
     if (!live(c)) return GWAS_E_STATE;
+    {
+        DeviceScope scope;
+        HIPCHK(c, hipSetDevice(c->device));
+        if (int rc = settle(c)) return rc;   // queued blocks are timed under the old setting
+    }
     c->timing = enable != 0;
     c->t_launches = 0;
     c->t_cols = 0;

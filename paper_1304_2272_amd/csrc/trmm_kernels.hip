@@ -655,7 +655,9 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     const size_t xs = a.xt == X_I8 ? 1 : 8;
     if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
     if (a.at == A_I8S) {
-        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6)
+        // the int8-slice product forms z^T z only (its mode takes the cross
+        // products from x^T W)
+        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6 || a.with_cross)
             return hipErrorInvalidValue;
     } else {
         if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;

@@ -1,10 +1,13 @@
 """Parity at the workloads' full sizes, in the bench's launch configuration.
 
-n = 20,000 (FP64, float64 dosages streamed from host memory in 5,000-SNP host
-blocks): sampled SNPs against the oracle, chosen at both ends of every host
-block and at random.  n = 50,000 (int8 dosages resident on the device, the
+n = 20,000 (FP64, float64 dosages streamed from pinned host memory in 5,000-SNP
+host blocks): the whole 500,000-SNP, 100-block sequence, queued block after
+block; sampled SNPs against the oracle at both ends of the first, second,
+middle and last host blocks and at random.  n = 50,000 (int8 dosages, the
 bench workload): the reduced-precision modes against the FP64 path on every
-SNP of a 32,768-SNP block, and the FP64 path against planted coefficients.
+SNP of a 32,768-SNP block (normwise, SNP coefficient and var), and the FP64
+path against planted coefficients.  Heritability up to 0.999 (kappa(M) up to
+about 1e4) at n = 5,000 and 20,000 against the oracle.
 """
 
 import numpy as np
@@ -26,34 +29,100 @@ def normwise(b, bref):
     return float(np.max(num / den))
 
 
+def snp_errors(b, bref, var, vref):
+    """(max relative error of the SNP coefficient, of var, and the SNP
+    coefficient's error in standard-error units)."""
+    bs, brs = b[..., -1], bref[..., -1]
+    d = np.abs(bs - brs)
+    sd = np.sqrt(vref)
+    return (float(np.max(d / np.abs(brs))), float(np.max(np.abs(var - vref) / vref)),
+            float(np.max(d / (sd[:, None] if d.ndim == 2 else sd))))
+
+
 @pytest.mark.timeout(900)
-def test_n20000_fp64_streamed_sampled_vs_oracle():
-    n, p, seed, hb, nblk = 20_000, 4, 1305, 5_000, 4
-    _say(f"n={n} p={p}: {nblk} host blocks of {hb} float64 SNPs")
-    prob = synth.make_problem(n, p, seed)
-    b_all = []
-    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"]) as ctx:
-        for k in range(nblk):
-            XR = synth.snp_block(n, seed, k * hb, hb)
-            b, var, info = ctx.stream_block(XR)
-            assert (info == 0).all()
-            b_all.append(b)
-    b_all = np.concatenate(b_all)
+def test_n20000_fp64_whole_stream_from_pinned_host_vs_oracle():
+    # 100 host blocks of 5,000 float64 SNPs (80 GB in all) from pinned host
+    # memory, queued 20 at a time into one context (16 GB of pinned blocks
+    # refilled between waits): every block's copy runs behind the previous
+    # block's product, and the staging slots keep alternating across waits
+    import torch
+    n, p, seed, hb, nblk, group = 20_000, 4, 1305, 5_000, 100, 20
+    dev = torch.device("cuda:0")
+    m = hb * nblk
+    _say(f"n={n} p={p}: {nblk} pinned host blocks of {hb} float64 SNPs, queued {group} at a time")
+    prob = synth.make_problem(n, p, seed, device="cuda:0")
+    XL, Y = torch.from_numpy(prob["XL"]).to(dev), torch.from_numpy(prob["Y"]).to(dev)
     rng = np.random.default_rng(seed)
-    idx = sorted(set([j for k in range(nblk) for j in list(range(k * hb, k * hb + 8)) +
-                      list(range((k + 1) * hb - 8, (k + 1) * hb))] +
-                     list(rng.choice(nblk * hb, 128, replace=False))))
-    chunks = {}
-    for j in idx:
-        c = j // synth.CHUNK
-        if c not in chunks:
-            chunks[c] = synth.snp_chunk(n, seed, c)
-    XS = np.stack([chunks[j // synth.CHUNK][j % synth.CHUNK] for j in idx])
-    _say(f"  oracle on {len(idx)} sampled SNPs")
-    bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XS)
-    err = normwise(b_all[idx], bo)
-    _say(f"  max normwise err {err:.3e}")
-    assert err < 1e-10
+    edge = [j for k in (0, 1, nblk // 2, nblk - 1) for j in list(range(k * hb, k * hb + 8)) +
+            list(range((k + 1) * hb - 8, (k + 1) * hb))]
+    idx = np.array(sorted(set(edge) | set(rng.choice(m, 256, replace=False).tolist())))
+    XS = np.empty((idx.size, n))
+    host = torch.empty((group, hb, n), dtype=torch.float64).pin_memory()
+    ob = torch.empty((m, 1, p), dtype=torch.float64).pin_memory()
+    ov = torch.empty(m, dtype=torch.float64).pin_memory()
+    oi = torch.empty(m, dtype=torch.int32).pin_memory()
+    with binding.GwasContext(prob["M"], XL, Y) as ctx:
+        for g in range(nblk // group):
+            for j in range(group):
+                k = g * group + j
+                host[j].copy_(synth.snp_block_device(n, seed, k * hb, hb, dev, dtype=torch.float64))
+                sel = (idx >= k * hb) & (idx < (k + 1) * hb)
+                XS[sel] = host[j][torch.from_numpy(idx[sel] - k * hb)].numpy()
+            for j in range(group):
+                sl = slice((g * group + j) * hb, (g * group + j + 1) * hb)
+                ctx.stream_block_async(host[j], (ob[sl], ov[sl], oi[sl]))
+            ctx.wait()
+            _say(f"  host blocks {g * group}..{g * group + group - 1} done")
+    assert bool((oi == 0).all())
+    M = prob["M"].cpu().numpy()
+    _say(f"  oracle on {idx.size} sampled SNPs")
+    bo, vo, io = GLSOracle(M, prob["XL"], prob["Y"]).solve(XS)
+    b, var = ob.numpy()[idx], ov.numpy()[idx]
+    err = normwise(b, bo)
+    srel, vrel, se = snp_errors(b, bo, var, vo)
+    _say(f"  max normwise err {err:.3e}; SNP coefficient {se:.3e} SE, rel {srel:.3e}; var rel {vrel:.3e}")
+    assert (io == 0).all() and err < 1e-10 and se < 1e-10 and vrel < 1e-10
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n", [5_000, 20_000])
+@pytest.mark.parametrize("h2", [0.9, 0.99, 0.999])
+def test_high_heritability_vs_oracle(n, h2):
+    # M = h^2 Phi + (1 - h^2) I with Phi of rank 2,000 < n: kappa(M) grows as
+    # 1 / (1 - h^2), about 1e4 at h^2 = 0.999.  The explicit inverse L^-1 of
+    # the float64 and int8-slice products is held to the float64 bar there;
+    # the float32 product's error is reported against 16 u kappa_i.
+    import torch
+    p, m, seed = 4, 256, 1400 + int(h2 * 1000)
+    dev = torch.device("cuda:0")
+    prob = synth.make_problem(n, p, seed, h2=h2, device="cuda:0")
+    M = prob["M"].cpu().numpy()
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    # Phi has rank 2,000 < n: the smallest eigenvalue of M is sigma^2 (1 - h^2)
+    from scipy.sparse.linalg import eigsh
+    lmax = float(eigsh(M, k=1, which="LA", return_eigenvectors=False)[0])
+    _say(f"n={n} h2={h2}: kappa(M) = {lmax / (prob['sigma2'] * (1.0 - h2)):.3g}")
+    orc = GLSOracle(M, prob["XL"], prob["Y"])
+    bo, vo, io = orc.solve(XR)
+    N, _ = orc.normal_equations(XR)
+    kappa = N[:, -1, -1] * vo
+    XL, Y = torch.from_numpy(prob["XL"]).to(dev), torch.from_numpy(prob["Y"]).to(dev)
+    for precision in ("fp64", "int8", "fp32"):
+        with binding.GwasContext(prob["M"], XL, Y, precision=precision, x_dtype="i8",
+                                 slices=6 if precision == "int8" else 0) as ctx:
+            b, var, info = ctx.stream_block(XR)
+        assert np.array_equal(info, io)
+        err = normwise(b, bo)
+        srel, vrel, se = snp_errors(b, bo, var, vo)
+        _say(f"  {precision}: normwise {err:.3e}, SNP coefficient {se:.3e} SE / rel {srel:.3e}, var rel {vrel:.3e}")
+        if precision == "fp32":
+            lim = 16 * 2.0 ** -24 * kappa
+            rel = np.abs(b[:, 0, -1] - bo[:, 0, -1]) / np.abs(bo[:, 0, -1])
+            worst = max(float(np.max(rel / lim)), float(np.max(np.abs(var - vo) / vo / lim)))
+            _say(f"    against 16 u kappa_i: {worst:.3f} (kappa_i <= {kappa.max():.2f})")
+            assert worst <= 1.0
+        else:
+            assert err < 1e-10 and se < 1e-10 and vrel < 1e-10
 
 
 @pytest.fixture(scope="module")
@@ -69,6 +138,7 @@ def n50k():
     with binding.GwasContext(data["M"], data["XL"], data["Y"], x_dtype="i8") as ctx:
         b, var, info = ctx.stream_block(data["X"])
         data["b64"] = b.cpu().numpy()
+        data["var64"] = var.cpu().numpy()
         data["info64"] = info.cpu().numpy()
     yield data
     del data
@@ -82,11 +152,17 @@ def test_n50000_reduced_vs_fp64_all_snps(n50k, precision, tol):
     with binding.GwasContext(n50k["M"], n50k["XL"], n50k["Y"], precision=precision,
                              x_dtype="i8") as ctx:
         b, var, info = ctx.stream_block(n50k["X"])
-    b = b.cpu().numpy()
+    b, var = b.cpu().numpy(), var.cpu().numpy()
     assert np.array_equal(info.cpu().numpy(), n50k["info64"])
     err = normwise(b, n50k["b64"])
-    _say(f"  max normwise err {err:.3e}")
+    srel, vrel, se = snp_errors(b, n50k["b64"], var, n50k["var64"])
+    _say(f"  max normwise err {err:.3e}; SNP coefficient {se:.3e} SE, rel {srel:.3e}; var rel {vrel:.3e}")
     assert err < tol
+    if precision == "fp32":
+        # the stated floor 16 u kappa_i with kappa_i >= 1
+        assert srel < 16 * 2.0 ** -24 and vrel < 16 * 2.0 ** -24
+    else:
+        assert se < 1e-10 and srel < 1e-10 and vrel < 1e-10
 
 
 @pytest.mark.timeout(600)

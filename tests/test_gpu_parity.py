@@ -27,6 +27,40 @@ def normwise(b, bref):
     return float(np.max(num / den)) if b.shape[0] else 0.0
 
 
+U32, U16 = 2.0 ** -24, 2.0 ** -8   # unit roundoff of float32 and bfloat16
+
+
+def snp_errors(b, bref, var, vref, ok):
+    """(max relative error of the SNP coefficient, of var, and the SNP
+    coefficient's error in standard-error units) over the SNPs in ok."""
+    if not ok.any():
+        return 0.0, 0.0, 0.0
+    bs, brs = b[ok][..., -1], bref[ok][..., -1]
+    d = np.abs(bs - brs)
+    sd = np.sqrt(vref[ok])
+    rel = float(np.max(d / np.abs(brs)))
+    vrel = float(np.max(np.abs(var[ok] - vref[ok]) / vref[ok]))
+    se = float(np.max(d / (sd[:, None] if d.ndim == 2 else sd)))
+    return rel, vrel, se
+
+
+def reduced_floor(orc, XR, b, bref, var, vref, ok, u):
+    """The stated floor of the reduced-precision modes: S_BR is their only
+    reduced-precision quantity and c_i is float64-exact, so b_SNP = c_i / s_i
+    and var_i = 1 / s_i carry the relative error of s_i, at most
+    16 u kappa_i with kappa_i = S_BR / s_i = (x^T M^-1 x) var_i.  Returns the
+    worst ratio of error to that limit over b_SNP and var, and max kappa."""
+    if not ok.any():
+        return 0.0, 0.0
+    N, _ = orc.normal_equations(XR[ok])
+    kappa = N[:, -1, -1] * vref[ok]
+    lim = 16.0 * u * kappa
+    rel = np.abs(b[ok][..., -1] - bref[ok][..., -1]) / np.abs(bref[ok][..., -1])
+    vrel = np.abs(var[ok] - vref[ok]) / vref[ok]
+    worst = max(float(np.max(rel / (lim[:, None] if rel.ndim == 2 else lim))), float(np.max(vrel / lim)))
+    return worst, float(kappa.max())
+
+
 def run(prob, XR, **kw):
     with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], **kw) as ctx:
         return ctx.stream_block(XR)
@@ -275,15 +309,19 @@ def test_reduced_precision_ragged_within_rounding_bound(precision, cfg, n, p, m,
     prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
     XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
     b, var, info = run(prob, XR, precision=precision, x_dtype="i8", dev_block=dev_block)
-    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
+    bo, vo, io = orc.solve(XR)
     assert np.array_equal(info, io)
     ok = io == 0
-    u = 2.0 ** -24 if precision == "fp32" else 2.0 ** -8
+    u = U32 if precision == "fp32" else U16
     bound = rounding_bound(prob, XR[ok], bo[ok], u, 2.0 ** -24)
     num = np.linalg.norm((b[ok] - bo[ok]).reshape(int(ok.sum()), -1), axis=1)
     err = num / np.linalg.norm(bo[ok].reshape(int(ok.sum()), -1), axis=1)
-    _say(f"  err {err.max():.3e}, worst err / bound {np.max(err / (bound + 1e-300)):.3f}")
+    worst, kmax = reduced_floor(orc, XR, b, bo, var, vo, ok, u)
+    _say(f"  err {err.max():.3e}, worst err / bound {np.max(err / (bound + 1e-300)):.3f}; "
+         f"SNP coefficient and var against 16 u kappa: {worst:.3f} (kappa <= {kmax:.1f})")
     assert np.all(err <= 2.0 * bound + 1e-13)
+    assert worst <= 1.0
 
 
 @pytest.mark.parametrize("slices,tol", [(4, 1e-8), (5, 1e-9), (6, TOL_FP64)])
@@ -389,6 +427,45 @@ def test_group_graph_after_a_member_is_replaced():
         assert torch.equal(single, replay[1][0])
     finally:
         for c in ctxs:
+            c.close()
+
+
+def test_group_rebuilt_after_autotune_changes_tile_height(tmp_path, monkeypatch):
+    # Grouped schedules and graphs belong to the members' tile shape: after
+    # gwas_autotune moves every member from 256-row tiles (shape 4) to 128-row
+    # tiles (shape 2), eager and graph grouped calls must equal fresh
+    # contexts built in shape 2, bit for bit.
+    import torch
+    dev = torch.device("cuda:0")
+    blk, m = 512, 1024
+    monkeypatch.setenv("GWAS_TRMM_CFG", "4")
+    probs, ctxs = _cohort_contexts("fp64", dev_block=blk)
+    monkeypatch.setenv("GWAS_TRMM_CFG", "2")
+    _, fresh = _cohort_contexts("fp64", dev_block=blk)
+    monkeypatch.delenv("GWAS_TRMM_CFG")
+    cache = tmp_path / "tune.txt"
+    # cache lines that make each member's autotune choose shape 2, row group 1
+    cache.write_text("".join(f"gfx950 n_pad={c.query()['n_pad']} precision=0 x_dtype=1 cols={blk} cfg=2 rgroup=1\n"
+                             for c in ctxs))
+    monkeypatch.setenv("GWAS_TUNE_CACHE", str(cache))
+    try:
+        XRs = [synth.snp_block_device(pr["n"], 31, 0, m, dev, cohort=i) for i, pr in enumerate(probs)]
+        binding.stream_group(ctxs, XRs)
+        binding.stream_group(ctxs, XRs, graph=True)
+        torch.cuda.synchronize()
+        for c, X in zip(ctxs, XRs):
+            assert c.autotune(X, blk) == (2, 1)
+        ref = binding.stream_group(fresh, XRs)
+        after = binding.stream_group(ctxs, XRs)
+        torch.cuda.synchronize()
+        replay = binding.stream_group(ctxs, XRs, graph=True)
+        torch.cuda.synchronize()
+        _say("group after autotune 4 -> 2: eager and graph calls against fresh shape-2 contexts")
+        for r, a, g in zip(ref, after, replay):
+            for x, y, z in zip(r, a, g):
+                assert torch.equal(x, y) and torch.equal(x, z)
+    finally:
+        for c in ctxs + fresh:
             c.close()
 
 
@@ -500,7 +577,8 @@ def test_p2_intercept_only(precision, x_dtype, tol):
     prob = synth.make_problem(n, p, seed)
     XR = synth.snp_block(n, seed, 0, m, dtype=np.int8 if x_dtype == "i8" else np.float64)
     b, var, info = run(prob, XR, precision=precision, x_dtype=x_dtype, dev_block=256)
-    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
+    bo, vo, io = orc.solve(XR)
     assert np.array_equal(info, io) and b.shape == (m, 1, p)
     if precision == "fp32":
         # at n this small the float32 rounding of L^-1, magnified by the
@@ -511,8 +589,12 @@ def test_p2_intercept_only(precision, x_dtype, tol):
         bound = rounding_bound(prob, XR[ok], bo[ok], 2.0 ** -24, 2.0 ** -24)
         num = np.linalg.norm((b[ok] - bo[ok]).reshape(int(ok.sum()), -1), axis=1)
         rel = num / np.linalg.norm(bo[ok].reshape(int(ok.sum()), -1), axis=1)
-        _say(f"  err {rel.max():.3e}, worst err / bound {np.max(rel / (bound + 1e-300)):.3f}")
-        assert np.all(rel <= 2.0 * bound + 1e-13) and rel.max() < 5e-8
+        srel, vrel, se = snp_errors(b, bo, var, vo, ok)
+        worst, kmax = reduced_floor(orc, XR, b, bo, var, vo, ok, U32)
+        _say(f"  err {rel.max():.3e}, worst err / bound {np.max(rel / (bound + 1e-300)):.3f}; "
+             f"SNP coefficient rel {srel:.3e} ({se:.3e} SE), var rel {vrel:.3e}, "
+             f"against 16 u kappa {worst:.3f} (kappa <= {kmax:.1f})")
+        assert np.all(rel <= 2.0 * bound + 1e-13) and worst <= 1.0
         return
     err = normwise(b, bo)
     verr = float(np.max(np.abs(var - vo) / np.abs(vo)))
@@ -555,7 +637,8 @@ def test_random_shapes_vs_oracle(precision, n, p, t, m, dev_block, x_dtype, on_d
             b, var, info = b.cpu().numpy(), var.cpu().numpy(), info.cpu().numpy()
     else:
         b, var, info = run(prob, XR, **kw)
-    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
+    bo, vo, io = orc.solve(XR)
     assert np.array_equal(info, io)
     ok = io == 0
     assert b.shape == (m, t, p)
@@ -572,13 +655,16 @@ def test_random_shapes_vs_oracle(precision, n, p, t, m, dev_block, x_dtype, on_d
             bound = rounding_bound(prob, XR[ok], bo[ok][:, j:j + 1, :], 2.0 ** -24, 2.0 ** -24)
             worst = max(worst, float(np.max(relj / (bound + 1e-300))))
             assert np.all(relj <= 2.0 * bound + 1e-13)
-        _say(f"  err {rel.max():.3e}, worst err / bound {worst:.3f}")
-        if n >= 500:   # past the small-n cancellation the workload's bar holds
-            assert rel.max() < TOL_FP32
+        srel, vrel, se = snp_errors(b, bo, var, vo, ok)
+        fl, kmax = reduced_floor(orc, XR, b, bo, var, vo, ok, U32)
+        _say(f"  err {rel.max():.3e}, worst err / bound {worst:.3f}; SNP coefficient rel {srel:.3e} "
+             f"({se:.3e} SE), var rel {vrel:.3e}, against 16 u kappa {fl:.3f} (kappa <= {kmax:.1f})")
+        assert fl <= 1.0
     else:
         tol = TOL_FP64 if (precision == "fp64" or n >= 100) else 1e-8
-        _say(f"  err {rel.max():.3e}")
-        assert rel.max() < tol
+        srel, vrel, se = snp_errors(b, bo, var, vo, ok)
+        _say(f"  err {rel.max():.3e}; SNP coefficient {se:.3e} SE, var rel {vrel:.3e}")
+        assert rel.max() < tol and se < tol
 
 
 def _random_groups(count=8, seed=2025):
