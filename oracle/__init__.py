@@ -3,6 +3,6 @@
 Only the tests, the entry module's smoke check and the benchmark's CPU-baseline
 leg import this package; the GPU library never does.
 """
-from .gls import GLSOracle, gls_literal, solve_normal_equations, RANK_TOL
+from .gls import GLSOracle, GLSWhitenedQR, gls_literal, solve_normal_equations, RANK_TOL
 
-__all__ = ["GLSOracle", "gls_literal", "solve_normal_equations", "RANK_TOL"]
+__all__ = ["GLSOracle", "GLSWhitenedQR", "gls_literal", "solve_normal_equations", "RANK_TOL"]

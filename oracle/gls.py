@@ -81,6 +81,54 @@ class GLSOracle:
         return solve_normal_equations(N, r, self.rank_tol)
 
 
+class GLSWhitenedQR:
+    """Eq. (1) through the reduction of Section 2 with its other OLS solver.
+
+    Section 2 turns each GLS problem into ordinary least squares by whitening
+    with a factor of M (M = L L^T, Xbar_i = L^-1 X_i, ybar = L^-1 y) and names
+    QR as the alternative to the normal equations for the OLS step.  This
+    class does exactly that: a Cholesky factor of M and triangular solves
+    (LAPACK primitives) for the whitening, then Householder QR of every
+    whitened Xbar_i = [Xbar_L | xbar_i] (numpy), b_i = R^-1 Q^T ybar and
+    var_i = [(Xbar_i^T Xbar_i)^-1]_pp = 1 / R_pp^2.  It forms no M^-1 X_i and
+    no normal equations, so where M is ill-conditioned its SNP coefficients
+    keep far more digits than those of GLSOracle (whose X_i^T M^-1 X_i loses
+    about kappa(M) u): it serves as the reference of the SNP coefficient in
+    standard-error units there.  info_i = p when R_pp^2 falls to or below
+    rank_tol * ||xbar_i||^2 (the Schur complement s_i against S_BR, as in
+    GLSOracle).
+    """
+
+    def __init__(self, M, XL, Y, rank_tol: float = RANK_TOL):
+        M = np.asarray(M, dtype=np.float64)
+        self.n = M.shape[0]
+        XL = np.asarray(XL, dtype=np.float64).reshape(self.n, -1)
+        self.p = XL.shape[1] + 1
+        self.rank_tol = rank_tol
+        self._L = sla.cholesky(M, lower=True, check_finite=True)
+        self.XLb = sla.solve_triangular(self._L, XL, lower=True)
+        self.Yb = sla.solve_triangular(self._L, _as_2d(Y), lower=True)
+
+    def solve(self, XR):
+        """b (m,t,p), var (m,), info (m,) int32 for SNP-major dosages XR (m,n)."""
+        XR = np.asarray(XR, dtype=np.float64)
+        m, p, t = XR.shape[0], self.p, self.Yb.shape[1]
+        b = np.full((m, t, p), np.nan)
+        var = np.full(m, np.nan)
+        info = np.zeros(m, dtype=np.int32)
+        Zb = sla.solve_triangular(self._L, XR.T, lower=True)        # n x m
+        for i in range(m):
+            Xb = np.column_stack([self.XLb, Zb[:, i]])
+            Q, R = np.linalg.qr(Xb)
+            rpp2 = R[p - 1, p - 1] ** 2
+            if not rpp2 > self.rank_tol * float(Zb[:, i] @ Zb[:, i]):
+                info[i] = p
+                continue
+            b[i] = sla.solve_triangular(R, Q.T @ self.Yb).T
+            var[i] = 1.0 / rpp2
+        return b, var, info
+
+
 def solve_normal_equations(N, r, rank_tol: float = RANK_TOL):
     """Solve N_i b_i = r_i per SNP (LU with pivoting), with var_i and info_i."""
     m, p, _ = N.shape

@@ -13,7 +13,7 @@ about 1e4) at n = 5,000 and 20,000 against the oracle.
 import numpy as np
 import pytest
 
-from oracle import GLSOracle
+from oracle import GLSOracle, GLSWhitenedQR
 from paper_1304_2272_amd import binding, synth
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -89,9 +89,14 @@ def test_n20000_fp64_whole_stream_from_pinned_host_vs_oracle():
 @pytest.mark.parametrize("h2", [0.9, 0.99, 0.999])
 def test_high_heritability_vs_oracle(n, h2):
     # M = h^2 Phi + (1 - h^2) I with Phi of rank 2,000 < n: kappa(M) grows as
-    # 1 / (1 - h^2), about 1e4 at h^2 = 0.999.  The explicit inverse L^-1 of
-    # the float64 and int8-slice products is held to the float64 bar there;
-    # the float32 product's error is reported against 16 u kappa_i.
+    # 1 / (1 - h^2), about 1.7e4 at h^2 = 0.999.  b and var of the float64 and
+    # int8-slice products (explicit inverse L^-1) are held to the float64 bar
+    # against the oracle.  The SNP coefficient in standard-error units is
+    # checked against the whitened-QR route of Section 2, whose error there
+    # is a few kappa(M) u: the oracle's normal equations X_i^T M^-1 X_i lose
+    # about a hundred times that (2e-10 at n = 20,000, h^2 = 0.999 against an
+    # extended-precision solution), more than the products' own error.  The
+    # float32 product's error is held to 16 u kappa_i.
     import torch
     p, m, seed = 4, 256, 1400 + int(h2 * 1000)
     dev = torch.device("cuda:0")
@@ -101,11 +106,16 @@ def test_high_heritability_vs_oracle(n, h2):
     # Phi has rank 2,000 < n: the smallest eigenvalue of M is sigma^2 (1 - h^2)
     from scipy.sparse.linalg import eigsh
     lmax = float(eigsh(M, k=1, which="LA", return_eigenvectors=False)[0])
-    _say(f"n={n} h2={h2}: kappa(M) = {lmax / (prob['sigma2'] * (1.0 - h2)):.3g}")
+    kappa_m = lmax / (prob["sigma2"] * (1.0 - h2))
+    _say(f"n={n} h2={h2}: kappa(M) = {kappa_m:.3g}")
     orc = GLSOracle(M, prob["XL"], prob["Y"])
     bo, vo, io = orc.solve(XR)
+    bq, vq, iq = GLSWhitenedQR(M, prob["XL"], prob["Y"]).solve(XR)
+    assert np.array_equal(io, iq)
     N, _ = orc.normal_equations(XR)
     kappa = N[:, -1, -1] * vo
+    _, _, se_ref = snp_errors(bo, bq, vo, vq)
+    _say(f"  oracle vs whitened QR: SNP coefficient {se_ref:.3e} SE")
     XL, Y = torch.from_numpy(prob["XL"]).to(dev), torch.from_numpy(prob["Y"]).to(dev)
     for precision in ("fp64", "int8", "fp32"):
         with binding.GwasContext(prob["M"], XL, Y, precision=precision, x_dtype="i8",
@@ -113,16 +123,18 @@ def test_high_heritability_vs_oracle(n, h2):
             b, var, info = ctx.stream_block(XR)
         assert np.array_equal(info, io)
         err = normwise(b, bo)
-        srel, vrel, se = snp_errors(b, bo, var, vo)
-        _say(f"  {precision}: normwise {err:.3e}, SNP coefficient {se:.3e} SE / rel {srel:.3e}, var rel {vrel:.3e}")
+        _, vrel, _ = snp_errors(b, bo, var, vo)
+        srel, _, se = snp_errors(b, bq, var, vq)
+        _say(f"  {precision}: normwise {err:.3e}, var rel {vrel:.3e}; against whitened QR: SNP coefficient "
+             f"{se:.3e} SE ({se / (kappa_m * 2.0 ** -53):.1f} kappa(M) u) / rel {srel:.3e}")
         if precision == "fp32":
             lim = 16 * 2.0 ** -24 * kappa
-            rel = np.abs(b[:, 0, -1] - bo[:, 0, -1]) / np.abs(bo[:, 0, -1])
-            worst = max(float(np.max(rel / lim)), float(np.max(np.abs(var - vo) / vo / lim)))
+            rel = np.abs(b[:, 0, -1] - bq[:, 0, -1]) / np.abs(bq[:, 0, -1])
+            worst = max(float(np.max(rel / lim)), float(np.max(np.abs(var - vq) / vq / lim)))
             _say(f"    against 16 u kappa_i: {worst:.3f} (kappa_i <= {kappa.max():.2f})")
             assert worst <= 1.0
         else:
-            assert err < 1e-10 and se < 1e-10 and vrel < 1e-10
+            assert err < 1e-10 and vrel < 1e-10 and se < 1e-10
 
 
 @pytest.fixture(scope="module")
@@ -162,7 +174,10 @@ def test_n50000_reduced_vs_fp64_all_snps(n50k, precision, tol):
         # the stated floor 16 u kappa_i with kappa_i >= 1
         assert srel < 16 * 2.0 ** -24 and vrel < 16 * 2.0 ** -24
     else:
-        assert se < 1e-10 and srel < 1e-10 and vrel < 1e-10
+        # b_SNP is noise around a true zero effect, so its relative error is
+        # unbounded near zero; in standard-error units and through var it is
+        # held to the float64 bar
+        assert se < 1e-10 and vrel < 1e-10
 
 
 @pytest.mark.timeout(600)

@@ -8,7 +8,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import GLSOracle, gls_literal
+from oracle import GLSOracle, GLSWhitenedQR, gls_literal
 from oracle import gls as oracle_gls
 from paper_1304_2272_amd import synth
 
@@ -284,3 +284,110 @@ def test_planted_mistakes_are_caught(bad):
     wrong, _, _ = bad(prob["M"], prob["XL"], y).solve(XR[k:k + 1])
     assert np.max(np.abs(wrong[0, 0] - want)) > 1e-3
 
+
+
+# -- the whitened-QR route (Section 2's other OLS solver) ---------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_whitened_qr_exact_rationals(seed):
+    # the same integer problems as P1: both routes give the exact b
+    rng = np.random.default_rng(100 + seed)
+    n, m = 7, 4
+    A = rng.integers(-3, 4, size=(n, n))
+    M = A.T @ A + np.eye(n, dtype=np.int64)
+    XL = np.column_stack([np.ones(n, dtype=np.int64), rng.integers(-4, 5, size=n)])
+    y = rng.integers(-9, 10, size=n)
+    XR = rng.integers(0, 3, size=(m, n))
+    bq, vq, iq = GLSWhitenedQR(M, XL, y).solve(XR)
+    Mf = [[Fraction(int(v)) for v in row] for row in M]
+    for i in range(m):
+        Xi = [[Fraction(int(XL[r, 0])), Fraction(int(XL[r, 1])), Fraction(int(XR[i, r]))] for r in range(n)]
+        Af = _frac_solve(Mf, Xi)
+        N = _frac_mm(_frac_T(Xi), Af)
+        rhs = _frac_mm(_frac_T(Af), [[Fraction(int(v))] for v in y])
+        bex = [row[0] for row in _frac_solve(N, rhs)]
+        Ninv = _frac_solve(N, [[Fraction(int(r == c)) for c in range(3)] for r in range(3)])
+        assert iq[i] == 0
+        assert _rel(bq[i, 0], [float(v) for v in bex]) < 1e-13
+        assert abs(vq[i] - float(Ninv[2][2])) <= 1e-13 * abs(float(Ninv[2][2]))
+
+
+def test_whitened_qr_planted_ols_traits_and_rank():
+    prob = synth.make_problem(300, 4, seed=11, noise=False)
+    XR = synth.snp_block(300, 11, 0, 30)
+    b, _, info = GLSWhitenedQR(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert (info == 0).all()
+    want = np.concatenate([prob["beta"][:, 0], [0.0]])
+    assert np.max(np.abs(b[:, 0, :] - want)) < 1e-10
+    # M = I: ordinary least squares
+    rng = np.random.default_rng(5)
+    n = 80
+    XL = np.column_stack([np.ones(n), rng.standard_normal((n, 2))])
+    Y = rng.standard_normal((n, 3))
+    XR = rng.integers(0, 3, size=(6, n)).astype(np.float64)
+    b, _, _ = GLSWhitenedQR(np.eye(n), XL, Y).solve(XR)
+    for i in range(6):
+        ref = np.linalg.lstsq(np.column_stack([XL, XR[i]]), Y, rcond=None)[0]
+        assert _rel(b[i], ref.T) < 1e-12
+    # rank-deficient SNPs flagged as by the plain route
+    M, XL, y, XR = _problem(40, 4, 5, seed=13)
+    XR[2] = 2.0
+    XR[4] = 0.0
+    b, var, info = GLSWhitenedQR(M, XL, y).solve(XR)
+    assert list(info) == [0, 0, 4, 0, 4] and np.isnan(b[2]).all() and np.isnan(var[4])
+    bo, vo, _ = GLSOracle(M, XL, y).solve(XR)
+    assert _rel(b[[0, 1, 3]], bo[[0, 1, 3]]) < 1e-11 and _rel(var[[0, 1, 3]], vo[[0, 1, 3]]) < 1e-11
+
+
+def _refined_reference(M, XL, y, XR):
+    """b_SNP and var of Eq. (1) to near extended precision: M^-1 [x | X_L | y]
+    by float64 LU with three steps of iterative refinement whose residuals
+    are formed in long double, then the p x p normal equations in long
+    double (Gauss-Jordan)."""
+    import scipy.linalg as sla
+    m, n = XR.shape
+    p = XL.shape[1] + 1
+    R = np.concatenate([XR.T, XL, y[:, None]], axis=1)
+    lu = sla.lu_factor(M)
+    A = sla.lu_solve(lu, R).astype(np.longdouble)
+    Ml, Rl = M.astype(np.longdouble), R.astype(np.longdouble)
+    for _ in range(3):
+        A = A + sla.lu_solve(lu, (Rl - Ml @ A).astype(np.float64)).astype(np.longdouble)
+    bs = np.empty(m)
+    vs = np.empty(m)
+    for i in range(m):
+        cols = list(range(m, m + p - 1)) + [i]
+        N = Rl[:, cols].T @ A[:, cols]
+        r = A[:, cols].T @ Rl[:, -1]
+        aug = np.concatenate([N, r[:, None], np.eye(p, dtype=np.longdouble)], axis=1)
+        for k in range(p):
+            aug[k] = aug[k] / aug[k, k]
+            for j in range(p):
+                if j != k:
+                    aug[j] = aug[j] - aug[j, k] * aug[k]
+        bs[i] = float(aug[p - 1, p])
+        vs[i] = float(aug[p - 1, 2 * p])
+    return bs, vs
+
+
+def test_whitened_qr_keeps_snp_digits_at_high_condition():
+    # h^2 = 0.9999 with Phi of rank 60 < n: kappa(M) about 1e5.  Against an
+    # extended-precision solution the whitened QR route's SNP coefficients in
+    # standard-error units are within a few kappa(M) u (the forward error of a
+    # backward-stable solve), while the plain route's X_i^T M^-1 X_i loses
+    # about a hundred times more (printed)
+    n, p, m, seed = 400, 4, 40, 31
+    prob = synth.make_problem(n, p, seed, h2=0.9999, k=60)
+    M, XL, y = prob["M"], prob["XL"], prob["Y"][:, 0]
+    XR = synth.snp_block(n, seed, 0, m)
+    ev = np.linalg.eigvalsh(M)
+    assert ev[-1] / ev[0] > 1e4
+    bs, vs = _refined_reference(M, XL, y, XR)
+    bq, vq, _ = GLSWhitenedQR(M, XL, y).solve(XR)
+    bo, vo, _ = GLSOracle(M, XL, y).solve(XR)
+    se_q = np.max(np.abs(bq[:, 0, -1] - bs) / np.sqrt(vs))
+    se_o = np.max(np.abs(bo[:, 0, -1] - bs) / np.sqrt(vs))
+    print(f"kappa(M) {ev[-1] / ev[0]:.3g}: SE error whitened QR {se_q:.3e}, normal equations {se_o:.3e}")
+    kappa = ev[-1] / ev[0]
+    assert se_q < 4.0 * kappa * 2.0 ** -53
+    assert _rel(vq, vs) < 1e-11 and _rel(vo, vs) < 1e-9
