@@ -203,6 +203,31 @@ int gwas_stream_block_async(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t 
 int gwas_stream_wait(gwas_ctx* ctx);
 
 /*
+ * For callers that cannot allocate memory or wait on the host: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same solves as gwas_stream_block, queued on the context's stream (the
+ * desc's `stream`) behind the work queued there and on the context, and
+ * returned from at once: the outputs are written when that stream reaches
+ * this point.  The call allocates nothing (no hipMalloc, hipFree, pinned
+ * memory or events) and copies nothing between host and device: XR (16-byte
+ * aligned, ldx * element size a multiple of 16 and at most 4 MiB), b,
+ * var_snp and info must all be device memory (GWAS_E_INVALID otherwise).
+ * The per-SNP scratch of each sub-block (the product's partial sums, their
+ * chunk totals and, in the reduced modes, the cross products x^T W) lives in
+ * one static device buffer of 256 MiB that every GPU the library runs on
+ * holds until the process ends; sub-blocks are as wide as fits it (at most
+ * dev_block columns).  A context whose scratch for 128 SNP columns exceeds
+ * 256 MiB (large n with many traits) gets GWAS_E_INVALID, with the sizes in
+ * gwas_last_error.  Results equal gwas_stream_block's bit for bit.  All
+ * contexts on one device share the buffer: calls that overlap in time on
+ * one device (other streams, other contexts, other host threads) race and
+ * must be ordered by the caller.  Kernel timing does not cover these calls.
+ * Errors as gwas_stream_block.
+ */
+int gwas_stream_block_noalloc(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t mblk,
+                              double* b, int64_t ldb, double* var_snp, int32_t* info);
+
+/*
  * Several cohorts at once (the multi-cohort, multi-trait workload): contexts
  * with their own M, X_L, y and n, sharing the SNP positions of a block of
  * mblk SNPs.  Each sub-block of every context goes into ONE grouped launch

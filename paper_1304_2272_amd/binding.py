@@ -33,7 +33,8 @@ FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_fre
              "gwas_strerror", "gwas_info", "gwas_last_error", "gwas_set_timing",
              "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
              "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe",
-             "gwas_test_inject_fault", "gwas_stream_block_async", "gwas_stream_wait")
+             "gwas_test_inject_fault", "gwas_stream_block_async", "gwas_stream_wait",
+             "gwas_stream_block_noalloc")
 GROUP_GRAPH = 1
 
 
@@ -118,6 +119,8 @@ def load():
     L.gwas_stream_block_async.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
     L.gwas_stream_wait.restype = ctypes.c_int
     L.gwas_stream_wait.argtypes = [vp]
+    L.gwas_stream_block_noalloc.restype = ctypes.c_int
+    L.gwas_stream_block_noalloc.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
     _lib = L
     return L
 
@@ -268,6 +271,22 @@ class GwasContext:
                                                ptr(var) if var is not None else None,
                                                ptr(info) if info is not None else None)
         self._pending.append((keep, XR, out))
+        self._check(rc)
+
+    def stream_block_noalloc(self, XR, out):
+        """Queue the block on the context's stream without any allocation
+        (``gwas_stream_block_noalloc``); XR and ``out`` = (b, var, info) are
+        device tensors, valid once that stream has reached this point."""
+        xp, ldx, keep, xdev = _ptr_ld(XR, np.int8 if self.x_dtype == "i8" else np.float64, "XR")
+        m = XR.shape[0] if XR.ndim == 2 else 1
+        b, var, info = out
+        if not (xdev and all(a is None or (_is_torch(a) and a.is_cuda) for a in out)):
+            raise TypeError("stream_block_noalloc takes device tensors only")
+        if keep.data_ptr() != XR.data_ptr():
+            raise ValueError("XR must have unit stride along n: the call copies nothing")
+        rc = self._lib.gwas_stream_block_noalloc(self._h, xp, ldx, m, b.data_ptr(), self.p * self.t,
+                                                 var.data_ptr() if var is not None else None,
+                                                 info.data_ptr() if info is not None else None)
         self._check(rc)
 
     def wait(self):

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,8 +38,33 @@ struct Layout {
     size_t off_xbuf[2], off_part, off_red, off_xw, off_xwpart, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
     size_t sched_len;
+    // gwas_stream_block_noalloc: sub-block width whose per-SNP scratch fits
+    // the static device buffer (0: not even one column tile fits), and the
+    // room of its tile schedule in the workspace
+    int64_t na_cols;
+    size_t na_sched_len, off_sched_na;
     size_t total;
 };
+
+// The static device buffer of gwas_stream_block_noalloc.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+constexpr size_t NOALLOC_ALIGN = 256;
+
+// Offsets, in a buffer of per-SNP scratch for `cols` columns, of the
+// product's partial sums, their chunk totals and (reduced modes) the cross
+// products x^T W with their split-K partials; [4] is the end.
+void noalloc_offsets(const Layout& L, int64_t cols, size_t off[5]) {
+    const bool red = L.precision != GWAS_FP64;
+    const size_t sz[4] = {
+        (size_t)L.npb_max * L.Q * cols * 8, (size_t)chunks_of(L.npb_max) * L.Q * cols * 8,
+        red ? (size_t)L.Qc * cols * 8 : 0, red ? (size_t)xw_splits(L.n) * L.Qc * cols * 8 : 0};
+    size_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+        off[i] = o;
+        o = (o + sz[i] + NOALLOC_ALIGN - 1) / NOALLOC_ALIGN * NOALLOC_ALIGN;
+    }
+    off[4] = o;
+}
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -106,6 +132,27 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     }
     L.off_sched = take(L.sched_len * 2 * 4);
     L.off_sched_tail = take(L.sched_len * 2 * 4);
+    // the widest multiple of 128 columns (at most dev_block) whose scratch
+    // fits the static buffer, and room for its schedule in every shape
+    {
+        int64_t lo = 0, hi = L.dev_block / TILE_N;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            size_t off[5];
+            noalloc_offsets(L, mid * TILE_N, off);
+            if (off[4] <= NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+        }
+        L.na_cols = lo * TILE_N;
+        L.na_sched_len = 0;
+        if (L.na_cols > 0)
+            for (int c = 0; c < trmm_num_cfgs(); ++c) {
+                if (at == A_I8S ? c > 0 : !trmm_cfg_valid(at, xt, c)) continue;
+                for (int r : {0, 1, 2, 4, 8})
+                    L.na_sched_len = std::max(L.na_sched_len, (size_t)trmm_schedule_len(
+                                                                  L.n_pad, L.na_cols, trmm_geom(at, xt, c, slices, r)));
+            }
+        L.off_sched_na = take(std::max<size_t>(L.na_sched_len, 1) * 2 * 4);
+    }
     // region shared by the set-up temporary and the streaming buffers
     L.off_region = o;
     const size_t elem = (x_dtype == GWAS_X_I8) ? 1 : 8;
@@ -162,6 +209,9 @@ struct gwas_ctx {
     int* sched = nullptr;
     int* sched_tail = nullptr;
     int64_t tail_cols = -1;
+    int* sched_na = nullptr;        // schedule of gwas_stream_block_noalloc's sub-blocks
+    char* nscratch = nullptr;       // device address of this device's static scratch
+    hipEvent_t ev_na = nullptr;     // orders gwas_stream_block_noalloc after queued work
     int at = A_F64;
     int cfg = 0;
     int rgroup = 0;                 // schedule row group (0: the traffic model's choice)
@@ -190,6 +240,36 @@ struct gwas_ctx {
     struct Group* grp = nullptr;    // grouped-launch state, owned by the first context of a group
     struct Back* back = nullptr;    // reverse-pass state (gwas_backward_*)
 };
+
+// Scratch of gwas_stream_block_noalloc (per-SNP partial sums, chunk totals
+// and cross products of one sub-block).  Each device holds its own copy for
+// the life of the process; host code uses only the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, which must be current; looked
+// up once per device.
+int noalloc_scratch(int dev, char** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return GWAS_E_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return GWAS_E_HIP;
+        }
+        scratch_addr[dev] = ptr;
+    }
+    *out = static_cast<char*>(scratch_addr[dev]);
+    return GWAS_OK;
+}
+}  // namespace
 
 // Reverse-pass state: M^-1 = U U^T, W = M^-1 [X_L | y], the constants
 // W_L^T W_L and W_L^T w_y, per-sub-block scratch and the accumulators.
@@ -436,6 +516,7 @@ void release(gwas_ctx* c) {
     if (c->s_d2h) (void)hipStreamDestroy(c->s_d2h);
     if (c->own_comp && c->s_comp) (void)hipStreamDestroy(c->s_comp);
     if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+    if (c->ev_na) (void)hipEventDestroy(c->ev_na);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     (void)hipGetLastError();
 }
@@ -451,6 +532,22 @@ int upload_schedule(gwas_ctx* c, int64_t cols, int* dst, std::vector<int>& host)
     }
     HIPCHK(c, hipMemcpyAsync(dst, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice,
                              c->s_comp));
+    return GWAS_OK;
+}
+
+// Schedule of gwas_stream_block_noalloc's sub-blocks (na_cols columns; the
+// last sub-block of a call may be narrower and runs the same schedule).
+int upload_noalloc_schedule(gwas_ctx* c) {
+    const Layout& Y = c->lay;
+    if (Y.na_cols <= 0) return GWAS_OK;
+    const int64_t len = trmm_schedule_len(Y.n_pad, Y.na_cols, c->shape);
+    std::vector<int> host((size_t)(2 * len), 0);
+    if (len > (int64_t)Y.na_sched_len || trmm_schedule(Y.n_pad, Y.na_cols, c->shape, host.data(), len) != len) {
+        c->err = "tile schedule does not fit";
+        return GWAS_E_INVALID;
+    }
+    // synchronous: the host vector is released on return
+    HIPCHK(c, hipMemcpy(c->sched_na, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
     return GWAS_OK;
 }
 
@@ -589,6 +686,8 @@ int init_body(gwas_ctx* c, const gwas_desc* d) {
     }
     rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
     if (rc) return rc;
+    rc = upload_noalloc_schedule(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(s));
     int flags[2] = {0, 0};
     HIPCHK(c, hipMemcpy(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost));
@@ -652,6 +751,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     };
     DeviceScope scope;
     if (hipSetDevice(d->device) != hipSuccess) return bail(GWAS_E_NO_DEVICE);
+    if (int rc2 = noalloc_scratch(d->device, &c->nscratch)) return bail(rc2);
     if (d->workspace) {
         if (d->workspace_bytes < Y.total) return bail(GWAS_E_WORKSPACE);
         c->ws = static_cast<char*>(d->workspace);
@@ -676,6 +776,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->flags = (int*)(w + Y.off_flags);
     c->sched = (int*)(w + Y.off_sched);
     c->sched_tail = (int*)(w + Y.off_sched_tail);
+    c->sched_na = (int*)(w + Y.off_sched_na);
     for (int s = 0; s < 2; ++s) {
         c->xbuf[s] = w + Y.off_xbuf[s];
         c->bbuf[s] = (double*)(w + Y.off_b[s]);
@@ -694,6 +795,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     hipError_t e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking);
     c->own_comp = true;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_na, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_h2d, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_d2h, hipStreamNonBlocking);
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {
@@ -866,6 +968,59 @@ int gwas_stream_wait(gwas_ctx* c) {
     DeviceScope scope;
     HIPCHK(c, hipSetDevice(c->device));
     return settle(c);
+}
+
+int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
+                              int64_t ldb, double* var_snp, int32_t* info) {
+    if (!live(c)) return GWAS_E_STATE;
+    if (int rc = check_block_args(c, XR, ldx, mblk, b, ldb)) return rc;
+    if (mblk == 0) return GWAS_OK;
+    const Layout& Y = c->lay;
+    if (Y.na_cols <= 0) {
+        size_t off[5];
+        noalloc_offsets(Y, TILE_N, off);
+        char msg[200];
+        snprintf(msg, sizeof(msg), "gwas_stream_block_noalloc: the scratch of %d SNP columns needs %zu bytes, "
+                 "more than the static buffer's %zu", TILE_N, off[4], NOALLOC_SCRATCH_BYTES);
+        c->err = msg;
+        return GWAS_E_INVALID;
+    }
+    DeviceScope scope;
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t elem = (Y.x_dtype == GWAS_X_I8) ? 1 : 8;
+    if (!(on_device(XR) && reinterpret_cast<uintptr_t>(XR) % 16 == 0 && (ldx * (int64_t)elem) % 16 == 0 &&
+          ldx * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES) ||
+        !on_device(b) || (var_snp && !on_device(var_snp)) || (info && !on_device(info))) {
+        c->err = "gwas_stream_block_noalloc: XR (16-byte aligned, ldx bytes a multiple of 16, at most 4 MiB), "
+                 "b, var_snp and info must be device memory";
+        return GWAS_E_INVALID;
+    }
+    hipStream_t s = c->s_user;
+    // behind the blocks queued on the context's own streams
+    HIPCHK(c, hipEventRecord(c->ev_na, c->s_comp));
+    HIPCHK(c, hipStreamWaitEvent(s, c->ev_na, 0));
+    size_t off[5];
+    noalloc_offsets(Y, Y.na_cols, off);
+    // the float64 mode takes its cross terms from the partial sums (no x^T W)
+    const bool red = Y.precision != GWAS_FP64;
+    const SubScratch sc{reinterpret_cast<double*>(c->nscratch + off[0]), reinterpret_cast<double*>(c->nscratch + off[1]),
+                        red ? reinterpret_cast<double*>(c->nscratch + off[2]) : nullptr,
+                        red ? reinterpret_cast<double*>(c->nscratch + off[3]) : nullptr, Y.na_cols};
+    const char* xr = static_cast<const char*>(XR);
+    for (int64_t col0 = 0; col0 < mblk; col0 += Y.na_cols) {
+        const int64_t cols = std::min<int64_t>(Y.na_cols, mblk - col0);
+        const void* xptr = xr + (size_t)col0 * ldx * elem;
+        TrmmArgs ta = trmm_args_for(c, xptr, ldx, cols);
+        ta.part = sc.part;
+        ta.ldp = sc.ld;
+        ta.sched = c->sched_na;
+        ta.sched_cols = Y.na_cols;
+        ta.n_sched = trmm_schedule_len(Y.n_pad, Y.na_cols, c->shape);
+        HIPCHK(c, trmm_stream(ta, s));
+        HIPCHK(c, finish_sub(c, sc, xptr, ldx, cols, b + (size_t)col0 * ldb, ldb,
+                             var_snp ? var_snp + col0 : nullptr, info ? info + col0 : nullptr, s));
+    }
+    return GWAS_OK;
 }
 
 namespace {
@@ -1177,6 +1332,8 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     int rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
+    rc = upload_noalloc_schedule(c);
+    if (rc) return rc;
     if (best_rgroup) *best_rgroup = best_rg;
     if (best_cfg) *best_cfg = best;
     return GWAS_OK;

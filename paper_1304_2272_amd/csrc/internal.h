@@ -107,6 +107,8 @@ struct TrmmArgs {
     const int* sched; int64_t n_sched;
     int full_k;                 // A is a full (not lower-triangular) n_pad x n_pad matrix
     int rgroup;                 // row tiles per L2 group of the schedule (0: the model's choice)
+    int64_t sched_cols;         // columns the schedule was built for (0: cols); workgroups
+                                // whose column tile starts at or past cols return at once
 };
 hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s);
 // the int8-slice kernel (a.at == A_I8S); called by trmm_stream

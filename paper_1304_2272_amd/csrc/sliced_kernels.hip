@@ -45,6 +45,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
     // registers once: read through a reference, every field would be loaded
     // again after each barrier (a barrier is a memory fence).
     const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+    // a schedule built for more columns than this launch has (sched_cols)
+    if ((int64_t)J * TN >= a.cols) return;
 
     __shared__ __attribute__((aligned(16))) char As[2][TMS * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];

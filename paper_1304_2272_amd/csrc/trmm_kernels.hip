@@ -134,6 +134,8 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     // registers once: read through a reference, every field would be loaded
     // again after each barrier (a barrier is a memory fence).
     const TrmmArgs a = GROUPED ? la.group[e0 >> SCHED_CTX_SHIFT] : la;
+    // a schedule built for more columns than this launch has (sched_cols)
+    if ((int64_t)J * TN >= a.cols) return;
 
     __shared__ __attribute__((aligned(16))) char As[2][TM * ROW_STRIDE];
     __shared__ __attribute__((aligned(16))) char Bs[2][TN * ROW_STRIDE];
@@ -671,7 +673,9 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
         if ((int64_t)sh.tm * a.ldu * asz > INT32_MAX || ((int64_t)sh.tn * a.ldx + a.n_pad) * (int64_t)xs > INT32_MAX)
             return hipErrorInvalidValue;
     }
-    if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, a.cols, sh)))
+    const int64_t scols = a.sched_cols ? a.sched_cols : a.cols;
+    if (scols < a.cols) return hipErrorInvalidValue;
+    if (check_sched && (a.n_sched != trmm_schedule_len(a.n_pad, scols, sh)))
         return hipErrorInvalidValue;
     if (a.n_sched > 0x7fffffff) return hipErrorInvalidValue;
     return hipSuccess;

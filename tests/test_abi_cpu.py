@@ -96,6 +96,7 @@ def test_null_context_calls(lib):
     assert lib.gwas_test_inject_fault(None, 1) == 7
     assert lib.gwas_stream_block_async(None, None, 0, 0, None, 0, None, None) == 7
     assert lib.gwas_stream_wait(None) == 7
+    assert lib.gwas_stream_block_noalloc(None, None, 0, 0, None, 0, None, None) == 7
     assert lib.gwas_strerror(2).decode().startswith("M is not positive definite")
     assert lib.gwas_strerror(12345).decode() == "unknown status"
 
