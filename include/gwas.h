@@ -91,6 +91,20 @@ extern "C" {
                                   the p x p solve as in GWAS_FP32_REFINE.
                                   Needs x_dtype = GWAS_X_I8.                */
 
+#define GWAS_BF16X3_REFINE 4  /* L^-1 held as three bfloat16 slices per
+                                  entry (each rounds what the ones before it
+                                  leave: their sum is L^-1 to about 2^-27
+                                  relative); float64 dosages are cut into
+                                  three slices the same way while staged,
+                                  int8 dosages are exact in bfloat16.  The
+                                  products of slices i + j <= 2 (six; three
+                                  with int8 dosages) run on bfloat16 matrix
+                                  cores into the same float32 sums (float64
+                                  every 16 stages of K in the tiles that keep
+                                  float64 sums).  Cross products and the
+                                  p x p solve as in GWAS_FP32_REFINE, with
+                                  its stated error (u = 2^-24)           */
+
 /* ---- element type of the SNP dosages handed to gwas_stream_block -------- */
 #define GWAS_X_F64         0   /* float64                                   */
 #define GWAS_X_I8          1   /* int8 dosages (0, 1, 2), expanded on device */
@@ -108,7 +122,8 @@ typedef struct gwas_desc {
     const double* Y;         /* n x t phenotypes                             */
     int64_t ldy;             /* >= n                                         */
     int32_t inputs_on_device;/* nonzero: M, XL and Y are device pointers     */
-    int32_t precision;       /* GWAS_FP64 | GWAS_FP32_REFINE | GWAS_BF16_REFINE */
+    int32_t precision;       /* GWAS_FP64 | GWAS_FP32_REFINE | GWAS_BF16_REFINE
+                                | GWAS_INT8_SLICED | GWAS_BF16X3_REFINE       */
     int32_t x_dtype;         /* GWAS_X_F64 | GWAS_X_I8                       */
     int32_t device;          /* HIP device ordinal                           */
     int64_t dev_block;       /* SNP columns per device sub-block, 0 = auto   */
@@ -120,6 +135,21 @@ typedef struct gwas_desc {
                                 computes on streams of its own            */
     int32_t slices;          /* GWAS_INT8_SLICED: digits per entry, 4..6
                                 (0 = 6); ignored otherwise                  */
+    int64_t band;            /* 0: M is dense (n x n, ldm >= n).  w >= 1: M is
+                                banded, M(i,j) = 0 for |i - j| > w (relatives
+                                grouped near the diagonal, Section 5.1), and
+                                M holds its lower band in LAPACK band storage:
+                                M(i,j) at M[(i - j) + j*ldm] for
+                                j <= i <= min(n-1, j+w), ldm >= w+1.  Needs
+                                GWAS_FP64; the factor is kept as blocks of
+                                W = w rounded up to a multiple of 256 rows
+                                (block bidiagonal) and each streamed block is
+                                solved by block forward substitution, about
+                                3 n W flops per SNP instead of n^2.
+                                gwas_stream_group, gwas_autotune,
+                                gwas_stream_block_noalloc and the
+                                gwas_backward_* calls return GWAS_E_INVALID
+                                on such a context.                          */
 } gwas_desc;
 
 /*
@@ -129,6 +159,14 @@ typedef struct gwas_desc {
  */
 size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block,
                             int32_t precision, int32_t x_dtype);   /* slices = 6 */
+
+/*
+ * Device bytes a context with a banded M (half-bandwidth band >= 1, band
+ * storage with leading dimension ldm >= band + 1, GWAS_FP64) needs; 0 if
+ * the sizes are invalid.  Pure function.
+ */
+size_t gwas_workspace_bytes_band(int64_t n, int32_t p, int32_t t, int64_t dev_block, int64_t band,
+                                 int64_t ldm, int32_t x_dtype);
 
 /*
  * Create a context: copies M, X_L and y to the device, factors M = L L^T
@@ -143,7 +181,8 @@ size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block,
  * it).  Errors: GWAS_E_INVALID (n < p, p outside 2..20, t outside 1..256,
  * ld < n, NULL pointer, unknown precision or x_dtype; checked before any
  * device call; GWAS_INT8_SLICED with float64 dosages or slices outside
- * 4..6), GWAS_E_NO_DEVICE, GWAS_E_WORKSPACE, GWAS_E_OOM, GWAS_E_HIP,
+ * 4..6; band < 0, band > 0 with another precision than GWAS_FP64, or
+ * ldm < band + 1), GWAS_E_NO_DEVICE, GWAS_E_WORKSPACE, GWAS_E_OOM, GWAS_E_HIP,
  * GWAS_E_NOT_SPD (gwas_info gives the 1-based order of the first leading
  * minor of M that is not positive, as LAPACK's potrf does) and
  * GWAS_E_RANK_XL.  On GWAS_E_NOT_SPD and GWAS_E_RANK_XL *out is set so that
@@ -234,7 +273,9 @@ int gwas_stream_block_noalloc(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_
  * of the triangular product, whose tile schedule deals every (context, row
  * block) to the XCDs longest first, so cohorts of uneven n fill the chip
  * together; the cross products and p x p solves follow per context.
- * Results are identical to gwas_stream_block on each context.
+ * Each context's cross products, chunk sums and solves run on that
+ * context's own stream after the product, so those of different contexts
+ * overlap.  Results are identical to gwas_stream_block on each context.
  *
  *   ctxs, nctx   1..64 distinct contexts on one device with the same
  *                precision, x_dtype, dev_block and tile shape
@@ -243,8 +284,11 @@ int gwas_stream_block_noalloc(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_
  *                entries may be NULL)
  *   flags        GWAS_GROUP_GRAPH: full-width sub-blocks replay one HIP
  *                graph of the grouped product, cross products and solves,
- *                captured at first use (dosages are copied into and
- *                results out of fixed device buffers around each replay)
+ *                captured at first use.  With GWAS_FP64 the product reads
+ *                device dosages in place (the graph's argument array is
+ *                updated before a replay when the pointers change); other
+ *                precisions and host dosages are copied into fixed device
+ *                buffers; results are copied out of fixed buffers
  *
  * All work runs on the first context's compute stream; the call returns
  * when every output is written.  Errors: GWAS_E_INVALID (incompatible or
@@ -259,11 +303,17 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * Pick the tile shape of the triangular product and the row-group size of
  * its XCD schedule (row tiles that share one L2: 1, 2, 4 or 8) by timing
  * every admissible pair on `cols` (<= dev_block) SNP columns of XR (host or
- * device), and keep the fastest for later calls.  With the environment
+ * device), then, with that pair, the sub-block width gwas_stream_block
+ * splits blocks into (dev_block, half or a quarter of it, those of whole
+ * multiples of 128 columns that fit in `cols`), and keep the fastest for
+ * later calls (gwas_query reports the width; gwas_stream_group keeps
+ * dev_block).  With the environment
  * variable GWAS_TUNE_CACHE naming a file, an earlier result for the same
  * padded n, precision, dosage type and width is reused and new results are
- * appended.  *best_cfg (may be NULL) receives the chosen shape, -1 for
- * GWAS_INT8_SLICED (one shape); *best_rgroup (may be NULL) the row group.
+ * appended.  *best_cfg (may be NULL) receives the chosen shape (for
+ * GWAS_INT8_SLICED: 0 stages its operands through registers, 1 and 2 load
+ * them straight into LDS, 2 with a wider tile); *best_rgroup (may be NULL)
+ * the row group.
  * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged
  * up to float64 rounding order.  For the float32 and bfloat16 products a
  * shape also decides how their sums are kept: the 256 x 256 shape (6, the
@@ -353,8 +403,9 @@ int gwas_set_timing(gwas_ctx* ctx, int32_t enable);
 int gwas_kernel_time(gwas_ctx* ctx, int64_t* launches, double* total_ms,
                      int64_t* columns);
 
-/* Sizes the context was built with: n_pad (padded order of the device
- * factors), the sub-block width and the device ordinal. */
+/* Sizes of the context: n_pad (padded order of the device factors), the
+ * sub-block width of gwas_stream_block (dev_block, or the width
+ * gwas_autotune chose) and the device ordinal. */
 int gwas_query(const gwas_ctx* ctx, int64_t* n_pad, int64_t* dev_block,
                int32_t* device);
 

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgwas.so"
 GWAS_OK = 0
 ERRORS = {1: "GWAS_E_INVALID", 2: "GWAS_E_NOT_SPD", 3: "GWAS_E_RANK_XL", 4: "GWAS_E_NO_DEVICE",
           5: "GWAS_E_HIP", 6: "GWAS_E_OOM", 7: "GWAS_E_STATE", 8: "GWAS_E_WORKSPACE"}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "int8": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "int8": 3, "bf16x3": 4}
 X_DTYPES = {"f64": 0, "i8": 1}
 
 FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_free",
@@ -34,7 +34,7 @@ FUNCTIONS = ("gwas_workspace_bytes", "gwas_init", "gwas_stream_block", "gwas_fre
              "gwas_kernel_time", "gwas_query", "gwas_stream_group", "gwas_autotune",
              "gwas_backward_begin", "gwas_backward_block", "gwas_backward_end", "gwas_peak_probe",
              "gwas_test_inject_fault", "gwas_stream_block_async", "gwas_stream_wait",
-             "gwas_stream_block_noalloc")
+             "gwas_stream_block_noalloc", "gwas_workspace_bytes_band")
 GROUP_GRAPH = 1
 
 
@@ -50,6 +50,7 @@ class Desc(ctypes.Structure):
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("slices", ctypes.c_int32),
+        ("band", ctypes.c_int64),
     ]
 
 
@@ -80,6 +81,8 @@ def load():
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.gwas_workspace_bytes.restype = ctypes.c_size_t
     L.gwas_workspace_bytes.argtypes = [i64, i32, i32, i64, i32, i32]
+    L.gwas_workspace_bytes_band.restype = ctypes.c_size_t
+    L.gwas_workspace_bytes_band.argtypes = [i64, i32, i32, i64, i64, i64, i32]
     L.gwas_init.restype = ctypes.c_int
     L.gwas_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Desc)]
     L.gwas_stream_block.restype = ctypes.c_int
@@ -179,7 +182,9 @@ class GwasContext:
     """One factorisation of M and its derived constants, reused for every block."""
 
     def __init__(self, M, XL, Y, precision="fp64", x_dtype="f64", dev_block=0, device=0,
-                 stream=None, slices=0):
+                 stream=None, slices=0, band=0):
+        """M is (n, n), or with ``band`` = w >= 1 the lower band storage of a
+        banded M as an (n, ldm) array, ldm >= w + 1: M[j, d] = M(j + d, j)."""
         L = load()
         self._lib = L
         self.precision = precision
@@ -209,10 +214,11 @@ class GwasContext:
             p = XLt.shape[0] + 1
             t = Yt.shape[0]
         self.n, self.p, self.t = n, p, t
-        d = Desc(n=n, p=p, t=t, M=mp, ldm=n, XL=xlp, ldxl=n, Y=yp, ldy=n,
+        ldm = keep[0].shape[1] if band else n
+        d = Desc(n=n, p=p, t=t, M=mp, ldm=ldm, XL=xlp, ldxl=n, Y=yp, ldy=n,
                  inputs_on_device=1 if dev else 0, precision=PRECISIONS[precision],
                  x_dtype=X_DTYPES[x_dtype], device=device, dev_block=dev_block,
-                 workspace=None, workspace_bytes=0, stream=stream, slices=slices)
+                 workspace=None, workspace_bytes=0, stream=stream, slices=slices, band=band)
         h = ctypes.c_void_p()
         rc = L.gwas_init(ctypes.byref(h), ctypes.byref(d))
         del keep

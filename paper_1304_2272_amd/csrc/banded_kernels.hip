@@ -1,0 +1,286 @@
+// The per-block triangular solve for a banded M (the banded-matrix variant
+// the paper names as future work, Section 5.1).  With M = L L^T of
+// half-bandwidth w and blocks of W >= w rows, M is block tridiagonal and L
+// block lower bidiagonal: L_ii on the diagonal and E_i = L_{i,i-1} below it.
+// Forward substitution then runs block row by block row,
+//     Z_i = L_ii^-1 (X_i - E_i Z_{i-1}) = U_ii^T X_i + Gt_i^T Z_{i-1},
+// with U_ii = L_ii^-T and Gt_i = -E_i^T U_ii formed at set-up.  One launch
+// of band_step_kernel is one block row for every SNP column of a sub-block:
+// a float64 matrix-core product with K = [the triangular part of U_ii^T |
+// all of Gt_i^T] against [X_i | Z_{i-1}], which stores Z_i for the next
+// block row and writes the same partial sums as the dense product (S_BL,
+// bbar_B and S_BR of Algorithm 2 per 32-row slice of Z).
+#include "internal.h"
+#include "trmm_common.h"
+
+#include <algorithm>
+
+namespace gwas {
+namespace {
+
+constexpr int BT_M = 128, BT_N = 128, BT_NT = 512;   // tile and threads
+constexpr int BT_WTM = 2, BT_WTN = 4;                 // 16 x 16 blocks per wave (32 x 64)
+constexpr int BT_WGN = 2;                             // waves along the columns
+constexpr int BT_BK = 16;                             // K per stage (one 128-byte row of doubles)
+constexpr int BT_ROWS = BT_WTM * 16;                  // rows of a partial-sum slice
+
+// One BT_M x BT_N tile of Z_i per workgroup.  Stages of 16 K go global ->
+// registers -> LDS (double buffered); within a stage lane group g = lane/16
+// supplies the contiguous K slice [4g, 4g + 4) to both operands, one K per
+// instruction (the 16x16x4 float64 instruction sums its K in any order the
+// two operands agree on).  Workgroup b runs on XCD b % 8: the row tiles of a
+// column tile run on one XCD, so its dosage and Z panels stay in that L2.
+template <typename XT>
+__global__ __launch_bounds__(BT_NT) void band_step_kernel(BandArgs a) {
+    constexpr int EPC = 16 / (int)sizeof(XT);          // dosage elements per 16-byte chunk
+    const int b = blockIdx.x;
+    const int rtiles = (int)(a.W / BT_M);
+    const int q = b >> 3;
+    const int64_t ct = (b & 7) + 8 * (int64_t)(q / rtiles);
+    const int rt = q % rtiles;
+    const int64_t c0 = ct * BT_N;
+    if (c0 >= a.cols) return;
+    const int64_t r0 = (int64_t)rt * BT_M;               // first row of the tile inside the block
+    const int64_t g0 = a.blk * a.W;                      // first global row of the block
+
+    __shared__ __attribute__((aligned(16))) char As[2][BT_M * ROW_STRIDE];
+    __shared__ __attribute__((aligned(16))) char Bs[2][BT_N * ROW_STRIDE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / BT_WGN, wc = wave % BT_WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // stages: the U_ii^T part runs K up to the tile's last row (U_ii^T is
+    // lower triangular), the Gt_i^T part all W (none in block row 0)
+    const int nA = (int)(std::min<int64_t>(r0 + BT_M, a.W) / BT_BK);
+    const int nst = nA + (a.blk > 0 ? (int)(a.W / BT_BK) : 0);
+    const XT* X = reinterpret_cast<const XT*>(a.X);
+
+    d4_t acc[BT_WTM][BT_WTN];
+#pragma unroll
+    for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < BT_WTN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    // staged operands of one stage: two 16-byte chunks of A and of B per thread
+    u4_t ra[2], rb[2];
+    auto load = [&](int s) {
+        const bool pa = s < nA;
+        const int64_t k0 = (int64_t)(pa ? s : s - nA) * BT_BK;
+        const double* Ab = pa ? a.Ut : a.Gt;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int idx = tid + c * BT_NT;
+            const int row = idx >> 3, ch = idx & 7;
+            ra[c] = *reinterpret_cast<const u4_t*>(Ab + (r0 + row) * a.W + k0 + 2 * ch);
+        }
+        if (!pa) {
+            // Z_{i-1}: float64, rows 0..W-1 of every column of the sub-block
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int idx = tid + c * BT_NT;
+                const int64_t col = c0 + (idx >> 3);
+                rb[c] = col < a.cols ? *reinterpret_cast<const u4_t*>(a.Zprev + col * a.ldz + k0 + 2 * ((idx & 7)))
+                                     : u4_t{0u, 0u, 0u, 0u};
+            }
+            return;
+        }
+        // X_i: rows g0 + k0 .. of the dosages, zero past n and past the block
+        if constexpr (sizeof(XT) == 8) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int idx = tid + c * BT_NT;
+                const int64_t col = c0 + (idx >> 3);
+                const int64_t g = g0 + k0 + 2 * (idx & 7);
+                const XT* src = X + col * a.ldx + g;
+                if (col < a.cols && g + 2 <= a.n) {
+                    rb[c] = *reinterpret_cast<const u4_t*>(src);
+                } else {
+                    double t2[2] __attribute__((aligned(16)));
+                    t2[0] = (col < a.cols && g < a.n) ? (double)src[0] : 0.0;
+                    t2[1] = 0.0;
+                    rb[c] = *reinterpret_cast<const u4_t*>(t2);
+                }
+            }
+        } else {
+            // one 16-byte chunk (16 K of one column) for each of the first
+            // BT_N threads
+            if (tid < BT_N) {
+                const int64_t col = c0 + tid;
+                const int64_t g = g0 + k0;
+                const XT* src = X + col * a.ldx + g;
+                if (col < a.cols && g + EPC <= a.n) {
+                    rb[0] = *reinterpret_cast<const u4_t*>(src);
+                } else {
+                    XT tmp[EPC] __attribute__((aligned(16)));
+#pragma unroll
+                    for (int e = 0; e < EPC; ++e) tmp[e] = (col < a.cols && g + e < a.n) ? src[e] : (XT)0;
+                    rb[0] = *reinterpret_cast<const u4_t*>(tmp);
+                }
+            }
+        }
+    };
+    auto store = [&](int buf, int s) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int idx = tid + c * BT_NT;
+            *reinterpret_cast<u4_t*>(As[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = ra[c];
+        }
+        if (sizeof(XT) == 8 || s >= nA) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int idx = tid + c * BT_NT;
+                *reinterpret_cast<u4_t*>(Bs[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = rb[c];
+            }
+        } else if (tid < BT_N) {
+            // int8 dosages of one column, expanded to float64
+            const int8_t* x8 = reinterpret_cast<const int8_t*>(&rb[0]);
+            double* dst = reinterpret_cast<double*>(Bs[buf] + tid * ROW_STRIDE);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dst[e] = (double)x8[e];
+        }
+    };
+
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        const bool more = s + 1 < nst;
+        if (more) load(s + 1);
+        double fa[BT_WTM][4], fb[BT_WTN][4];
+        // a lane's 32 bytes of K of one row of A or column of B, as two
+        // 16-byte reads
+        auto frag4 = [&](const char* p, double (&f)[4]) {
+            const u4_t lo = *reinterpret_cast<const u4_t*>(p);
+            const u4_t hi = *reinterpret_cast<const u4_t*>(p + 16);
+            f[0] = __builtin_bit_cast(double, u2_t{lo[0], lo[1]});
+            f[1] = __builtin_bit_cast(double, u2_t{lo[2], lo[3]});
+            f[2] = __builtin_bit_cast(double, u2_t{hi[0], hi[1]});
+            f[3] = __builtin_bit_cast(double, u2_t{hi[2], hi[3]});
+        };
+#pragma unroll
+        for (int i = 0; i < BT_WTM; ++i)
+            frag4(As[buf] + (wr * BT_ROWS + i * 16 + li) * ROW_STRIDE + lg * 32, fa[i]);
+#pragma unroll
+        for (int j = 0; j < BT_WTN; ++j)
+            frag4(Bs[buf] + (wc * BT_WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32, fb[j]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+                for (int j = 0; j < BT_WTN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][e], fb[j][e], acc[i][j], 0, 0, 0);
+        // the other buffer held stage s - 1, which every wave finished
+        // reading before the previous barrier
+        if (more) store(buf ^ 1, s + 1);
+        __syncthreads();
+    }
+
+    // Epilogue.  Element v of accumulator (i, j) holds row
+    // r0 + wr*32 + i*16 + lg + 4v and column c0 + wc*64 + j*16 + li.
+    const int64_t rw = r0 + wr * BT_ROWS;
+    const int64_t pb = (g0 + rw) / BT_ROWS;
+    const int64_t cbase = c0 + wc * BT_WTN * 16 + li;
+    const int Q = a.Qc + 1;
+#pragma unroll
+    for (int j = 0; j < BT_WTN; ++j) {
+        const int64_t col = cbase + j * 16;
+        if (col < a.cols) {
+#pragma unroll
+            for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a.Zcur[col * a.ldz + rw + i * 16 + lg + 4 * v] = acc[i][j][v];
+        }
+    }
+    for (int qq = 0; qq < a.Qc; ++qq) {
+        const double* Cq = a.C + qq * a.ldc + g0 + rw + lg;
+        double cv[BT_WTM][4];
+#pragma unroll
+        for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + 4 * v];
+#pragma unroll
+        for (int j = 0; j < BT_WTN; ++j) {
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * cv[i][v];
+            sum = wave_sum16(sum);
+            const int64_t col = cbase + j * 16;
+            if (lg == 0 && col < a.cols) a.part[(pb * Q + qq) * a.ldp + col] = sum;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BT_WTN; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < BT_WTM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * acc[i][j][v];
+        sum = wave_sum16(sum);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+    }
+}
+
+// Block (row0.., col0..) of M, rows x cols, from LAPACK lower band storage
+// (M(i, j) at AB[(i - j) + j*ldab] for j <= i <= j + w): entries above the
+// diagonal, outside the band or past n are zero, the diagonal past n one.
+__global__ void band_block_kernel(const double* __restrict__ AB, int64_t ldab, int64_t w, int64_t n, int64_t row0,
+                                  int64_t col0, int64_t rows, int64_t cols, double* __restrict__ out, int64_t ldo) {
+    for (int64_t c = blockIdx.x; c < cols; c += gridDim.x)
+        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+            const int64_t i = row0 + r, j = col0 + c;
+            double v = 0.0;
+            if (i >= j && i - j <= w) {
+                if (i < n) v = AB[(i - j) + j * ldab];
+                else if (i == j) v = 1.0;
+            }
+            out[r + c * ldo] = v;
+        }
+}
+
+}  // namespace
+
+int band_part_rows() { return BT_ROWS; }
+
+hipError_t band_step(const BandArgs& a, hipStream_t s) {
+    if (a.cols <= 0) return hipSuccess;
+    if (!a.Ut || !a.X || !a.Zcur || !a.part || !a.C || (a.blk > 0 && (!a.Gt || !a.Zprev)))
+        return hipErrorInvalidValue;
+    if (a.W < BT_M || a.W % 256 || a.blk < 0 || a.n < 1 || a.ldz < a.W || a.ldp < a.cols ||
+        a.ldc < (a.blk + 1) * a.W || a.Qc < 1)
+        return hipErrorInvalidValue;
+    const size_t xs = a.xt == X_I8 ? 1 : 8;
+    // 16-byte chunks of a column: the array, its stride and every block's
+    // first row (W is a multiple of 256) are 16-byte aligned
+    if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16) ||
+        (reinterpret_cast<uintptr_t>(a.Zprev) % 16) || (reinterpret_cast<uintptr_t>(a.Ut) % 16) ||
+        (a.Gt && reinterpret_cast<uintptr_t>(a.Gt) % 16))
+        return hipErrorInvalidValue;
+    if (a.ldx < a.n) return hipErrorInvalidValue;
+    const int64_t ctiles = (a.cols + BT_N - 1) / BT_N;
+    const int64_t grid = 8 * (a.W / BT_M) * ((ctiles + 7) / 8);
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    if (a.xt == X_I8)
+        hipLaunchKernelGGL(band_step_kernel<int8_t>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(band_step_kernel<double>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t band_block(const double* AB, int64_t ldab, int64_t w, int64_t n, int64_t row0, int64_t col0, int64_t rows,
+                      int64_t cols, double* out, int64_t ldo, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (!AB || !out || ldab < w + 1 || ldo < rows || w < 0) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(cols, 8192);
+    hipLaunchKernelGGL(band_block_kernel, dim3(grid), dim3(256), 0, s, AB, ldab, w, n, row0, col0, rows, cols, out,
+                       ldo);
+    return hipGetLastError();
+}
+
+}  // namespace gwas

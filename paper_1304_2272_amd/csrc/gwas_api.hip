@@ -13,6 +13,7 @@
 #include <climits>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace gwas;
@@ -32,6 +33,11 @@ constexpr int REFINE_STEPS = 2;
 
 struct Layout {
     int64_t n, n_pad, ld, dev_block, npb_max, Q;
+    // banded M: half-bandwidth (0 = dense), block order W and block rows nb;
+    // the factor is kept as U_ii = L_ii^-T and Gt_i = -E_i^T U_ii per block row
+    int64_t band, W, nb, band_ld;
+    size_t off_bandcopy;
+    size_t off_Ub, off_Gt, off_Ab, off_Eb, off_Z[2];
     int p, t, q1, Qc, precision, x_dtype, slices;
     size_t off_L, off_U, off_Ulow, off_rscale, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
@@ -69,11 +75,12 @@ void noalloc_offsets(const Layout& L, int64_t cols, size_t off[5]) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
-                 int32_t x_dtype) {
+                 int32_t x_dtype, int64_t band = 0) {
+    if (band < 0 || (band > 0 && precision != GWAS_FP64)) return false;
     if (p < 2 || p > 20 || n < p || t < 1 || t > MAX_T) return false;
     if (n > (int64_t)1 << 24) return false;
     if (dev_block < 0 || dev_block > ((int64_t)1 << 22)) return false;
-    if (precision < GWAS_FP64 || precision > GWAS_INT8_SLICED) return false;
+    if (precision < GWAS_FP64 || precision > GWAS_BF16X3_REFINE) return false;
     if (x_dtype != GWAS_X_F64 && x_dtype != GWAS_X_I8) return false;
     if (precision == GWAS_INT8_SLICED && x_dtype != GWAS_X_I8) return false;
     return true;
@@ -81,13 +88,21 @@ bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t pre
 
 int atype_of(int precision) {
     return precision == GWAS_FP64 ? A_F64 : precision == GWAS_FP32_REFINE ? A_F32
-         : precision == GWAS_BF16_REFINE ? A_BF16 : A_I8S;
+         : (precision == GWAS_BF16_REFINE || precision == GWAS_BF16X3_REFINE) ? A_BF16 : A_I8S;
 }
 
+// Block order of a banded M of half-bandwidth w: a multiple of 256 rows at
+// least w, so that M is block tridiagonal.
+int64_t band_block_order(int64_t w) { return (w + 255) / 256 * 256; }
+
 Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, int x_dtype,
-                   int slices) {
+                   int slices, int64_t band = 0, int64_t band_ld = 0) {
     Layout L{};
-    L.slices = slices;
+    L.band = band;
+    L.band_ld = band > 0 ? std::max(band_ld, band + 1) : 0;
+    L.W = band > 0 ? band_block_order(band) : 0;
+    // int8 digits of L^-1, or its three bfloat16 slices
+    L.slices = precision == GWAS_INT8_SLICED ? slices : precision == GWAS_BF16X3_REFINE ? 3 : 0;
     L.n = n;
     L.p = p;
     L.t = t;
@@ -96,18 +111,30 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.precision = precision;
     L.x_dtype = x_dtype;
     L.n_pad = (n + NPAD_ALIGN - 1) / NPAD_ALIGN * NPAD_ALIGN;
+    if (band > 0) L.n_pad = (n + L.W - 1) / L.W * L.W;
+    L.nb = band > 0 ? L.n_pad / L.W : 0;
     L.ld = L.n_pad;
     L.dev_block = dev_block > 0 ? (dev_block + TILE_N - 1) / TILE_N * TILE_N : DEFAULT_DEV_BLOCK;
-    L.npb_max = L.n_pad / (precision == GWAS_INT8_SLICED ? trmm_sliced_shape().part_rows : MIN_PART_ROWS);
+    L.npb_max = L.n_pad / (precision == GWAS_INT8_SLICED ? trmm_sliced_shape(0).part_rows : MIN_PART_ROWS);
     L.Q = (precision == GWAS_FP64) ? L.Qc + 1 : 1;
     const size_t nn = (size_t)L.ld * (size_t)L.n_pad;
     const size_t A = 256;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, A); return r; };
-    L.off_L = take(nn * 8);
-    L.off_U = take(nn * 8);
+    if (band > 0) {
+        // per block row U_ii and Gt_i (W x W each); L_ii and E_i of the
+        // block row being factored
+        L.off_Ub = take((size_t)L.n_pad * L.W * 8);
+        L.off_Gt = take((size_t)L.n_pad * L.W * 8);
+        L.off_Ab = take((size_t)L.W * L.W * 8);
+        L.off_Eb = take((size_t)L.W * L.W * 8);
+    } else {
+        L.off_L = take(nn * 8);
+        L.off_U = take(nn * 8);
+    }
     L.off_Ulow = (precision == GWAS_FP32_REFINE) ? take(nn * 4)
                : (precision == GWAS_BF16_REFINE) ? take(nn * 2)
+               : (precision == GWAS_BF16X3_REFINE) ? take(nn * 2 * 3)
                : (precision == GWAS_INT8_SLICED) ? take(nn * (size_t)slices) : 0;
     L.off_rscale = (precision == GWAS_INT8_SLICED) ? take((size_t)L.n_pad * 8) : 0;
     L.off_XY = take((size_t)L.n_pad * L.Qc * 8);
@@ -120,11 +147,11 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     const int at = atype_of(precision);
     const int xt = x_dtype == GWAS_X_I8 ? X_I8 : X_F64;
     // the reverse pass runs the float64 product with its default shape
-    L.sched_len = (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
+    L.sched_len = band > 0 ? 1 : (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
                                             trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0));
     // every admissible shape with the model's and every candidate row group
-    for (int c = 0; c < trmm_num_cfgs(); ++c) {
-        if (at == A_I8S ? c > 0 : !trmm_cfg_valid(at, xt, c)) continue;
+    for (int c = 0; c < trmm_num_cfgs() && band == 0; ++c) {
+        if (!trmm_cfg_valid(at, xt, c)) continue;
         for (int r : {0, 1, 2, 4, 8}) {
             const TrmmShape sh = trmm_geom(at, xt, c, slices, r);
             L.sched_len = std::max(L.sched_len, (size_t)trmm_schedule_len(L.n_pad, L.dev_block, sh));
@@ -142,11 +169,11 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
             noalloc_offsets(L, mid * TILE_N, off);
             if (off[4] <= NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
         }
-        L.na_cols = lo * TILE_N;
+        L.na_cols = band > 0 ? 0 : lo * TILE_N;   // the banded path has no schedule-driven product
         L.na_sched_len = 0;
         if (L.na_cols > 0)
             for (int c = 0; c < trmm_num_cfgs(); ++c) {
-                if (at == A_I8S ? c > 0 : !trmm_cfg_valid(at, xt, c)) continue;
+                if (!trmm_cfg_valid(at, xt, c)) continue;
                 for (int r : {0, 1, 2, 4, 8})
                     L.na_sched_len = std::max(L.na_sched_len, (size_t)trmm_schedule_len(
                                                                   L.n_pad, L.na_cols, trmm_geom(at, xt, c, slices, r)));
@@ -169,10 +196,18 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
         L.off_v[s] = rtake((size_t)L.dev_block * 8);
         L.off_i[s] = rtake((size_t)L.dev_block * 4);
     }
-    const int64_t n1 = (L.n_pad / 2 + LEAF - 1) / LEAF * LEAF;
-    const size_t tmp = (size_t)n1 * (size_t)(L.n_pad - n1) * 8;
+    // banded: Z of the previous and the current block row
+    for (int s = 0; s < 2 && band > 0; ++s) L.off_Z[s] = rtake((size_t)L.W * L.dev_block * 8);
+    // the factorisation's temporary (the order it recurses on: n_pad, or W)
+    const int64_t nf = band > 0 ? L.W : L.n_pad;
+    const int64_t n1 = (nf / 2 + LEAF - 1) / LEAF * LEAF;
+    const size_t tmp = (size_t)n1 * (size_t)(nf - n1) * 8;
     L.off_tmp = L.off_region;
-    L.total = L.off_region + std::max(r, align_up(tmp, A));
+    // banded M handed over in host memory: a device copy of its band storage
+    // (ldm x n doubles) beside the temporary, for the set-up only
+    L.off_bandcopy = L.off_region + align_up(tmp, A);
+    const size_t init_bytes = align_up(tmp, A) + (band > 0 ? align_up((size_t)L.band_ld * n * 8, A) : 0);
+    L.total = L.off_region + std::max(r, init_bytes);
     return L;
 }
 
@@ -195,6 +230,11 @@ struct gwas_ctx {
     uint64_t seq = 0;
     bool slot_used[2] = {false, false};
     bool out_used[2] = {false, false};
+    // pinned host buffers that pageable dosage blocks are packed into before
+    // their copy to the device (allocated at the first pageable block)
+    char* pin[2] = {nullptr, nullptr};
+    bool pin_used[2] = {false, false};
+    bool pin_failed = false;
     int64_t pending = 0;          // blocks queued by gwas_stream_block_async, not yet waited for
     int device = 0;
     Layout lay{};
@@ -204,6 +244,7 @@ struct gwas_ctx {
            *consts = nullptr;
     void* Ulow = nullptr;
     double* rscale = nullptr;
+    double *Ub = nullptr, *Gt = nullptr, *Ab = nullptr, *Eb = nullptr, *Zb[2] = {nullptr, nullptr};   // banded M
     TrmmShape shape{};
     int* flags = nullptr;
     int* sched = nullptr;
@@ -212,8 +253,11 @@ struct gwas_ctx {
     int* sched_na = nullptr;        // schedule of gwas_stream_block_noalloc's sub-blocks
     char* nscratch = nullptr;       // device address of this device's static scratch
     hipEvent_t ev_na = nullptr;     // orders gwas_stream_block_noalloc after queued work
+    hipEvent_t ev_fork = nullptr;   // grouped calls: the product is done, per-SNP work may start
+    hipEvent_t ev_join = nullptr;   // grouped calls: this context's per-SNP work is done
     int at = A_F64;
     int cfg = 0;
+    int64_t sub = 0;                // sub-block width of gwas_stream_block (dev_block, or the autotuner's)
     int rgroup = 0;                 // schedule row group (0: the traffic model's choice)
     char* xbuf[2] = {nullptr, nullptr};
     double* part = nullptr;
@@ -302,6 +346,12 @@ struct Group {
     TrmmArgs* h_args_graph = nullptr;
     TrmmArgs* d_args_graph = nullptr;
     int* d_sched_graph = nullptr;
+    // float64 groups read device dosages in place in graph mode: the dosage
+    // pointers the graph's argument array holds, and pinned copies of the
+    // array (alternating) that new pointers are uploaded from
+    std::vector<const void*> graph_x;
+    std::vector<int64_t> graph_ldx;
+    TrmmArgs* h_args_upd[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -408,6 +458,61 @@ hipError_t join_user(gwas_ctx* c, hipStream_t s) {
     return e;
 }
 
+bool pinned_host(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+// The pinned buffers pageable blocks are staged through; false (and the
+// runtime's own staging is used) when they cannot be had.
+bool ensure_pinned_ring(gwas_ctx* c) {
+    if (c->pin[0]) return true;
+    if (c->pin_failed) return false;
+    const size_t bytes = (size_t)c->lay.n * (size_t)c->lay.dev_block * (c->lay.x_dtype == GWAS_X_I8 ? 1 : 8);
+    for (int s = 0; s < 2; ++s) {
+        void* ptr = nullptr;
+        if (hipHostMalloc(&ptr, bytes, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int q = 0; q < 2; ++q)
+                if (c->pin[q]) (void)hipHostFree(c->pin[q]);
+            c->pin[0] = c->pin[1] = nullptr;
+            c->pin_failed = true;
+            return false;
+        }
+        c->pin[s] = static_cast<char*>(ptr);
+    }
+    return true;
+}
+
+// cols columns of `bytes` bytes at a stride of `ld` bytes, packed into dst;
+// large copies are split over host threads.
+void pack_columns(char* dst, const char* src, size_t ld, size_t bytes, int64_t cols) {
+    auto work = [=](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) memcpy(dst + (size_t)c * bytes, src + (size_t)c * ld, bytes);
+    };
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = (bytes * (size_t)cols >= (size_t(64) << 20)) ? (int)std::min<unsigned>(8, std::max(1u, hw)) : 1;
+    if (T <= 1 || cols < T) {
+        work(0, cols);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t done = 0;   // columns handed to threads that started
+    try {
+        for (int i = 0; i < T; ++i) {
+            th.emplace_back(work, cols * i / T, cols * (i + 1) / T);
+            done = cols * (i + 1) / T;
+        }
+    } catch (...) {
+    }
+    for (auto& t : th) t.join();
+    if (done < cols) work(done, cols);
+}
+
 bool on_device(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t a;
@@ -423,22 +528,23 @@ bool on_device(const void* p) {
 //   [A11 .; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T,
 //   L21 = A21 L11^-T, A22 <- A22 - L21 L21^T, and
 //   U = L^-T with U12 = -U11 L21^T U22.
-int chol_inv(gwas_ctx* c, int64_t o, int64_t sz) {
-    const int64_t ld = c->lay.ld;
+// Lm and Um are the factor and its inverse transpose (leading dimension ld);
+// element 0 is row `row0` of M, for the failing-pivot report.
+int chol_inv(gwas_ctx* c, double* Lm, double* Um, int64_t ld, int64_t row0, int64_t o, int64_t sz) {
     hipStream_t s = c->s_comp;
     if (sz == LEAF) {
-        HIPCHK(c, chol_leaf(c->L + o + o * ld, c->U + o + o * ld, ld, o, c->lay.n, c->flags, s));
+        HIPCHK(c, chol_leaf(Lm + o + o * ld, Um + o + o * ld, ld, row0 + o, c->lay.n, c->flags, s));
         return GWAS_OK;
     }
     const int64_t n1 = (sz / 2 + LEAF - 1) / LEAF * LEAF;
     const int64_t n2 = sz - n1;
-    int rc = chol_inv(c, o, n1);
+    int rc = chol_inv(c, Lm, Um, ld, row0, o, n1);
     if (rc) return rc;
-    double* L21 = c->L + (o + n1) + o * ld;
-    double* L22 = c->L + (o + n1) + (o + n1) * ld;
-    double* U11 = c->U + o + o * ld;
-    double* U12 = c->U + o + (o + n1) * ld;
-    double* U22 = c->U + (o + n1) + (o + n1) * ld;
+    double* L21 = Lm + (o + n1) + o * ld;
+    double* L22 = Lm + (o + n1) + (o + n1) * ld;
+    double* U11 = Um + o + o * ld;
+    double* U12 = Um + o + (o + n1) * ld;
+    double* U22 = Um + (o + n1) + (o + n1) * ld;
     // T = A21 U11 (= L21), copied into place
     GemmArgs g{};
     g = GemmArgs{n2, n1, n1, L21, ld, 'N', U11, ld, 'N', c->tmp, n2, 1.0, 0.0, KR_B_UPPER, 0};
@@ -447,7 +553,7 @@ int chol_inv(gwas_ctx* c, int64_t o, int64_t sz) {
     // A22 -= L21 L21^T (lower tiles)
     g = GemmArgs{n2, n2, n1, c->tmp, n2, 'N', c->tmp, n2, 'T', L22, ld, -1.0, 1.0, 0, 1};
     HIPCHK(c, gemm_f64(g, s));
-    rc = chol_inv(c, o + n1, n2);
+    rc = chol_inv(c, Lm, Um, ld, row0, o + n1, n2);
     if (rc) return rc;
     // T = U11 L21^T (n1 x n2), U12 = -T U22
     g = GemmArgs{n1, n2, n1, U11, ld, 'N', L21, ld, 'T', c->tmp, n1, 1.0, 0.0, KR_A_UPPER, 0};
@@ -507,6 +613,8 @@ void release(gwas_ctx* c) {
         }
         if (g->d_sched) (void)hipFree(g->d_sched);
         if (g->h_args_graph) (void)hipHostFree(g->h_args_graph);
+        for (int s = 0; s < 2; ++s)
+            if (g->h_args_upd[s]) (void)hipHostFree(g->h_args_upd[s]);
         if (g->d_args_graph) (void)hipFree(g->d_args_graph);
         if (g->d_sched_graph) (void)hipFree(g->d_sched_graph);
         delete g;
@@ -517,7 +625,11 @@ void release(gwas_ctx* c) {
     if (c->own_comp && c->s_comp) (void)hipStreamDestroy(c->s_comp);
     if (c->ev_user) (void)hipEventDestroy(c->ev_user);
     if (c->ev_na) (void)hipEventDestroy(c->ev_na);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    for (int s = 0; s < 2; ++s)
+        if (c->pin[s]) (void)hipHostFree(c->pin[s]);
     (void)hipGetLastError();
 }
 
@@ -560,7 +672,7 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.slices = Y.slices;
     ta.rscale = c->rscale;
     ta.Ut = (c->at == A_F64) ? (const void*)c->U : c->Ulow;
-    ta.ldu = Y.ld;
+    ta.ldu = (Y.precision == GWAS_BF16X3_REFINE) ? 3 * Y.n_pad : Y.ld;   // slices one after another
     ta.n_pad = Y.n_pad;
     ta.X = xptr;
     ta.ldx = xld;
@@ -611,7 +723,8 @@ SolveArgs solve_args_for(const gwas_ctx* c, const SubScratch& sc, int64_t cols, 
     sa.refine = (Y.precision == GWAS_FP64) ? 0 : REFINE_STEPS;
     sa.rank_tol = (Y.precision == GWAS_FP64) ? RANK_TOL_F64
                 : (Y.precision == GWAS_FP32_REFINE) ? RANK_TOL_F32
-                : (Y.precision == GWAS_BF16_REFINE) ? RANK_TOL_BF16 : RANK_TOL_I8S;
+                : (Y.precision == GWAS_BF16_REFINE) ? RANK_TOL_BF16
+                : (Y.precision == GWAS_BF16X3_REFINE) ? RANK_TOL_F32 : RANK_TOL_I8S;
     sa.b = bo;
     sa.ldb = ldbo;
     sa.var = vo;
@@ -645,6 +758,60 @@ int64_t group_schedule(const std::vector<gwas_ctx*>& cs, int64_t cols, std::vect
     return trmm_schedule_multi(nrb.data(), (int)cs.size(), cols, cs[0]->shape, &out);
 }
 
+// Set-up for a banded M (half-bandwidth w, blocks of W rows): block row by
+// block row, A_ii = M_ii - E_i E_i^T = L_ii L_ii^T (with U_ii = L_ii^-T),
+// Gt_i = -E_i^T U_ii and E_{i+1} = M_{i+1,i} U_ii; then the whitened
+// C = L^-1 [X_L | Y] by the same block forward substitution the streamed
+// blocks take, C_i = U_ii^T XY_i + Gt_i^T C_{i-1}.
+int init_banded(gwas_ctx* c, const gwas_desc* d) {
+    const Layout& Y = c->lay;
+    const int64_t n = Y.n, n_pad = Y.n_pad, W = Y.W, w = Y.band;
+    hipStream_t s = c->s_comp;
+    const double* AB = d->M;
+    if (!d->inputs_on_device) {
+        double* cp = reinterpret_cast<double*>(c->ws + Y.off_bandcopy);
+        HIPCHK(c, hipMemcpyAsync(cp, d->M, (size_t)d->ldm * n * 8, hipMemcpyHostToDevice, s));
+        AB = cp;
+    }
+    HIPCHK(c, hipMemsetAsync(c->Ub, 0, (size_t)n_pad * W * 8, s));
+    for (int64_t i = 0; i < Y.nb; ++i) {
+        double* Ui = c->Ub + i * W * W;
+        double* Gi = c->Gt + i * W * W;
+        HIPCHK(c, band_block(AB, d->ldm, w, n, i * W, i * W, W, W, c->Ab, W, s));
+        GemmArgs g{};
+        if (i > 0) {
+            g = GemmArgs{W, W, W, c->Eb, W, 'N', c->Eb, W, 'T', c->Ab, W, -1.0, 1.0, 0, 1};
+            HIPCHK(c, gemm_f64(g, s));
+        }
+        int rc = chol_inv(c, c->Ab, Ui, W, i * W, 0, W);
+        if (rc) return rc;
+        if (i > 0) {
+            g = GemmArgs{W, W, W, c->Eb, W, 'T', Ui, W, 'N', Gi, W, -1.0, 0.0, KR_B_UPPER, 0};
+            HIPCHK(c, gemm_f64(g, s));
+        }
+        if (i + 1 < Y.nb) {
+            HIPCHK(c, band_block(AB, d->ldm, w, n, (i + 1) * W, i * W, W, W, c->Ab, W, s));
+            g = GemmArgs{W, W, W, c->Ab, W, 'N', Ui, W, 'N', c->Eb, W, 1.0, 0.0, KR_B_UPPER, 0};
+            HIPCHK(c, gemm_f64(g, s));
+        }
+    }
+    const hipMemcpyKind kin = d->inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(c, hipMemsetAsync(c->XY, 0, (size_t)n_pad * Y.Qc * 8, s));
+    HIPCHK(c, hipMemcpy2DAsync(c->XY, n_pad * 8, d->XL, d->ldxl * 8, n * 8, Y.q1, kin, s));
+    HIPCHK(c, hipMemcpy2DAsync(c->XY + (size_t)n_pad * Y.q1, n_pad * 8, d->Y, d->ldy * 8, n * 8, Y.t, kin, s));
+    for (int64_t i = 0; i < Y.nb; ++i) {
+        GemmArgs g{W, Y.Qc, W, c->Ub + i * W * W, W, 'T', c->XY + i * W, n_pad, 'N', c->C + i * W, n_pad,
+                   1.0, 0.0, KR_A_LOWER, 0};
+        HIPCHK(c, gemm_f64(g, s));
+        if (i > 0) {
+            g = GemmArgs{W, Y.Qc, W, c->Gt + i * W * W, W, 'T', c->C + (i - 1) * W, n_pad, 'N', c->C + i * W,
+                         n_pad, 1.0, 1.0, 0, 0};
+            HIPCHK(c, gemm_f64(g, s));
+        }
+    }
+    return GWAS_OK;
+}
+
 int init_body(gwas_ctx* c, const gwas_desc* d) {
     const Layout& Y = c->lay;
     const int64_t ld = Y.ld, n = Y.n, n_pad = Y.n_pad;
@@ -654,20 +821,26 @@ int init_body(gwas_ctx* c, const gwas_desc* d) {
     HIPCHK(c, join_user(c, s));
     HIPCHK(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->flags), INT_MAX, 1, s));
     HIPCHK(c, hipMemsetAsync(c->flags + 1, 0, 4, s));
-    // M -> L (the lower triangle is what the factorisation reads), identity padding
-    HIPCHK(c, hipMemcpy2DAsync(c->L, ld * 8, d->M, d->ldm * 8, n * 8, n, kin, s));
-    HIPCHK(c, pad_identity(c->L, ld, n, n_pad, s));
-    HIPCHK(c, hipMemsetAsync(c->U, 0, (size_t)ld * n_pad * 8, s));
-    int rc = chol_inv(c, 0, n_pad);
-    if (rc) return rc;
-    // [X_L | Y] with zero padding rows, then C = L^-1 [X_L | Y]
-    HIPCHK(c, hipMemsetAsync(c->XY, 0, (size_t)n_pad * Y.Qc * 8, s));
-    HIPCHK(c, hipMemcpy2DAsync(c->XY, n_pad * 8, d->XL, d->ldxl * 8, n * 8, Y.q1, kin, s));
-    HIPCHK(c, hipMemcpy2DAsync(c->XY + (size_t)n_pad * Y.q1, n_pad * 8, d->Y, d->ldy * 8, n * 8,
-                               Y.t, kin, s));
-    GemmArgs g{n_pad, Y.Qc, n_pad, c->U, ld, 'T', c->XY, n_pad, 'N', c->C, n_pad, 1.0, 0.0,
-               KR_A_LOWER, 0};
-    HIPCHK(c, gemm_f64(g, s));
+    GemmArgs g{};
+    if (Y.band > 0) {
+        int rc = init_banded(c, d);
+        if (rc) return rc;
+    } else {
+        // M -> L (the lower triangle is what the factorisation reads), identity padding
+        HIPCHK(c, hipMemcpy2DAsync(c->L, ld * 8, d->M, d->ldm * 8, n * 8, n, kin, s));
+        HIPCHK(c, pad_identity(c->L, ld, n, n_pad, s));
+        HIPCHK(c, hipMemsetAsync(c->U, 0, (size_t)ld * n_pad * 8, s));
+        int rc = chol_inv(c, c->L, c->U, ld, 0, 0, n_pad);
+        if (rc) return rc;
+        // [X_L | Y] with zero padding rows, then C = L^-1 [X_L | Y]
+        HIPCHK(c, hipMemsetAsync(c->XY, 0, (size_t)n_pad * Y.Qc * 8, s));
+        HIPCHK(c, hipMemcpy2DAsync(c->XY, n_pad * 8, d->XL, d->ldxl * 8, n * 8, Y.q1, kin, s));
+        HIPCHK(c, hipMemcpy2DAsync(c->XY + (size_t)n_pad * Y.q1, n_pad * 8, d->Y, d->ldy * 8, n * 8,
+                                   Y.t, kin, s));
+        g = GemmArgs{n_pad, Y.Qc, n_pad, c->U, ld, 'T', c->XY, n_pad, 'N', c->C, n_pad, 1.0, 0.0,
+                     KR_A_LOWER, 0};
+        HIPCHK(c, gemm_f64(g, s));
+    }
     // [S_TL | bbar_T] = Xbar_L^T [Xbar_L | Ybar]
     g = GemmArgs{Y.q1, Y.Qc, n_pad, c->C, n_pad, 'T', c->C, n_pad, 'N', c->S, Y.q1, 1.0, 0.0, 0, 0};
     HIPCHK(c, gemm_f64(g, s));
@@ -679,15 +852,20 @@ int init_body(gwas_ctx* c, const gwas_desc* d) {
         HIPCHK(c, gemm_f64(g, s));
         if (Y.precision == GWAS_FP32_REFINE)
             HIPCHK(c, convert_f32(c->U, (float*)c->Ulow, ld, n_pad, n_pad, s));
+        else if (Y.precision == GWAS_BF16X3_REFINE)
+            HIPCHK(c, slice_bf16(c->U, ld, n_pad, (__bf16*)c->Ulow, 3 * n_pad, s));
         else if (Y.precision == GWAS_BF16_REFINE)
             HIPCHK(c, convert_bf16(c->U, (__bf16*)c->Ulow, ld, n_pad, n_pad, s));
         else
             HIPCHK(c, slice_rows(c->U, ld, n_pad, Y.slices, (int8_t*)c->Ulow, n_pad, c->rscale, s));
     }
-    rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
-    if (rc) return rc;
-    rc = upload_noalloc_schedule(c);
-    if (rc) return rc;
+    if (Y.band == 0) {
+        c->sub = Y.dev_block;
+        int rc = upload_schedule(c, c->sub, c->sched, c->host_sched);
+        if (rc) return rc;
+        rc = upload_noalloc_schedule(c);
+        if (rc) return rc;
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     int flags[2] = {0, 0};
     HIPCHK(c, hipMemcpy(flags, c->flags, sizeof(flags), hipMemcpyDeviceToHost));
@@ -714,12 +892,18 @@ size_t gwas_workspace_bytes(int64_t n, int32_t p, int32_t t, int64_t dev_block, 
     return make_layout(n, p, t, dev_block, precision, x_dtype, DEFAULT_SLICES).total;
 }
 
+size_t gwas_workspace_bytes_band(int64_t n, int32_t p, int32_t t, int64_t dev_block, int64_t band, int64_t ldm,
+                                 int32_t x_dtype) {
+    if (band < 1 || ldm < band + 1 || !sizes_valid(n, p, t, dev_block, GWAS_FP64, x_dtype, band)) return 0;
+    return make_layout(n, p, t, dev_block, GWAS_FP64, x_dtype, 0, band, ldm).total;
+}
+
 int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     if (!out) return GWAS_E_INVALID;
     *out = nullptr;
     if (!d || !d->M || !d->XL || !d->Y) return GWAS_E_INVALID;
-    if (!sizes_valid(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype)) return GWAS_E_INVALID;
-    if (d->ldm < d->n || d->ldxl < d->n || d->ldy < d->n) return GWAS_E_INVALID;
+    if (!sizes_valid(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype, d->band)) return GWAS_E_INVALID;
+    if (d->ldm < (d->band > 0 ? d->band + 1 : d->n) || d->ldxl < d->n || d->ldy < d->n) return GWAS_E_INVALID;
     if (d->workspace && (reinterpret_cast<uintptr_t>(d->workspace) % 256)) return GWAS_E_INVALID;
     const int slices = (d->precision == GWAS_INT8_SLICED) ? (d->slices ? d->slices : DEFAULT_SLICES) : 0;
     if (d->precision == GWAS_INT8_SLICED && (slices < 4 || slices > 6)) return GWAS_E_INVALID;
@@ -733,7 +917,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         delete c;
         return rc;
     }
-    c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype, slices);
+    c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype, slices, d->band, d->ldm);
     const Layout& Y = c->lay;
     c->at = atype_of(d->precision);
     c->cfg = trmm_default_cfg(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64);
@@ -743,6 +927,8 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
         if (trmm_cfg_valid(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, v)) c->cfg = v;
     }
     c->shape = trmm_geom(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c->cfg, slices);
+    // the banded product has its own fixed tile (128 x 128, 32-row slices)
+    if (d->band > 0) c->shape = TrmmShape{128, 128, band_part_rows(), 512, 1, 32};
     auto bail = [&](int code) {
         release(c);
         c->magic = CTX_DEAD;
@@ -788,6 +974,14 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
     c->xwpart = Y.off_xwpart ? (double*)(w + Y.off_xwpart) : nullptr;
     c->tmp = (double*)(w + Y.off_tmp);
+    if (Y.band > 0) {
+        c->Ub = (double*)(w + Y.off_Ub);
+        c->Gt = (double*)(w + Y.off_Gt);
+        c->Ab = (double*)(w + Y.off_Ab);
+        c->Eb = (double*)(w + Y.off_Eb);
+        for (int s = 0; s < 2; ++s) c->Zb[s] = (double*)(w + Y.off_Z[s]);
+        c->L = c->U = nullptr;
+    }
 
     // The library computes on streams of its own (default priority); work the
     // caller queued on its stream before a call is joined through an event.
@@ -796,6 +990,8 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->own_comp = true;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_na, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_h2d, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_d2h, hipStreamNonBlocking);
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {
@@ -830,6 +1026,36 @@ int settle(gwas_ctx* c) {
     return collect_timing(c);
 }
 
+// The banded forward substitution of one sub-block: one launch per block
+// row, Z alternating between the two buffers; partial sums as the dense
+// product's.
+hipError_t band_product(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, hipStream_t s) {
+    const Layout& Y = c->lay;
+    for (int64_t i = 0; i < Y.nb; ++i) {
+        BandArgs ba{};
+        ba.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+        ba.W = Y.W;
+        ba.blk = i;
+        ba.Ut = c->Ub + i * Y.W * Y.W;
+        ba.Gt = i > 0 ? c->Gt + i * Y.W * Y.W : nullptr;
+        ba.X = xptr;
+        ba.ldx = xld;
+        ba.n = Y.n;
+        ba.cols = cols;
+        ba.Zprev = i > 0 ? c->Zb[(i - 1) & 1] : nullptr;
+        ba.Zcur = c->Zb[i & 1];
+        ba.ldz = Y.W;
+        ba.C = c->C;
+        ba.ldc = Y.n_pad;
+        ba.Qc = Y.Qc;
+        ba.part = c->part;
+        ba.ldp = Y.dev_block;
+        const hipError_t e = band_step(ba, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // One pass of Algorithm 2's loop for a block, queued on the context's
 // streams without waiting: per sub-block the copy in (when the dosages are
 // not read in place), the product, the per-SNP kernels and the copy out (when
@@ -847,14 +1073,18 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
     const bool x_dev = on_device(XR);
     const bool direct_x = x_dev && (reinterpret_cast<uintptr_t>(XR) % 16 == 0) &&
                           ((ldx * (int64_t)elem) % 16 == 0) && ldx * (int64_t)elem <= X_DIRECT_MAX_LD_BYTES;
+    // pageable host dosages: packed into pinned buffers by the host while the
+    // device works on the sub-block before, then copied asynchronously
+    const bool stage_host = !x_dev && !pinned_host(XR) && ensure_pinned_ring(c);
     const bool direct_out = on_device(b) && (!var_snp || on_device(var_snp)) &&
                             (!info || on_device(info));
     const int pt = Y.p * Y.t;
-    const int64_t nsub = (mblk + Y.dev_block - 1) / Y.dev_block;
+    const int64_t sub = c->sub > 0 ? c->sub : Y.dev_block;
+    const int64_t nsub = (mblk + sub - 1) / sub;
 
     for (int64_t k = 0; k < nsub; ++k) {
-        const int64_t col0 = k * Y.dev_block;
-        const int64_t cols = std::min<int64_t>(Y.dev_block, mblk - col0);
+        const int64_t col0 = k * sub;
+        const int64_t cols = std::min<int64_t>(sub, mblk - col0);
         const int slot = (int)(c->seq++ & 1);
         const void* xptr;
         int64_t xld;
@@ -864,8 +1094,18 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
         } else {
             // the slot's previous sub-block has finished reading it
             if (c->slot_used[slot]) HIPCHK(c, hipStreamWaitEvent(c->s_h2d, c->ev_done[slot], 0));
-            HIPCHK(c, hipMemcpy2DAsync(c->xbuf[slot], Y.n_pad * elem, xr + (size_t)col0 * ldx * elem,
-                                       ldx * elem, Y.n * elem, cols, hipMemcpyDefault, c->s_h2d));
+            const char* src = xr + (size_t)col0 * ldx * elem;
+            int64_t sld = ldx * (int64_t)elem;
+            if (stage_host) {
+                // the pinned slot's last copy to the device has finished
+                if (c->pin_used[slot]) HIPCHK(c, hipEventSynchronize(c->ev_loaded[slot]));
+                pack_columns(c->pin[slot], src, (size_t)sld, (size_t)Y.n * elem, cols);
+                src = c->pin[slot];
+                sld = Y.n * (int64_t)elem;
+                c->pin_used[slot] = true;
+            }
+            HIPCHK(c, hipMemcpy2DAsync(c->xbuf[slot], Y.n_pad * elem, src, sld, Y.n * elem, cols,
+                                       hipMemcpyDefault, c->s_h2d));
             HIPCHK(c, hipEventRecord(c->ev_loaded[slot], c->s_h2d));
             HIPCHK(c, hipStreamWaitEvent(c->s_comp, c->ev_loaded[slot], 0));
             xptr = c->xbuf[slot];
@@ -889,7 +1129,7 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
             ldbo = pt;
         }
         const int* sched = c->sched;
-        if (cols != Y.dev_block) {
+        if (cols != sub && Y.band == 0) {
             if (cols != c->tail_cols) {
                 // the host copy of the tail schedule is rewritten: queued
                 // blocks may still be reading it
@@ -900,12 +1140,16 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
             }
             sched = c->sched_tail;
         }
-        TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
-        ta.sched = sched;
         if (timed) {
             if (int rc = timer_start(c, c->s_comp)) return rc;
         }
-        HIPCHK(c, trmm_stream(ta, c->s_comp));
+        if (Y.band > 0) {
+            HIPCHK(c, band_product(c, xptr, xld, cols, c->s_comp));
+        } else {
+            TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
+            ta.sched = sched;
+            HIPCHK(c, trmm_stream(ta, c->s_comp));
+        }
         if (timed) {
             if (int rc = timer_stop(c, c->s_comp, cols)) return rc;
         }
@@ -973,6 +1217,7 @@ int gwas_stream_wait(gwas_ctx* c) {
 int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double* b,
                               int64_t ldb, double* var_snp, int32_t* info) {
     if (!live(c)) return GWAS_E_STATE;
+    if (c->lay.band > 0) return GWAS_E_INVALID;   // the banded product keeps Z in the context
     if (int rc = check_block_args(c, XR, ldx, mblk, b, ldb)) return rc;
     if (mblk == 0) return GWAS_OK;
     const Layout& Y = c->lay;
@@ -1037,7 +1282,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         const gwas_ctx* c = ctxs[i];
         if (c->device != c0->device || c->at != c0->at || c->cfg != c0->cfg ||
             c->lay.x_dtype != c0->lay.x_dtype || c->lay.dev_block != c0->lay.dev_block ||
-            c->lay.slices != c0->lay.slices)
+            c->lay.slices != c0->lay.slices || c->lay.band > 0)
             return GWAS_E_INVALID;
         if (!XR[i] || !b[i] || ldx[i] < c->lay.n || ldb[i] < (int64_t)c->lay.p * c->lay.t)
             return GWAS_E_INVALID;
@@ -1123,8 +1368,20 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         la.sched = sched;
         la.n_sched = n_sched;
         HIPCHK(c0, trmm_stream(la, s));
-        for (int i = 0; i < nctx; ++i)
-            HIPCHK(c0, finish_sub(cs[i], ctx_scratch(cs[i]), xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], s));
+        // each context's cross products, chunk sums and solves on its own
+        // stream, so the small launches of different contexts overlap; the
+        // group's stream waits for all of them (in a capture these are
+        // parallel branches of the graph)
+        if (nctx > 1) HIPCHK(c0, hipEventRecord(c0->ev_fork, s));
+        for (int i = 0; i < nctx; ++i) {
+            hipStream_t si = (i == 0) ? s : cs[i]->s_comp;
+            if (i > 0) HIPCHK(c0, hipStreamWaitEvent(si, c0->ev_fork, 0));
+            HIPCHK(c0, finish_sub(cs[i], ctx_scratch(cs[i]), xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], si));
+            if (i > 0) {
+                HIPCHK(c0, hipEventRecord(cs[i]->ev_join, si));
+                HIPCHK(c0, hipStreamWaitEvent(s, cs[i]->ev_join, 0));
+            }
+        }
         return GWAS_OK;
     };
 
@@ -1133,6 +1390,10 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         const int64_t cols = std::min<int64_t>(blk, mblk - col0);
         const int slot = (int)(k & 1);
         const bool use_graph = want_graph && cols == blk;
+        // in a float64 graph the product reads the dosages through the
+        // argument array and nothing else reads them: device dosages stay
+        // in place and the array is updated before a replay
+        const bool graph_direct = use_graph && c0->lay.precision == GWAS_FP64;
         int rc = ensure_schedule(cols);
         if (rc) return rc;
         std::vector<const void*> xp(nctx);
@@ -1143,7 +1404,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         for (int i = 0; i < nctx; ++i) {
             gwas_ctx* c = cs[i];
             const char* src = static_cast<const char*>(XR[i]) + (size_t)col0 * ldx[i] * elem;
-            if (direct_x[i] && !use_graph) {
+            if (direct_x[i] && (!use_graph || graph_direct)) {
                 xp[i] = src;
                 xl[i] = ldx[i];
             } else {
@@ -1202,6 +1463,26 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                 HIPCHK(c0, ec);
                 HIPCHK(c0, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
                 g->graph_key = key;
+                g->graph_x = xp;
+                g->graph_ldx = xl;
+            } else if (g->graph_x != xp || g->graph_ldx != xl) {
+                // new dosage pointers: upload the argument array, in stream
+                // order behind the replays that read the old one, from a
+                // pinned copy that no queued upload still reads
+                if (!g->h_args_upd[slot])
+                    HIPCHK(c0, hipHostMalloc((void**)&g->h_args_upd[slot], MAX_GROUP * sizeof(TrmmArgs), 0));
+                if (k >= 2) HIPCHK(c0, hipEventSynchronize(c0->ev_done[slot]));
+                for (int i = 0; i < nctx; ++i) {
+                    TrmmArgs a = g->h_args_graph[i];
+                    a.X = xp[i];
+                    a.ldx = xl[i];
+                    HIPCHK(c0, trmm_check(a, false));
+                    g->h_args_upd[slot][i] = a;
+                }
+                HIPCHK(c0, hipMemcpyAsync(g->d_args_graph, g->h_args_upd[slot], nctx * sizeof(TrmmArgs),
+                                          hipMemcpyHostToDevice, s));
+                g->graph_x = xp;
+                g->graph_ldx = xl;
             }
             HIPCHK(c0, hipGraphLaunch(g->exec, s));
         } else {
@@ -1245,6 +1526,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
 int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
                   int32_t* best_rgroup) {
     if (!live(c)) return GWAS_E_STATE;
+    if (c->lay.band > 0) return GWAS_E_INVALID;   // one tile shape
     const Layout& Y = c->lay;
     if (!XR || ldx < Y.n || cols < 1) return GWAS_E_INVALID;
     cols = std::min<int64_t>(cols, Y.dev_block);
@@ -1259,16 +1541,21 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     snprintf(keyline, sizeof(keyline), "gfx950 n_pad=%lld precision=%d x_dtype=%d cols=%lld",
              (long long)Y.n_pad, Y.precision, Y.x_dtype, (long long)cols);
     int best = -1, best_rg = 0;
+    int64_t best_sub = 0;
     if (cache) {
         if (FILE* f = fopen(cache, "r")) {
             char line[256];
             while (fgets(line, sizeof(line), f)) {
                 const size_t kl = strlen(keyline);
                 int v = -1, r = 0;
-                if (strncmp(line, keyline, kl) == 0 && sscanf(line + kl, " cfg=%d rgroup=%d", &v, &r) == 2 &&
-                    (c->at == A_I8S ? v == -1 : trmm_cfg_valid(c->at, xt, v)) && r >= 1 && r <= 32) {
+                long long w = Y.dev_block;   // lines without a width keep dev_block
+                if (strncmp(line, keyline, kl) == 0 &&
+                    sscanf(line + kl, " cfg=%d rgroup=%d sub=%lld", &v, &r, &w) >= 2 &&
+                    trmm_cfg_valid(c->at, xt, v) && r >= 1 && r <= 32 && w >= TILE_N && w <= Y.dev_block &&
+                    w % TILE_N == 0) {
                     best = v;
                     best_rg = r;
+                    best_sub = w;
                 }
             }
             fclose(f);
@@ -1290,11 +1577,11 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         float best_ms = 0.f;
         // every admissible tile shape (the int8-slice product has one) with
         // every candidate row group of the schedule
-        for (int cfg = (c->at == A_I8S ? -1 : 0); cfg < (c->at == A_I8S ? 0 : trmm_num_cfgs()); ++cfg) {
-            if (c->at != A_I8S && !trmm_cfg_valid(c->at, xt, cfg)) continue;
+        for (int cfg = 0; cfg < trmm_num_cfgs(); ++cfg) {
+            if (!trmm_cfg_valid(c->at, xt, cfg)) continue;
             for (int rg : RGROUP_CANDIDATES) {
                 c->gen += 1;
-                c->cfg = cfg < 0 ? 0 : cfg;
+                c->cfg = cfg;
                 c->rgroup = rg;
                 c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, rg);
                 int rc = upload_schedule(c, cols, c->sched_tail, c->host_tail);
@@ -1315,11 +1602,49 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
                 }
             }
         }
+        // the sub-block width with that shape: dev_block, a half or a
+        // quarter of it (whole multiples of 128 columns that fit the timing
+        // block), by the product's time per column over whole sub-blocks
+        c->gen += 1;
+        c->cfg = best;
+        c->rgroup = best_rg;
+        c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, best_rg);
+        double best_per_col = 0.0;
+        for (int d : {1, 2, 4}) {
+            const int64_t w = Y.dev_block / d / TILE_N * TILE_N;
+            if (w < TILE_N || w > cols) continue;
+            const int64_t reps = cols / w;
+            int rc = upload_schedule(c, w, c->sched_tail, c->host_tail);
+            if (rc) return rc;
+            auto launch_all = [&]() -> int {
+                for (int64_t q = 0; q < reps; ++q) {
+                    TrmmArgs ta = trmm_args_for(c, static_cast<const char*>(xptr) + (size_t)(q * w) * xld * elem,
+                                                xld, w);
+                    ta.sched = c->sched_tail;
+                    HIPCHK(c, trmm_stream(ta, c->s_comp));
+                }
+                return GWAS_OK;
+            };
+            if (int lrc = launch_all()) return lrc;                 // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->s_comp));
+            if (int lrc = launch_all()) return lrc;
+            HIPCHK(c, hipEventRecord(e1, c->s_comp));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            const double per_col = ms / (double)(reps * w);
+            if (best_sub == 0 || per_col < best_per_col) {
+                best_sub = w;
+                best_per_col = per_col;
+            }
+        }
+        if (best_sub == 0) best_sub = Y.dev_block;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (cache) {
             if (FILE* f = fopen(cache, "a")) {
-                fprintf(f, "%s cfg=%d rgroup=%d ms=%.3f\n", keyline, best, best_rg, best_ms);
+                fprintf(f, "%s cfg=%d rgroup=%d sub=%lld ms=%.3f\n", keyline, best, best_rg, (long long)best_sub,
+                        best_ms);
                 fclose(f);
             }
         }
@@ -1329,7 +1654,8 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     c->rgroup = best_rg;
     c->shape = trmm_geom(c->at, xt, c->cfg, Y.slices, best_rg);
     c->tail_cols = -1;
-    int rc = upload_schedule(c, Y.dev_block, c->sched, c->host_sched);
+    c->sub = best_sub > 0 ? best_sub : Y.dev_block;
+    int rc = upload_schedule(c, c->sub, c->sched, c->host_sched);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
     rc = upload_noalloc_schedule(c);
@@ -1341,6 +1667,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
 
 int gwas_backward_begin(gwas_ctx* c) {
     if (!live(c)) return GWAS_E_STATE;
+    if (c->lay.band > 0) return GWAS_E_INVALID;   // needs the dense inverse factor
     const Layout& Y = c->lay;
     if (Y.t != 1) return GWAS_E_INVALID;
     DeviceScope scope;
@@ -1603,7 +1930,7 @@ int gwas_kernel_time(gwas_ctx* c, int64_t* launches, double* total_ms, int64_t* 
 int gwas_query(const gwas_ctx* c, int64_t* n_pad, int64_t* dev_block, int32_t* device) {
     if (!c || c->magic != CTX_MAGIC) return GWAS_E_STATE;
     if (n_pad) *n_pad = c->lay.n_pad;
-    if (dev_block) *dev_block = c->lay.dev_block;
+    if (dev_block) *dev_block = c->sub > 0 ? c->sub : c->lay.dev_block;
     if (device) *device = c->device;
     return GWAS_OK;
 }

@@ -281,6 +281,23 @@ __global__ void convert_kernel(const double* __restrict__ in, T* __restrict__ ou
             out[r + c * ld] = (T)in[r + c * ld];
 }
 
+// Three bfloat16 slices of each row of L^-1: slice i is what slices 0..i-1
+// leave of U(k, r), rounded to bfloat16 (every remainder is exact in
+// float64), written to out[k + i*n_pad + r*ldo].
+__global__ void slice_bf16_kernel(const double* __restrict__ U, int64_t ld, int64_t n_pad,
+                                  __bf16* __restrict__ out, int64_t ldo) {
+    for (int64_t r = blockIdx.x; r < n_pad; r += gridDim.x)
+        for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) {
+            double v = U[k + r * ld];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const __bf16 h = (__bf16)v;
+                out[k + i * n_pad + r * ldo] = h;
+                v -= (double)h;
+            }
+        }
+}
+
 // One workgroup per row of L^-1 (grid-stride): block max, power-of-two
 // scale, then exact 7-bit digits (every step is a multiplication by a power
 // of two or the subtraction of a nearby integer, so no rounding occurs).
@@ -418,6 +435,13 @@ hipError_t convert_bf16(const double* in, __bf16* out, int64_t ld, int64_t rows,
     if (ld < rows) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<int64_t>(cols, 8192);
     hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(grid), dim3(256), 0, s, in, out, ld, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, int64_t ldo, hipStream_t s) {
+    if (!U || !out || ld < n_pad || ldo < 3 * n_pad) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(n_pad, 8192);
+    hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(256), 0, s, U, ld, n_pad, out, ldo);
     return hipGetLastError();
 }
 

@@ -97,7 +97,9 @@ constexpr int MAX_GROUP = 64;
 struct TrmmArgs {
     int at, xt, cfg;
     const TrmmArgs* group;      // grouped launch: device array of per-context arguments
-    int slices;                 // A_I8S: int8 slices per row of L^-1
+    int slices;                 // A_I8S: int8 slices per row of L^-1; A_BF16: 3 for the
+                                // bfloat16-slice product (row r holds its slices one after
+                                // another, n_pad elements each), else 0
     const double* rscale;       // A_I8S: power-of-two scale of each row of L^-1
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
@@ -121,11 +123,19 @@ TrmmShape trmm_shape(int cfg);
 bool trmm_cfg_valid(int at, int xt, int cfg);
 int trmm_default_cfg(int at, int xt);
 constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of the floating-point shapes
-TrmmShape trmm_sliced_shape();       // tile of the int8-slice product (part_rows 16)
+// tiles of the int8-slice product (part_rows 16): shape cfg < trmm_sliced_cfgs()
+int trmm_sliced_cfgs();
+TrmmShape trmm_sliced_shape(int cfg = 0);
+bool trmm_sliced_direct(int cfg);    // the shape loads its operands straight into LDS
 // shape of the kernel that runs (at, xt, cfg, slices), with its schedule
 // grouping: rgroup row tiles per group, or the traffic model's choice for 0
 TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup = 0);
 constexpr int RGROUP_CANDIDATES[] = {1, 2, 4, 8};   // what the autotuner tries
+
+// Row r of L^-1 (column r of U, U[k + r*ld]) as three bfloat16 slices
+// out[k + i*n_pad + r*ldo], i = 0..2 (ldo >= 3 n_pad): slice i rounds what
+// slices 0..i-1 leave, so their sum is L^-1(r, k) to about 2^-27 relative.
+hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, int64_t ldo, hipStream_t s);
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
 // and S int8 slices A_s(r,k) with L^-1(r,k)/rscale[r] = sum_s A_s(r,k) 2^(-6-7s)
@@ -172,6 +182,33 @@ struct BackArgs {
     double* coef;
 };
 hipError_t snp_backward(const BackArgs& a, hipStream_t s);
+
+// One block row of the banded forward substitution for every SNP column of
+// a sub-block: Z_i = U_ii^T X_i + Gt^T Z_{i-1} (W x cols, float64), stored
+// into Zcur (column j at Zcur + j*ldz), with the partial sums of the dense
+// product (part[(pb*Q + q)*ldp + j], Q = Qc + 1, pb = global 32-row slice:
+// z^T C[:,q] for q < Qc and z^T z).
+//   Ut   U_ii = L_ii^-T, W x W column-major (row r of L_ii^-1 at Ut + r*W)
+//   Gt   -E_i^T U_ii (W x W column-major; unused in block row 0)
+//   X    n x cols dosages (xt), column j at X + j*ldx; rows blk*W.. are X_i
+//   C    n_pad x Qc whitened [Xbar_L | Ybar], ld ldc
+struct BandArgs {
+    int xt;
+    int64_t W, blk;
+    const double* Ut; const double* Gt;
+    const void* X; int64_t ldx; int64_t n; int64_t cols;
+    const double* Zprev; double* Zcur; int64_t ldz;
+    const double* C; int64_t ldc; int Qc;
+    double* part; int64_t ldp;
+};
+hipError_t band_step(const BandArgs& a, hipStream_t s);
+int band_part_rows();   // rows per partial-sum slice of band_step (32)
+// out (rows x cols, ld ldo) = block (row0.., col0..) of the SPD M given in
+// LAPACK lower band storage of half-bandwidth w (M(i,j) at AB[(i-j) + j*ldab],
+// j <= i <= j + w); zero above the diagonal and outside the band, identity
+// past n.
+hipError_t band_block(const double* AB, int64_t ldab, int64_t w, int64_t n, int64_t row0, int64_t col0,
+                      int64_t rows, int64_t cols, double* out, int64_t ldo, hipStream_t s);
 
 // Partial sums of the triangular product reduced in chunks of `chunk`
 // slices: out[(g*Q + q)*ldo + j] = sum over pb in chunk g (ascending) of

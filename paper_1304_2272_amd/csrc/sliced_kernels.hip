@@ -206,27 +206,192 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_kernel(TrmmArgs la
     }
 }
 
+// The same product with its operands loaded straight from global memory
+// into LDS (16-byte buffer loads with the LDS destination): no staging
+// registers and no LDS write instructions, so a wave's registers go to a
+// wider tile.  A stage row is 128 bytes of K with no padding; chunk c of
+// row r sits in slot c ^ (r & 7), so the 16 rows a fragment read touches
+// fall on distinct banks.  One load instruction of a wave fills 1 KB of
+// LDS, 8 rows of 8 slots, lane l writing slot l % 8 of row l / 8.  Reads
+// past the dosage block (columns past cols) return zero through the
+// buffer range; elements k >= n of a column may hold other data, which
+// meets zero entries of L^-1 for every row below n, and rows at or past n
+// are zeroed before the epilogue's sums.
+template <int S, int WGM, int WGN, int WTN, bool GROUPED>
+__global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_lds_kernel(TrmmArgs la) {
+    constexpr int BK = ROW_BYTES;                 // int8 K per stage row
+    constexpr int TMR = WGM * 16;                 // real rows per tile
+    constexpr int TMS = TMR * S;                  // sliced rows per tile
+    constexpr int TN = WGN * WTN * 16;
+    constexpr int NW = WGM * WGN;                 // waves
+    constexpr int NA = TMS / 8, NB = TN / 8;      // load instructions (8 rows each) per stage
+    static_assert(TMS % 8 == 0 && TN % 8 == 0, "whole load instructions");
+
+    const int e0 = la.sched[2 * (int64_t)blockIdx.x];
+    const int J = la.sched[2 * (int64_t)blockIdx.x + 1];
+    if (e0 < 0) return;
+    const int I = e0 & SCHED_ROW_MASK;
+    const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
+    if ((int64_t)J * TN >= a.cols) return;
+
+    __shared__ __attribute__((aligned(1024))) char As[2][TMS * BK];
+    __shared__ __attribute__((aligned(1024))) char Bs[2][TN * BK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WGN, wc = wave % WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    const int64_t r0 = (int64_t)I * TMR;
+    const int64_t kend = std::min<int64_t>(r0 + TMR, a.n_pad);
+    const int nk = (int)((kend + BK - 1) / BK);
+    const int64_t c0 = (int64_t)J * TN;
+
+    // descriptors: the tile's sliced rows of L^-1; its dosage columns up to
+    // the 16-byte chunk holding element n - 1 of the last column in the block
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(a.Ut) + (int64_t)I * TMS * a.ldu), (short)0,
+        (int)(TMS * a.ldu), 0x00020000);
+    const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
+    const int64_t xbytes = ((xcols - 1) * a.ldx + a.n + 15) / 16 * 16;
+    const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int8_t*>(reinterpret_cast<const int8_t*>(a.X) + c0 * a.ldx), (short)0, (int)xbytes, 0x00020000);
+    // this lane's row (column) within each of its load instructions and the
+    // swizzled chunk it fetches
+    const int lrow = lane >> 3;
+    const int lchunk = (lane & 7) ^ (lrow & 7);
+    // instruction q of a stage (8 rows) is issued by wave q % NW
+    auto load = [&](int kt, int buf) {
+#pragma unroll
+        for (int c = 0; c < (NA + NW - 1) / NW; ++c) {
+            const int q = wave + c * NW;
+            if (NA % NW == 0 || q < NA) {
+                const int row = q * 8 + lrow;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsA, (__attribute__((address_space(3))) void*)(As[buf] + q * 8 * BK), 16,
+                    (unsigned)(row * a.ldu + kt * BK + lchunk * 16), 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < (NB + NW - 1) / NW; ++c) {
+            const int q = wave + c * NW;
+            if (NB % NW == 0 || q < NB) {
+                const int col = q * 8 + lrow;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsB, (__attribute__((address_space(3))) void*)(Bs[buf] + q * 8 * BK), 16,
+                    (unsigned)(col * a.ldx + kt * BK + lchunk * 16), 0, 0, 0);
+            }
+        }
+    };
+
+    i4_t acc[S][WTN];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = i4_t{0, 0, 0, 0};
+
+    // fragment rows start at multiples of 16: row & 7 = li & 7
+    const int sw = li & 7;
+    auto read_step = [&](int buf, int h, u4_t (&fa)[S], u4_t (&fb)[WTN]) {
+        const int slot = ((2 * lg + h) ^ sw) * 16;
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            fa[i] = *reinterpret_cast<const u4_t*>(As[buf] + (wr * S * 16 + i * 16 + li) * BK + slot);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+            fb[j] = *reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * BK + slot);
+    };
+    auto mma_step = [&](const u4_t (&fa)[S], const u4_t (&fb)[WTN]) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reinterpret_cast<const i4_t&>(fa[i]),
+                                                                 reinterpret_cast<const i4_t&>(fb[j]), acc[i][j], 0, 0, 0);
+    };
+    load(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        // the other buffer held stage kt - 1, which every wave finished
+        // reading before the previous barrier
+        if (kt + 1 < nk) load(kt + 1, buf ^ 1);
+        u4_t a0[S], b0[WTN], a1[S], b1[WTN];
+        read_step(buf, 0, a0, b0);
+        read_step(buf, 1, a1, b1);
+        mma_step(a0, b0);
+        mma_step(a1, b1);
+        // this wave's loads into the other buffer have landed; then every wave's
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+    const int Q = a.with_cross ? a.Qc + 1 : 1;
+    const int64_t rw = r0 + wr * 16;
+    const int64_t pb = rw / 16;
+    const int64_t cbase = c0 + wc * WTN * 16 + li;
+    double sc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t r = rw + I8_ROW_G * lg + I8_ROW_V * v;
+        sc[v] = r < a.n ? a.rscale[r] : 0.0;      // rows past n: zero
+    }
+    double z[WTN][4];
+#pragma unroll
+    for (int j = 0; j < WTN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = S - 1; i >= 0; --i) t += ldexp((double)acc[i][j][v], -6 - 7 * i);
+            z[j][v] = sc[v] * t;
+        }
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum += z[j][v] * z[j][v];
+        sum = wave_sum16(sum);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+    }
+}
+
 }  // namespace
 
-TrmmShape trmm_sliced_shape() { return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512, 1, 32}; }
+// Shapes of the int8-slice product: 0, operands staged through registers
+// (32 real rows x 256 columns); 1, the same tile loaded straight into LDS;
+// 2, loaded straight into LDS with waves of 16 x 80 (32 x 320).
+int trmm_sliced_cfgs() { return 3; }
+TrmmShape trmm_sliced_shape(int cfg) {
+    return TrmmShape{2 * 16, cfg == 2 ? 4 * 5 * 16 : 4 * 4 * 16, 16, 512, 1, 32};
+}
+bool trmm_sliced_direct(int cfg) { return cfg == 1 || cfg == 2; }
+
+namespace {
+template <bool G>
+hipError_t launch_sliced(const TrmmArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.n_sched), block(512);
+#define GWAS_SLICED_CASE(S)                                                                            \
+    case S:                                                                                            \
+        if (a.cfg == 0) hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, G>), grid, block, 0, s, a);       \
+        else if (a.cfg == 1) hipLaunchKernelGGL((trmm_sliced_lds_kernel<S, 2, 4, 4, G>), grid, block, 0, s, a); \
+        else if (a.cfg == 2) hipLaunchKernelGGL((trmm_sliced_lds_kernel<S, 2, 4, 5, G>), grid, block, 0, s, a); \
+        else return hipErrorInvalidValue;                                                               \
+        return hipGetLastError();
+    switch (a.slices) {
+        GWAS_SLICED_CASE(4) GWAS_SLICED_CASE(5) GWAS_SLICED_CASE(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef GWAS_SLICED_CASE
+}
+}  // namespace
 
 // Arguments were checked by trmm_check (single launches) or by the caller
 // (grouped launches).
 hipError_t trmm_sliced_launch(const TrmmArgs& a, hipStream_t s) {
-    switch (a.slices) {
-#define GWAS_SLICED_CASE(S)                                                                       \
-    case S:                                                                                       \
-        if (a.group)                                                                              \
-            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, true>), dim3((unsigned)a.n_sched),  \
-                               dim3(512), 0, s, a);                                               \
-        else                                                                                      \
-            hipLaunchKernelGGL((trmm_sliced_kernel<S, 2, 4, 4, false>), dim3((unsigned)a.n_sched), \
-                               dim3(512), 0, s, a);                                               \
-        return hipGetLastError();
-        GWAS_SLICED_CASE(4) GWAS_SLICED_CASE(5) GWAS_SLICED_CASE(6)
-#undef GWAS_SLICED_CASE
-        default: return hipErrorInvalidValue;
-    }
+    return a.group ? launch_sliced<true>(a, s) : launch_sliced<false>(a, s);
 }
 
 }  // namespace gwas

@@ -99,6 +99,21 @@ template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_, bool SUM32_ = false
     static constexpr int NT = 64 * WGM * WGN;     // threads
 };
 
+// Segments of the bfloat16-slice product: the K range runs once per pair
+// (slice i of L^-1, slice j of the dosages) with i + j <= 2, smallest
+// first, all into the same sums.  Three slices of L^-1 with int8 dosages
+// (exact in bfloat16): (2,0), (1,0), (0,0); with float64 dosages, cut into
+// three slices as well: (2,0), (1,1), (0,2), (1,0), (0,1), (0,0).
+__device__ __forceinline__ int seg_a(int nseg, int s) {
+    if (nseg == 3) return 2 - s;
+    if (nseg == 6) return s == 0 ? 2 : (s == 1 || s == 3) ? 1 : 0;
+    return 0;
+}
+__device__ __forceinline__ int seg_x(int nseg, int s) {
+    if (nseg == 6) return (s == 1 || s == 4) ? 1 : s == 2 ? 2 : 0;
+    return 0;
+}
+
 // One TM x TN tile of Z = L^-1 X per workgroup.  The tile's K range is
 // [0, r0 + TM) because L^-1 is lower triangular.  Stages of 128 bytes of K
 // per row go global -> registers -> LDS (double buffered); within a stage
@@ -153,6 +168,12 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     // stage index: 32-bit where registers are short (SUM32 shapes)
     typedef typename std::conditional<S::SUM32, int, int64_t>::type kidx_t;
     const kidx_t nk = (kidx_t)(kend / BK);
+    // the bfloat16-slice product (a.slices == 3) runs the K range once per
+    // segment; slice i of L^-1 starts i * n_pad elements into each row
+    const int nseg = (sizeof(AT) == 2 && a.slices == 3) ? (sizeof(XT) == 1 ? 3 : 6) : 1;
+    const kidx_t nkt = nk * (kidx_t)nseg;
+    const int64_t seg_bytes = a.n_pad * (int64_t)sizeof(AT);
+    int xj_next = 0;   // dosage slice of the stage held in the staging registers
     const char* Ut = reinterpret_cast<const char*>(a.Ut);
     const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
     const XT* X = reinterpret_cast<const XT*>(a.X);
@@ -196,10 +217,17 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         voB = (tid / CPC) * (int)(a.ldx * (int64_t)sizeof(XT)) + (tid % CPC) * 16;
     }
     auto load_buf = [&](int kt) {
+        int ai = 0;
+        if (nseg > 1) {
+            const int seg = kt / (int)nk;
+            kt -= seg * (int)nk;
+            ai = seg_a(nseg, seg);
+            xj_next = seg_x(nseg, seg);
+        }
 #pragma unroll
         for (int c = 0; c < CA; ++c)
             ra[c] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 rsA, voA, (int)(c * (NT / 8) * row_bytes + kt * ROW_BYTES), 0));
+                                                 rsA, voA, (int)(c * (NT / 8) * row_bytes + kt * ROW_BYTES + ai * seg_bytes), 0));
 #pragma unroll
         for (int c = 0; c < CB; ++c)
             rb[c] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(
@@ -223,12 +251,19 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             load_buf(kt);
             return;
         }
+        int64_t aoff = 0;
+        if (nseg > 1) {
+            const kidx_t seg = kt / nk;
+            kt -= seg * nk;
+            aoff = seg_a(nseg, (int)seg) * seg_bytes;
+            xj_next = seg_x(nseg, (int)seg);
+        }
 #pragma unroll
         for (int c = 0; c < CA; ++c) {
             const int idx = tid + c * NT;
             if (A_CHUNKS % NT == 0 || idx < A_CHUNKS) {
                 const int row = idx >> 3, ch = idx & 7;
-                ra[c] = *reinterpret_cast<const u4_t*>(Ut + (r0 + row) * row_bytes + kt * ROW_BYTES + ch * 16);
+                ra[c] = *reinterpret_cast<const u4_t*>(Ut + (r0 + row) * row_bytes + aoff + kt * ROW_BYTES + ch * 16);
             }
         }
         // Whole tile inside the block and the stage inside n: one branch for
@@ -307,8 +342,22 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 const XT* x = reinterpret_cast<const XT*>(&rb[c]);
 #pragma unroll
                 for (int e = 0; e < EPC; ++e) {
-                    if constexpr (sizeof(XT) == 1) dst[e] = from_i8<AT>((int8_t)x[e]);
-                    else dst[e] = from_f64<AT>((double)x[e]);
+                    if constexpr (sizeof(XT) == 1) {
+                        dst[e] = from_i8<AT>((int8_t)x[e]);
+                    } else if constexpr (sizeof(AT) == 2) {
+                        // slice xj of a float64 dosage: what the slices
+                        // before it leave, rounded to bfloat16 (each
+                        // remainder is exact in float64)
+                        double v = (double)x[e];
+                        if (nseg > 1) {
+                            for (int q = 0; q < xj_next; ++q) v -= (double)(__bf16)v;
+                            dst[e] = (__bf16)v;
+                        } else {
+                            dst[e] = from_f64<AT>(v);
+                        }
+                    } else {
+                        dst[e] = from_f64<AT>((double)x[e]);
+                    }
                 }
             }
         }
@@ -374,9 +423,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     store(0);
     __syncthreads();
     if constexpr (S::SUM32) {
-        for (kidx_t kt = 0; kt < nk; ++kt) {
+        for (kidx_t kt = 0; kt < nkt; ++kt) {
             const int buf = kt & 1;
-            const bool more = kt + 1 < nk;
+            const bool more = kt + 1 < nkt;
             if (more) load(kt + 1);
             piece_t pa[SETS][WTM], pb[SETS][WTN];
             // lgkmcnt(0), already met after the previous barrier: it tells
@@ -409,9 +458,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             __syncthreads();
         }
     } else if constexpr (NQ == 1) {
-        for (kidx_t kt = 0; kt < nk; ++kt) {
+        for (kidx_t kt = 0; kt < nkt; ++kt) {
             const int buf = kt & 1;
-            const bool more = kt + 1 < nk;
+            const bool more = kt + 1 < nkt;
             if (more) load(kt + 1);
             piece_t fa[2][WTM], fb[2][WTN];
             read_piece(buf, 0, fa[0], fb[0]);
@@ -429,9 +478,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     } else {
         piece_t pa[2][WTM], pb[2][WTN];
         read_piece(0, 0, pa[0], pb[0]);
-        for (kidx_t kt = 0; kt < nk; ++kt) {
+        for (kidx_t kt = 0; kt < nkt; ++kt) {
             const int buf = kt & 1;
-            const bool more = kt + 1 < nk;
+            const bool more = kt + 1 < nkt;
             if (more) load(kt + 1);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -593,6 +642,7 @@ TrmmShape trmm_shape(int cfg) {
 }
 
 bool trmm_cfg_valid(int at, int xt, int cfg) {
+    if (at == A_I8S) return xt == X_I8 && cfg >= 0 && cfg < trmm_sliced_cfgs();
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
     // 64 x 128 waves fit two per SIMD only with float32 sums and int8 dosages
     if (cfg == 6) return at != A_F64 && xt == X_I8;
@@ -615,13 +665,14 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 // 128 x 256 tile and the reduced-precision products take the 128 x 128
 // tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
+    if (at == A_I8S) return 0;
     if (at == A_F64) return xt == X_I8 ? 2 : 3;
     if (xt == X_I8) return 6;
     return 1;
 }
 
 TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup) {
-    TrmmShape sh = (at == A_I8S) ? trmm_sliced_shape() : trmm_shape(cfg);
+    TrmmShape sh = (at == A_I8S) ? trmm_sliced_shape(cfg) : trmm_shape(cfg);
     if (sh.tm == 0) return sh;
     // workgroups per CU: the 256-thread shape is sized for two
     const int per_cu = (at != A_I8S && cfg == 0) ? 2 : 1;
@@ -659,7 +710,13 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.at == A_I8S) {
         // the int8-slice product forms z^T z only (its mode takes the cross
         // products from x^T W)
-        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6 || a.with_cross)
+        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6 || a.with_cross ||
+            !trmm_cfg_valid(a.at, a.xt, a.cfg))
+            return hipErrorInvalidValue;
+        // 32-bit buffer offsets of the shapes that load straight into LDS
+        const TrmmShape sh = trmm_sliced_shape(a.cfg);
+        if (trmm_sliced_direct(a.cfg) &&
+            ((int64_t)sh.tm * a.slices * a.ldu > INT32_MAX || (int64_t)sh.tn * a.ldx + a.n_pad > INT32_MAX))
             return hipErrorInvalidValue;
     } else {
         if (!trmm_cfg_valid(a.at, a.xt, a.cfg)) return hipErrorInvalidValue;

@@ -122,6 +122,87 @@ def make_problem(n: int, p: int, seed: int, t: int = 1, h2: float = 0.5,
             "h2": h2, "sigma2": sigma2, "k": k, "seed": seed}
 
 
+def banded_problem(n: int, p: int, seed: int, w: int, t: int = 1, h2: float = 0.5, sigma2: float = 1.0,
+                   cover: int = 8, noise: bool = True, device=None):
+    """A cohort whose relatives sit next to each other: M of half-bandwidth w.
+
+    Local markers stand in for shared haplotypes: marker j is carried by a
+    window of w + 1 consecutive individuals starting at a_j (windows evenly
+    spaced so that each individual is in about ``cover`` of them), with
+    Binomial(2, f_j) genotypes, f_j ~ U(0.05, 0.5), standardised within the
+    window (monomorphic draws redrawn) and scaled by 1/sqrt(cover).  With Z
+    the n x K matrix of these columns, Phi = Z Z^T has Phi(i, i') = 0 for
+    |i - i'| > w and M = sigma^2 (h^2 Phi + (1 - h^2) I) is SPD.  e ~ N(0, M)
+    is drawn as sigma (sqrt(h^2) Z g + sqrt(1 - h^2) eps).  Returns M in lower
+    band storage, an (n, w + 1) array with M_band[j, d] = M(j + d, j), beside
+    X_L, Y and beta as :func:`make_problem` draws them.  With ``device`` (a
+    torch device string) the band is accumulated there, in the same order
+    and float64 operations, and returned as a numpy array.
+    """
+    if not 1 <= w < n:
+        raise ValueError("1 <= w < n")
+    L = w + 1
+    K = max(1, -(-cover * n // L))
+    starts = np.linspace(0, n - L, K).round().astype(np.int64)
+    f = _child(seed, 10).uniform(0.05, 0.5, size=K)
+    rng = _child(seed, 11)
+    g = _child(seed, _S_G).standard_normal((K, t))
+    e = np.zeros((n, t))
+    zs = []
+    for j in range(K):
+        z = _dosages_from_uniform(rng.random(L), f[j]).astype(np.float64)
+        while z.std() == 0.0:
+            z = _dosages_from_uniform(rng.random(L), f[j]).astype(np.float64)
+        z = (z - z.mean()) / z.std() / np.sqrt(cover)
+        zs.append(z)
+        e[starts[j]:starts[j] + L] += np.outer(z, g[j])
+    # column r of marker j's window gets z[r + d] z[r] at band offset d
+    if device is None:
+        band = np.zeros((n, L))
+        pad = np.zeros((L + L, L))
+        for j in range(K):
+            pad[:L] = np.outer(zs[j], zs[j])
+            band[starts[j]:starts[j] + L] += np.lib.stride_tricks.as_strided(pad, shape=(L, L),
+                                                                             strides=((L + 1) * 8, L * 8))
+    else:
+        import torch
+        bt = torch.zeros((n, L), dtype=torch.float64, device=device)
+        pt = torch.zeros((L + L, L), dtype=torch.float64, device=device)
+        for j in range(K):
+            zt = torch.from_numpy(zs[j]).to(device)
+            pt[:L] = torch.outer(zt, zt)
+            bt[starts[j]:starts[j] + L] += torch.as_strided(pt, (L, L), (L + 1, L))
+        band = bt.cpu().numpy()
+        del bt, pt
+    # entries past the matrix (row j + d >= n) stay zero
+    band *= sigma2 * h2
+    band[:, 0] += sigma2 * (1.0 - h2)
+    for d in range(1, L):
+        band[n - d:, d] = 0.0
+    XL = np.empty((n, p - 1))
+    XL[:, 0] = 1.0
+    if p > 2:
+        XL[:, 1:] = _child(seed, _S_XL).standard_normal((n, p - 2))
+    beta = _child(seed, _S_BETA).standard_normal((p - 1, t))
+    Y = XL @ beta
+    if noise:
+        eps = _child(seed, _S_EPS).standard_normal((n, t))
+        Y = Y + np.sqrt(sigma2 * h2) * e + np.sqrt(sigma2 * (1.0 - h2)) * eps
+    return {"M_band": band, "XL": XL, "Y": Y, "beta": beta, "n": n, "p": p, "t": t, "w": w,
+            "h2": h2, "sigma2": sigma2, "seed": seed}
+
+
+def band_to_dense(M_band: np.ndarray) -> np.ndarray:
+    """The symmetric n x n matrix of lower band storage (n, w + 1)."""
+    n, L = M_band.shape
+    M = np.zeros((n, n))
+    for d in range(L):
+        idx = np.arange(n - d)
+        M[idx + d, idx] = M_band[:n - d, d]
+        M[idx, idx + d] = M_band[:n - d, d]
+    return M
+
+
 def snp_chunk(n: int, seed: int, chunk: int, dtype=np.float64, cohort=None) -> np.ndarray:
     """Dosage chunk ``chunk`` (CHUNK SNPs), SNP-major (CHUNK, n).
 
@@ -147,6 +228,15 @@ def snp_block(n: int, seed: int, start: int, cols: int, dtype=np.float64, cohort
         hi = min(start + cols, (c + 1) * CHUNK)
         out[lo - start:hi - start] = blk[lo - c * CHUNK:hi - c * CHUNK]
     return out
+
+
+def imputed_block(n: int, seed: int, start: int, cols: int) -> np.ndarray:
+    """Non-integer dosages in [0, 2] as imputation gives them (expected
+    allele counts): the hard calls of :func:`snp_block` plus N(0, 0.2^2)
+    noise, clipped to [0, 2]; SNP-major (cols, n) float64."""
+    x = snp_block(n, seed, start, cols, dtype=np.float64)
+    noise = _child(seed, _S_XR, 1 << 20, start).normal(0.0, 0.2, size=x.shape)
+    return np.clip(x + noise, 0.0, 2.0)
 
 
 def snp_block_device(n: int, seed: int, start: int, cols: int, device, dtype=None, cohort=None):

@@ -69,7 +69,7 @@ def _desc(n=16, p=3, t=1, **kw):
 @pytest.mark.parametrize("field,value", [
     ("n", 2), ("p", 1), ("p", 21), ("t", 0), ("ldm", 5), ("ldxl", 5), ("ldy", 5),
     ("precision", 9), ("x_dtype", 3), ("M", None), ("XL", None), ("Y", None),
-    ("dev_block", -5),
+    ("dev_block", -5), ("band", -1),
 ])
 def test_init_rejects_invalid_before_device(lib, field, value):
     d, keep = _desc(**{field: value})
@@ -86,6 +86,22 @@ def test_init_without_device_reports_no_device(lib):
     h = ctypes.c_void_p()
     assert lib.gwas_init(ctypes.byref(h), ctypes.byref(d)) == 4   # GWAS_E_NO_DEVICE
     assert h.value is None
+
+
+def test_banded_descriptor_validated_before_device(lib):
+    # band needs float64 arithmetic and ldm >= band + 1; checked before any
+    # device call
+    import numpy as np
+    assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 100, 101, 0) > 0
+    assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 100, 100, 0) == 0     # ldm < band + 1
+    assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 0, 1, 0) == 0         # band < 1
+    # far smaller than the dense factor at n = 20,000 with w = 500
+    assert lib.gwas_workspace_bytes_band(20000, 4, 1, 0, 500, 501, 1) < lib.gwas_workspace_bytes(20000, 4, 1, 0, 0, 1) / 4
+    for precision, ldm in ((1, 17), (0, 5)):     # float32 arithmetic; ldm < band + 1
+        d, keep = _desc(n=16, p=3, band=5, ldm=ldm, precision=precision)
+        h = ctypes.c_void_p(123)
+        assert lib.gwas_init(ctypes.byref(h), ctypes.byref(d)) == 1
+        assert h.value is None
 
 
 def test_null_context_calls(lib):

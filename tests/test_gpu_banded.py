@@ -1,0 +1,104 @@
+"""Banded M (the variant of Section 5.1: relatives grouped near the
+diagonal): the block-bidiagonal factor and the block forward substitution of
+each streamed block against the CPU oracle, which takes the same M dense."""
+
+import numpy as np
+import pytest
+
+from oracle import GLSOracle
+from paper_1304_2272_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def normwise(b, bref):
+    num = np.linalg.norm((b - bref).reshape(b.shape[0], -1), axis=1)
+    den = np.linalg.norm(bref.reshape(b.shape[0], -1), axis=1)
+    return float(np.max(num / den))
+
+
+@pytest.mark.parametrize("n,w,p,t,m,x_dtype,dev_block", [
+    (3000, 100, 4, 1, 1500, "f64", 0),      # W = 256, 12 block rows, n not a multiple of W
+    (2100, 300, 8, 1, 1300, "i8", 256),     # W = 512, ragged sub-blocks
+    (700, 650, 3, 2, 400, "f64", 128),      # one block row (W = 768 >= n), two traits
+    (5000, 1000, 3, 1, 900, "i8", 0),       # W = 1024, 5 block rows
+    (1290, 256, 5, 1, 333, "f64", 128),     # w = W exactly
+])
+def test_banded_vs_oracle(n, w, p, t, m, x_dtype, dev_block):
+    seed = 5100 + n + w
+    _say(f"banded n={n} w={w} p={p} t={t} m={m} {x_dtype} dev_block={dev_block}")
+    prob = synth.banded_problem(n, p, seed, w, t=t)
+    xdt = np.int8 if x_dtype == "i8" else np.float64
+    XR = synth.snp_block(n, seed, 0, m, dtype=xdt)
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], x_dtype=x_dtype, dev_block=dev_block,
+                             band=w) as ctx:
+        b, var, info = ctx.stream_block(XR)
+    M = synth.band_to_dense(prob["M_band"])
+    bo, vo, io = GLSOracle(M, prob["XL"], prob["Y"]).solve(XR)
+    err = normwise(b, bo)
+    verr = float(np.max(np.abs(var - vo) / vo))
+    _say(f"  normwise {err:.3e}, var {verr:.3e}")
+    assert np.array_equal(info, io) and (io == 0).all()
+    assert err < TOL and verr < TOL
+
+
+def test_banded_equals_dense_path_and_partitions():
+    # the same M through the dense path; and a SNP's result does not depend
+    # on the block or sub-block it comes in (bit for bit)
+    import torch
+    n, w, p, m, seed = 1800, 200, 4, 1000, 5201
+    prob = synth.banded_problem(n, p, seed, w)
+    M = synth.band_to_dense(prob["M_band"])
+    XR = synth.snp_block(n, seed, 0, m)
+    with binding.GwasContext(M, prob["XL"], prob["Y"]) as ctx:
+        bd, vd, _ = ctx.stream_block(XR)
+    dev = torch.device("cuda:0")
+    Mb = torch.from_numpy(prob["M_band"]).to(dev)
+    XL, Y = torch.from_numpy(prob["XL"]).to(dev), torch.from_numpy(prob["Y"]).to(dev)
+    with binding.GwasContext(Mb, XL, Y, band=w, dev_block=256) as ctx:
+        Xd = torch.from_numpy(XR).to(dev)
+        b1, v1, _ = ctx.stream_block(Xd)
+        parts = [ctx.stream_block(Xd[a:z]) for a, z in ((0, 129), (129, 700), (700, m))]
+    b1, v1 = b1.cpu().numpy(), v1.cpu().numpy()
+    err = normwise(b1, bd)
+    _say(f"banded vs dense path: normwise {err:.3e}")
+    assert err < 1e-12 and float(np.max(np.abs(v1 - vd) / vd)) < 1e-12
+    b2 = np.concatenate([q[0].cpu().numpy() for q in parts])
+    assert np.array_equal(b2, b1)
+
+
+def test_banded_not_spd_and_rank_deficient_snp():
+    n, w, p, seed = 900, 120, 4, 5301
+    prob = synth.banded_problem(n, p, seed, w)
+    XR = synth.snp_block(n, seed, 0, 50)
+    XR[7] = 1.0                                   # collinear with the intercept
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], band=w) as ctx:
+        b, var, info = ctx.stream_block(XR)
+    assert info[7] == p and np.isnan(b[7]).all()
+    assert (np.delete(info, 7) == 0).all()
+    bad = prob["M_band"].copy()
+    bad[613, 0] = -1.0                            # M(613, 613) < 0: leading minor 614 fails
+    with pytest.raises(binding.GwasError) as ei:
+        binding.GwasContext(bad, prob["XL"], prob["Y"], band=w)
+    assert ei.value.code == 2 and ei.value.info == 614
+
+
+def test_banded_calls_that_need_the_dense_factor_are_refused():
+    import torch
+    n, w, p, seed = 600, 60, 3, 5401
+    prob = synth.banded_problem(n, p, seed, w)
+    XR = synth.snp_block(n, seed, 0, 40)
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], band=w) as ctx:
+        for call in (lambda: ctx.backward_begin(), lambda: ctx.autotune(XR),
+                     lambda: binding.stream_group([ctx], [XR])):
+            with pytest.raises(binding.GwasError) as ei:
+                call()
+            assert ei.value.code == 1
+        b, _, info = ctx.stream_block(XR)        # the context stays usable
+        assert (info == 0).all()

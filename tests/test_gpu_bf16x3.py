@@ -1,0 +1,131 @@
+"""The bfloat16-slice product (GWAS_BF16X3_REFINE) against the CPU oracle:
+L^-1 as three bfloat16 slices, float64 dosages (here non-integer, as
+imputation gives them) cut into three slices while staged, and the products
+of slices i + j <= 2 summed on bfloat16 matrix cores in float32.  Every SNP is
+held to the stated error of the float32 mode (16 u kappa_i on the SNP
+coefficient and var with u = 2^-24), and the normwise error of b to at most
+four times the float32 mode's on the same inputs; at n = 20,000 (float64 dosages,
+as streamed in the n = 20,000 workload) to 1e-8 normwise."""
+
+import numpy as np
+import pytest
+
+from oracle import GLSOracle
+from paper_1304_2272_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def normwise(b, bref):
+    num = np.linalg.norm((b - bref).reshape(b.shape[0], -1), axis=1)
+    den = np.linalg.norm(bref.reshape(b.shape[0], -1), axis=1)
+    return float(np.max(num / den))
+
+
+def floor_ratio(orc, XR, b, bo, var, vo):
+    """Worst error of b_SNP and var over 16 u kappa_i, kappa_i = S_BR / s_i."""
+    N, _ = orc.normal_equations(XR)
+    kappa = N[:, -1, -1] * vo
+    lim = 16.0 * U32 * kappa
+    rel = np.abs(b[:, 0, -1] - bo[:, 0, -1]) / np.abs(bo[:, 0, -1])
+    vrel = np.abs(var - vo) / vo
+    return max(float(np.max(rel / lim)), float(np.max(vrel / lim))), float(kappa.max())
+
+
+def check(prob, XR, x_dtype, vs_fp32=True, **kw):
+    orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
+    bo, vo, io = orc.solve(XR)
+    errs = {}
+    for precision in ("bf16x3", "fp32") if vs_fp32 else ("bf16x3",):
+        with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype=x_dtype,
+                                 **kw) as ctx:
+            b, var, info = ctx.stream_block(XR)
+        assert np.array_equal(info, io) and (io == 0).all()
+        errs[precision] = normwise(b, bo)
+        worst, kmax = floor_ratio(orc, XR, b, bo, var, vo)
+        _say(f"  {precision}: normwise {errs[precision]:.3e}; SNP coefficient and var against 16 u kappa: "
+             f"{worst:.3f} (kappa <= {kmax:.1f})")
+        assert worst <= 1.0
+        if precision == "bf16x3":
+            b3 = b
+    if vs_fp32:
+        # both keep float32 sums; a bfloat16 instruction adds 32 products per
+        # accumulation step against the float32 instruction's 4 (measured
+        # 2.1 to 2.4 times the float32 mode's normwise error)
+        assert errs["bf16x3"] <= 4.0 * errs["fp32"] + 1e-12
+    return b3, errs["bf16x3"]
+
+
+@pytest.mark.parametrize("n,p,m,dev_block", [(700, 4, 1500, 512), (3000, 8, 2000, 0), (2300, 3, 900, 256)])
+def test_imputed_float64_dosages_vs_oracle(n, p, m, dev_block):
+    seed = 3300 + n
+    _say(f"bf16x3 float64 imputed dosages n={n} p={p} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.imputed_block(n, seed, 0, m)
+    assert not np.all(XR == np.round(XR))
+    check(prob, XR, "f64", dev_block=dev_block)
+
+
+@pytest.mark.parametrize("n,p,m", [(1500, 8, 3000), (4100, 4, 1000)])
+def test_int8_dosages_vs_oracle(n, p, m):
+    seed = 3400 + n
+    _say(f"bf16x3 int8 dosages n={n} p={p} m={m}")
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    check(prob, XR, "i8")
+
+
+@pytest.mark.parametrize("x_dtype,cfgs", [("i8", [1, 2, 3, 5, 6]), ("f64", [1, 2, 5])])
+def test_every_tile_shape(x_dtype, cfgs, monkeypatch):
+    n, p, m, seed = 900, 5, 700, 3500
+    prob = synth.make_problem(n, p, seed, k=300)
+    XR = (synth.snp_block(n, seed, 0, m, dtype=np.int8) if x_dtype == "i8" else synth.imputed_block(n, seed, 0, m))
+    for cfg in cfgs:
+        monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
+        _say(f"bf16x3 {x_dtype} tile shape {cfg}")
+        check(prob, XR, x_dtype, dev_block=384)
+
+
+@pytest.mark.parametrize("n,p,m,dev_block", [(17, 3, 60, 128), (130, 5, 300, 128), (255, 4, 300, 256),
+                                               (257, 4, 531, 512)])
+@pytest.mark.parametrize("x_dtype", ["f64", "i8"])
+def test_small_and_ragged(n, p, m, dev_block, x_dtype):
+    # n below one stage, one tile and just past a tile; ragged column tiles
+    seed = 3600 + n
+    _say(f"bf16x3 {x_dtype} n={n} p={p} m={m} dev_block={dev_block}")
+    prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
+    XR = (synth.snp_block(n, seed, 0, m, dtype=np.int8) if x_dtype == "i8" else synth.imputed_block(n, seed, 0, m))
+    check(prob, XR, x_dtype, dev_block=dev_block)
+
+
+@pytest.mark.timeout(300)
+def test_n20000_float64_dosages_vs_oracle():
+    # the n = 20,000 workload's float64 wire format, imputed dosages
+    n, p, m, seed = 20_000, 4, 300, 3800
+    _say(f"bf16x3 float64 imputed dosages n={n} p={p} m={m}")
+    prob = synth.make_problem(n, p, seed, device="cuda:0")
+    prob["M"] = prob["M"].cpu().numpy()
+    XR = synth.imputed_block(n, seed, 0, m)
+    _, err = check(prob, XR, "f64", vs_fp32=False)
+    assert err < 1e-8
+
+
+def test_more_accurate_than_one_bfloat16_slice():
+    # the three slices carry L^-1 to about 2^-27; one slice (GWAS_BF16_REFINE)
+    # rounds it to 2^-9
+    n, p, m, seed = 2000, 4, 800, 3700
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.imputed_block(n, seed, 0, m)
+    _, e3 = check(prob, XR, "f64")
+    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision="bf16", x_dtype="f64") as ctx:
+        b1, _, _ = ctx.stream_block(XR)
+    bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    e1 = normwise(b1, bo)
+    _say(f"  one slice {e1:.3e}, three slices {e3:.3e}")
+    assert e3 < 1e-3 * e1

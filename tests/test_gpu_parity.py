@@ -243,7 +243,7 @@ def test_reduced_precision_vs_oracle(precision, tol):
     assert err < tol
 
 
-TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6]}
+TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6], "int8": [0, 1, 2]}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
@@ -338,6 +338,41 @@ def test_int8_slices(slices, tol):
     _say(f"  normwise err {err:.3e} var err {verr:.3e}")
     assert np.array_equal(info, io)
     assert err < tol and verr < 100 * tol
+
+
+@pytest.mark.parametrize("n,p,m,dev_block", [(2100, 6, 2500, 1024), (777, 3, 1500, 256), (130, 5, 300, 128),
+                                               (17, 3, 60, 128), (1030, 4, 333, 384)])
+@pytest.mark.parametrize("slices", [5, 6])
+def test_int8_slice_shapes_agree_bit_for_bit(n, p, m, dev_block, slices, monkeypatch):
+    # the register-staged shape (0) and the shapes that load straight into
+    # LDS (1, and 2 with wider waves) form the same exact int32 sums, so
+    # their results are equal bit for bit; strided device dosages with
+    # garbage past n give the same bits as compact ones
+    import torch
+    seed = 61 + n
+    prob = synth.make_problem(n, p, seed, k=max(50, n // 2))
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    dev = torch.device("cuda:0")
+    ldx = (n + 15) // 16 * 16 + 48
+    big = torch.full((m, ldx), 113, dtype=torch.int8, device=dev)
+    big[:, :n] = torch.from_numpy(XR).to(dev)
+    ref = None
+    for cfg in (0, 1, 2):
+        monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
+        _say(f"int8 slices={slices} shape {cfg} n={n} p={p} m={m} dev_block={dev_block}")
+        kw = dict(precision="int8", x_dtype="i8", slices=slices, dev_block=dev_block)
+        b, var, info = run(prob, XR, **kw)
+        bs, vs, is_ = run(prob, big[:, :n], **kw)
+        assert np.array_equal(b, bs.cpu().numpy()) and np.array_equal(var, vs.cpu().numpy())
+        if ref is None:
+            bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+            assert np.array_equal(info, io)
+            err = normwise(b[io == 0], bo[io == 0])
+            _say(f"  normwise {err:.3e} against the oracle")
+            assert err < (1e-9 if slices == 5 else TOL_FP64)
+            ref = (b, var, info)
+        else:
+            assert np.array_equal(b, ref[0]) and np.array_equal(var, ref[1]) and np.array_equal(info, ref[2])
 
 
 def test_int8_slices_needs_int8_dosages():
@@ -480,17 +515,19 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
         with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
                                  dev_block=1024) as ctx:
             best = ctx.autotune(XR, 1024)
-            _say(f"autotune {precision}: tile shape {best[0]}, row group {best[1]}")
-            assert best[0] in TILE_SHAPES.get(precision, [-1]) and best[1] in (1, 2, 4, 8)
+            sub = ctx.query()["dev_block"]
+            _say(f"autotune {precision}: tile shape {best[0]}, row group {best[1]}, sub-block width {sub}")
+            assert best[0] in TILE_SHAPES[precision] and best[1] in (1, 2, 4, 8) and sub in (256, 512, 1024)
             b, _, _ = ctx.stream_block(XR)
             assert normwise(b, bo) < tol
         with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision=precision, x_dtype="i8",
                                  dev_block=1024) as ctx:
             assert ctx.autotune(XR, 1024) == best          # read back from the cache
+            assert ctx.query()["dev_block"] == sub
             b2, _, _ = ctx.stream_block(XR)
             assert torch_equal(b, b2)                      # same shape and schedule: same bits
     lines = cache.read_text().splitlines()
-    assert len(lines) == 3 and all("cfg=" in ln and "rgroup=" in ln for ln in lines)
+    assert len(lines) == 3 and all("cfg=" in ln and "rgroup=" in ln and "sub=" in ln for ln in lines)
 
 
 def test_many_traits():

@@ -59,3 +59,23 @@ def test_problem_noise_covariance():
     E = prob["Y"] - prob["XL"] @ prob["beta"]
     C = E @ E.T / E.shape[1]
     assert np.max(np.abs(C - prob["M"])) < 0.15
+
+
+def test_banded_problem_structure():
+    # Phi of local markers: symmetric, zero past the half-bandwidth, diagonal
+    # near 1, and M = sigma^2 (h^2 Phi + (1 - h^2) I) >= sigma^2 (1 - h^2) I
+    n, w, h2, s2 = 500, 40, 0.6, 1.3
+    pr = synth.banded_problem(n, 4, 9, w, h2=h2, sigma2=s2)
+    M = synth.band_to_dense(pr["M_band"])
+    assert np.array_equal(M, M.T)
+    i, j = np.nonzero(M)
+    assert np.max(np.abs(i - j)) == w
+    ev = np.linalg.eigvalsh(M)
+    assert ev[0] >= s2 * (1 - h2) * (1 - 1e-12)
+    phi_diag = (np.diag(M) - s2 * (1 - h2)) / (s2 * h2)
+    assert abs(phi_diag.mean() - 1.0) < 0.1
+    # the band storage convention: M_band[j, d] = M(j + d, j)
+    assert pr["M_band"][10, 3] == M[13, 10]
+    # y = X_L beta when noise is off
+    pr0 = synth.banded_problem(n, 4, 9, w, noise=False)
+    assert np.allclose(pr0["Y"], pr0["XL"] @ pr0["beta"])

@@ -31,6 +31,7 @@ def _outs(m, t, p, dev):
     ("fp32", "i8", 384, 700, 3, 1),
     ("int8", "i8", 256, 3000, 5, 2),
     ("bf16", "f64", 0, 900, 2, 1),
+    ("bf16x3", "f64", 640, 1000, 4, 1),
 ])
 def test_noalloc_equals_stream_block(precision, x_dtype, dev_block, n, p, t):
     import torch
