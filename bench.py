@@ -39,10 +39,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "SNP GLS solves/sec at n=50k,p=8 (mixed vs FP64); TRSM % of MFMA peak"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}   # dense matrix-core peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0,   # dense matrix-core peaks
+               "bf16x3": 2500.0}
+PROBE_KIND = {"bf16x3": "bf16"}   # instruction each leg runs, for the measured peak
 PROBE_ITERS = 100000   # runs of 8 instructions per wave in the measured-peak probe
 SLICES = 6             # int8 digits per entry of L^-1 in the int8 leg
-DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "int8": "i8"}
+DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "int8": "i8", "bf16x3": "bf16x3"}
 WORKLOADS = {
     "n50000_p8": dict(n=50_000, p=8, m=1_000_000, step=50_000, x_dtype="i8"),
     "n20000_p4": dict(n=20_000, p=4, m=500_000, step=5_000, x_dtype="f64"),
@@ -245,10 +247,13 @@ def stream_leg(name, prob_dev, blocks, steps, w, p, t=1):
     elapsed = time.perf_counter() - t0
     launches, kms, kcols = ctx.kernel_time()
     ctx.close()
-    ops_per_snp = float(n) * float(n) * (SLICES if name == "int8" else 1)
+    # products per SNP: int8 digits of L^-1; bfloat16 slice pairs (three with
+    # int8 dosages, six with float64 ones)
+    mult = SLICES if name == "int8" else (3 if w["x_dtype"] == "i8" else 6) if name == "bf16x3" else 1
+    ops_per_snp = float(n) * float(n) * mult
     achieved = ops_per_snp * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     peak = PEAK_TFLOPS[name]
-    measured_peak = binding.peak_probe(name, iters=PROBE_ITERS) / 1e12
+    measured_peak = binding.peak_probe(PROBE_KIND.get(name, name), iters=PROBE_ITERS) / 1e12
     unit = "TOP/s" if name == "int8" else "TFLOP/s"
     log(f"[{name}] init {init_s:.2f} s, {m} SNPs from pinned host in {elapsed:.3f} s = {m / elapsed:.1f} SNP/s; "
         f"product {launches} launches, {kms / max(launches, 1):.2f} ms avg -> {achieved:.2f} {unit} "
@@ -334,17 +339,25 @@ def compact_c4(seed, steps, step=16384):
                                         for s in range(steps + 1)]})
     torch.cuda.synchronize()
     legs, outs = {}, {}
-    for leg, precision, grouped in [("fp64_grouped", "fp64", True), ("fp64_sequential", "fp64", False),
-                                    ("int8_grouped", "int8", True)]:
+    # (leg, precision, grouped, graph, SNP positions per call); calls of 512
+    # positions run a 512-column sub-block context
+    for leg, precision, grouped, graph, width in [
+            ("fp64_grouped", "fp64", True, False, step), ("fp64_sequential", "fp64", False, False, step),
+            ("int8_grouped", "int8", True, False, step), ("fp32_grouped", "fp32", True, False, step),
+            ("fp32_grouped_graph_512", "fp32", True, True, 512), ("fp64_grouped_graph_512", "fp64", True, True, 512)]:
         t0 = time.perf_counter()
         ctxs = [binding.GwasContext(d["M"], d["XL"], d["Y"], precision=precision, x_dtype="i8",
-                                    slices=SLICES if precision == "int8" else 0) for d in data]
+                                    slices=SLICES if precision == "int8" else 0,
+                                    dev_block=width if width < step else 0) for d in data]
         torch.cuda.synchronize()
         init_s = time.perf_counter() - t0
 
         def one(s):
+            if width < step:    # the block's positions in calls of `width`
+                return [binding.stream_group(ctxs, [d["X"][s][q:q + width] for d in data], graph=graph)
+                        for q in range(0, step, width)]
             if grouped:
-                return binding.stream_group(ctxs, [d["X"][s] for d in data])
+                return binding.stream_group(ctxs, [d["X"][s] for d in data], graph=graph)
             return [c.stream_block(d["X"][s]) for c, d in zip(ctxs, data)]
         one(0)
         torch.cuda.synchronize()
@@ -354,11 +367,13 @@ def compact_c4(seed, steps, step=16384):
         el = time.perf_counter() - t0
         for c in ctxs:
             c.close()
-        outs[leg] = res
+        if width == step:
+            outs[leg] = res
         rate = steps * step * len(data) / el
         legs[leg] = {"cohort_snps_per_s": rate, "trait_solves_per_s": rate * t, "init_s": init_s,
-                     "ms_per_step": 1e3 * el / steps}
+                     "ms_per_step": 1e3 * el / steps, "snps_per_call": width, "graph": graph}
         log(f"[cohorts8_t64 {leg}] init {init_s:.2f} s; {rate:.1f} cohort-SNP/s ({rate * t:.3g} trait solves/s)")
+        del res
     ref = outs["fp64_grouped"]
     err = max(float(((outs["int8_grouped"][s][c][0] - ref[s][c][0]).reshape(step, -1).norm(dim=1)
                      / ref[s][c][0].reshape(step, -1).norm(dim=1)).max())
@@ -367,6 +382,8 @@ def compact_c4(seed, steps, step=16384):
                for s in range(steps) for c in range(len(data)))
     del data, outs, ref
     torch.cuda.empty_cache()
+    legs["fp32_512_vs_full_width"] = legs["fp32_grouped_graph_512"]["cohort_snps_per_s"] / \
+        legs["fp32_grouped"]["cohort_snps_per_s"]
     return {"legs": legs, "cohort_n": [c["n"] for c in spec], "t": t, "p": p, "snps_per_step": step,
             "steps": steps, "int8_normwise_err_vs_fp64": err, "grouped_equals_sequential": same,
             "inputs": "int8 dosages device-resident"}
@@ -412,6 +429,63 @@ def compact_c5(seed, m=100_000, step=50_000):
             "forward_s": res["forward_s"], "backward_s": res["backward_s"], "m": m, "n": n, "p": p,
             "dl_dh2": dh2, "dl_dy_norm": float(gy.norm()), "loss": "sum_i b_SNP^2 / var",
             "inputs": "float64 dosages device-resident"}
+
+
+def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
+    """Banded M (relatives grouped near the diagonal, Section 5.1) at
+    n = 50,000, p = 8: for each half-bandwidth w, int8 dosages in pinned host
+    memory queued as in the main legs.  The algorithmic work of a banded
+    forward substitution is 2 n w flops per SNP; the kernels run
+    n_pad (3 W + 128) with blocks of W = w rounded up to 256 rows."""
+    import torch
+    from paper_1304_2272_amd import binding, synth
+    dev = torch.device("cuda:0")
+    blocks = host_blocks(n, seed, step, steps, torch.int8, dev)
+    X = [torch.from_numpy(blocks.array[i]) for i in range(steps)]
+    out_b = PinnedHost((step * steps, 1, p), np.float64)
+    out_v = PinnedHost((step * steps,), np.float64)
+    out_i = PinnedHost((step * steps,), np.int32)
+    ob, ov, oi = (torch.from_numpy(x.array) for x in (out_b, out_v, out_i))
+    res = {}
+    for w in widths:
+        pr = synth.banded_problem(n, p, seed + w, w, device="cuda:0")
+        Mb = torch.from_numpy(pr["M_band"]).to(dev)
+        XL, Y = torch.from_numpy(pr["XL"]).to(dev), torch.from_numpy(pr["Y"]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = binding.GwasContext(Mb, XL, Y, x_dtype="i8", band=w)
+        torch.cuda.synchronize()
+        init_s = time.perf_counter() - t0
+        ctx.stream_block_async(X[0], (ob[:step], ov[:step], oi[:step]))     # warm-up
+        ctx.wait()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for s in range(steps):
+            sl = slice(s * step, (s + 1) * step)
+            ctx.stream_block_async(X[s], (ob[sl], ov[sl], oi[sl]))
+        ctx.wait()
+        el = time.perf_counter() - t0
+        launches, kms, kcols = ctx.kernel_time()
+        n_pad = ctx.query()["n_pad"]
+        ctx.close()
+        W = -(-w // 256) * 256
+        alg = 2.0 * n * w * kcols / (kms * 1e-3) / 1e12
+        exe = float(n_pad) * (3 * W + 128) * kcols / (kms * 1e-3) / 1e12
+        rate = steps * step / el
+        res[str(w)] = {"snps_per_s": rate, "init_s": init_s, "block_order": W, "n_pad": n_pad,
+                       "product_ms_per_sub_block": kms / max(launches, 1),
+                       "roofline": {"bound": "mfma", "achieved": alg, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                    "frac": alg / PEAK_TFLOPS["fp64"],
+                                    "work": "algorithmic 2 n w flops per SNP"},
+                       "executed_tflops": exe, "rank_flags": int((oi.numpy()[:steps * step] != 0).sum())}
+        log(f"[banded w={w}] init {init_s:.2f} s, {rate:.1f} SNP/s; product {alg:.2f} TFLOP/s algorithmic "
+            f"(2nw), {exe:.2f} executed ({exe / PEAK_TFLOPS['fp64']:.3f} of peak)")
+        del Mb, XL, Y, pr
+        torch.cuda.empty_cache()
+    for x in (out_b, out_v, out_i, blocks):
+        x.close()
+    return {"n": n, "p": p, "m_per_w": steps * step, "x_dtype": "int8", "precision": "fp64",
+            "inputs": "int8 dosages in pinned host memory, queued blocks", "by_half_bandwidth": res}
 
 
 def run_main(args):
@@ -477,6 +551,7 @@ def run_main(args):
         others["n20000_p4"] = compact_c2(args.seed + 2, args.c2_blocks)
         others["cohorts8_t64"] = compact_c4(args.seed + 3, args.c4_steps)
         others["n10000_p4_grad"] = compact_c5(args.seed + 4)
+        others["banded_n50000_p8"] = compact_banded(args.seed + 5, [int(x) for x in args.band_widths.split(",") if x])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -527,7 +602,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1, help="untimed blocks per leg (one)")
     ap.add_argument("--workload", default="n50000_p8", choices=sorted(WORKLOADS))
-    ap.add_argument("--legs", default="fp64,fp32,int8,bf16")
+    ap.add_argument("--legs", default="fp64,fp32,int8,bf16x3,bf16")
     ap.add_argument("--host-blocks", type=int, default=20, help="distinct pinned host blocks (cycled)")
     ap.add_argument("--step-snps", type=int, default=0)
     ap.add_argument("--seed", type=int, default=1306)
@@ -535,6 +610,7 @@ def main():
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--c2-blocks", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=2)
+    ap.add_argument("--band-widths", default="256,1024,4096", help="half-bandwidths of the banded-M leg")
     ap.add_argument("--cpu-n", type=int, default=6144)
     ap.add_argument("--cpu-snps", type=int, default=4096)
     ap.add_argument("--copy-probe-mib", type=int, default=0,

@@ -1,8 +1,8 @@
 """Summaries of rocprofv3 output for ``profiles/`` (measurement tooling; the
 library does not use it).
 
-``trace``    Markdown table of a ``--kernel-trace --stats`` run (rocpd
-             database converted with rocpd2summary, or its stats CSV).
+``trace``    Markdown table of a ``--kernel-trace --stats`` run (its
+             kernel_stats.csv, or a rocpd2summary markdown table).
 ``traffic``  HBM bytes of the triangular product from two ``--pmc`` runs
              (FETCH_SIZE, then WRITE_SIZE, both in KiB per dispatch), each
              scaled by what the same counter reads for a plain element-wise
@@ -100,20 +100,29 @@ def traffic(args):
     print(json.dumps(rec, indent=1))
 
 
+def _short(name):
+    for a, b in (("(gwas::TrmmArgs)", ""), ("(gwas::SolveArgs)", ""), ("(gwas::BandArgs)", ""),
+                 ("(anonymous namespace)::", ""), ("bool _Accum", "__bf16")):
+        name = name.replace(a, b)
+    return name if len(name) <= 100 else name[:97] + "..."
+
+
 def trace(args):
-    rows = [l for l in open(args.stats) if l.startswith("|")]
     data = []
-    for l in rows[2:]:
-        c = [x.strip() for x in l.strip("|\n").split("|")]
-        name = c[0].replace("(gwas::TrmmArgs)", "").replace("(gwas::SolveArgs)", "")
-        name = name.replace("(anonymous namespace)::", "").replace("bool _Accum", "__bf16")
-        if len(name) > 100:
-            name = name[:97] + "..."
-        data.append((name, int(c[1]), float(c[2]), float(c[3]), float(c[4]), float(c[5]), float(c[6])))
+    if args.stats.endswith(".csv"):
+        # rocprofv3 --stats --output-format csv: <prefix>_kernel_stats.csv
+        for r in csv.DictReader(open(args.stats)):
+            data.append((_short(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                         float(r["Percentage"]), float(r["MinNs"]), float(r["MaxNs"])))
+        data.sort(key=lambda d: -d[2])
+    else:
+        rows = [l for l in open(args.stats) if l.startswith("|")]
+        for l in rows[2:]:
+            c = [x.strip() for x in l.strip("|\n").split("|")]
+            data.append((_short(c[0]), int(c[1]), float(c[2]), float(c[3]), float(c[4]), float(c[5]), float(c[6])))
     with open(args.out, "w") as f:
         f.write(f"# {args.title}\n\nCommand (repository root, one MI355X):\n\n```\n{args.command}\n```\n\n")
-        f.write("`rocprofv3 --kernel-trace --stats`, converted with `rocpd2summary -f md`; times in ms, "
-                "kernels by total time.\n\n")
+        f.write("`rocprofv3 --kernel-trace --stats`; times in ms, kernels by total time.\n\n")
         f.write("| kernel | calls | total ms | avg ms | % | min ms | max ms |\n|---|---:|---:|---:|---:|---:|---:|\n")
         for d in data[:args.top]:
             f.write(f"| `{d[0]}` | {d[1]} | {d[2] / 1e6:.1f} | {d[3] / 1e6:.3f} | {d[4]:.1f} | "
@@ -138,7 +147,8 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--out", required=True)
     r = sub.add_parser("trace")
-    r.add_argument("--stats", required=True, help="kernel stats table from rocpd2summary -f md")
+    r.add_argument("--stats", required=True,
+                   help="kernel stats: rocprofv3's <prefix>_kernel_stats.csv, or a rocpd2summary -f md table")
     r.add_argument("--title", required=True)
     r.add_argument("--command", required=True)
     r.add_argument("--top", type=int, default=14)
