@@ -255,9 +255,10 @@ int gwas_stream_wait(gwas_ctx* ctx);
  * chunk totals and, in the reduced modes, the cross products x^T W) lives in
  * one static device buffer of 256 MiB that every GPU the library runs on
  * holds until the process ends; sub-blocks are as wide as fits it (at most
- * dev_block columns).  A context whose scratch for 128 SNP columns exceeds
- * 256 MiB (large n with many traits) gets GWAS_E_INVALID, with the sizes in
- * gwas_last_error.  Results equal gwas_stream_block's bit for bit.  All
+ * dev_block columns).  Every entry of it a call reads, that call writes
+ * first, so nothing needs clearing between calls.  A context whose scratch
+ * for 128 SNP columns exceeds 256 MiB (large n with many traits) gets
+ * GWAS_E_INVALID, with the sizes in gwas_last_error.  Results equal gwas_stream_block's bit for bit.  All
  * contexts on one device share the buffer: calls that overlap in time on
  * one device (other streams, other contexts, other host threads) race and
  * must be ordered by the caller.  Kernel timing does not cover these calls.
