@@ -84,12 +84,21 @@ extern "C" {
  * float64-grade results from int8 dosages use GWAS_INT8_SLICED.
  */
 #define GWAS_INT8_SLICED   3   /* L^-1 held as `slices` int8 digits per entry
-                                  with a power-of-two scale per row; the
-                                  product with int8 dosages runs on int8
-                                  matrix cores with exact int32 sums and one
-                                  float64 combination; cross products and
-                                  the p x p solve as in GWAS_FP32_REFINE.
-                                  Needs x_dtype = GWAS_X_I8.                */
+                                  with a power-of-two scale per row, digits
+                                  in pairs (radix 127 inside a pair, 128
+                                  between pairs); the product with int8
+                                  dosages runs on int8 matrix cores with
+                                  exact int32 sums and one float64
+                                  combination; cross products and the p x p
+                                  solve as in GWAS_FP32_REFINE.  Needs
+                                  x_dtype = GWAS_X_I8 and n <= 261,888.
+                                  The default tile shape adds both digits of
+                                  a pair into one sum against centred
+                                  dosages x - 1, which needs dosages 0, 1 or
+                                  2: a SNP with any other value gets NaN in
+                                  b and var_snp (tile shape 0, through
+                                  GWAS_TRMM_CFG or gwas_autotune, takes any
+                                  int8 value).                            */
 
 #define GWAS_BF16X3_REFINE 4  /* L^-1 held as three bfloat16 slices per
                                   entry (each rounds what the ones before it
@@ -313,8 +322,10 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * padded n, precision, dosage type and width is reused and new results are
  * appended.  *best_cfg (may be NULL) receives the chosen shape (for
  * GWAS_INT8_SLICED: 0 stages its operands through registers, 1 and 2 load
- * them straight into LDS, 2 with a wider tile); *best_rgroup (may be NULL)
- * the row group.
+ * them straight into LDS, 2 with a wider tile; 3 to 5 add the two digits of
+ * a pair into one sum against centred dosages, 3 staging through registers,
+ * 4 and 5 loading straight into three or two LDS buffers, 5 the default);
+ * *best_rgroup (may be NULL) the row group.
  * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged
  * up to float64 rounding order.  For the float32 and bfloat16 products a
  * shape also decides how their sums are kept: the 256 x 256 shape (6, the
@@ -323,9 +334,9 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * modes (16 u kappa_i on the SNP coefficient and var) either way.
  *
  * The environment variable GWAS_TRMM_CFG (read by gwas_init) overrides the
- * default shape with one the autotuner would try (0..6; ignored when the
- * shape does not apply to the precision and dosage type): a measurement
- * and test aid.
+ * default shape with one the autotuner would try (0..6, 0..5 for
+ * GWAS_INT8_SLICED; ignored when the shape does not apply to the precision
+ * and dosage type): a measurement and test aid.
  */
 int gwas_autotune(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_t cols, int32_t* best_cfg,
                   int32_t* best_rgroup);

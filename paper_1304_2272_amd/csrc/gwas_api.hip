@@ -39,7 +39,7 @@ struct Layout {
     size_t off_bandcopy;
     size_t off_Ub, off_Gt, off_Ab, off_Eb, off_Z[2];
     int p, t, q1, Qc, precision, x_dtype, slices;
-    size_t off_L, off_U, off_Ulow, off_rscale, off_XY, off_C, off_W, off_S, off_consts, off_flags,
+    size_t off_L, off_U, off_Ulow, off_rscale, off_rsum, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
     size_t off_xbuf[2], off_part, off_red, off_xw, off_xwpart, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
@@ -83,6 +83,9 @@ bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t pre
     if (precision < GWAS_FP64 || precision > GWAS_BF16X3_REFINE) return false;
     if (x_dtype != GWAS_X_F64 && x_dtype != GWAS_X_I8) return false;
     if (precision == GWAS_INT8_SLICED && x_dtype != GWAS_X_I8) return false;
+    // exact int32 sums of the paired digits (|127 A_hi + A_lo| <= 8,192 per
+    // element) need n_pad < 2^18
+    if (precision == GWAS_INT8_SLICED && n > ((int64_t)1 << 18) - NPAD_ALIGN) return false;
     return true;
 }
 
@@ -137,6 +140,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
                : (precision == GWAS_BF16X3_REFINE) ? take(nn * 2 * 3)
                : (precision == GWAS_INT8_SLICED) ? take(nn * (size_t)slices) : 0;
     L.off_rscale = (precision == GWAS_INT8_SLICED) ? take((size_t)L.n_pad * 8) : 0;
+    L.off_rsum = (precision == GWAS_INT8_SLICED) ? take((size_t)L.n_pad * SLICE_PAIRS_MAX * 4) : 0;
     L.off_XY = take((size_t)L.n_pad * L.Qc * 8);
     L.off_C = take((size_t)L.n_pad * L.Qc * 8);
     L.off_W = (precision != GWAS_FP64) ? take((size_t)L.n_pad * L.Qc * 8) : 0;
@@ -150,7 +154,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.sched_len = band > 0 ? 1 : (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
                                             trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0));
     // every admissible shape with the model's and every candidate row group
-    for (int c = 0; c < trmm_num_cfgs() && band == 0; ++c) {
+    for (int c = 0; c < trmm_cfg_limit() && band == 0; ++c) {
         if (!trmm_cfg_valid(at, xt, c)) continue;
         for (int r : {0, 1, 2, 4, 8}) {
             const TrmmShape sh = trmm_geom(at, xt, c, slices, r);
@@ -172,7 +176,7 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
         L.na_cols = band > 0 ? 0 : lo * TILE_N;   // the banded path has no schedule-driven product
         L.na_sched_len = 0;
         if (L.na_cols > 0)
-            for (int c = 0; c < trmm_num_cfgs(); ++c) {
+            for (int c = 0; c < trmm_cfg_limit(); ++c) {
                 if (!trmm_cfg_valid(at, xt, c)) continue;
                 for (int r : {0, 1, 2, 4, 8})
                     L.na_sched_len = std::max(L.na_sched_len, (size_t)trmm_schedule_len(
@@ -244,6 +248,7 @@ struct gwas_ctx {
            *consts = nullptr;
     void* Ulow = nullptr;
     double* rscale = nullptr;
+    int* rsum = nullptr;
     double *Ub = nullptr, *Gt = nullptr, *Ab = nullptr, *Eb = nullptr, *Zb[2] = {nullptr, nullptr};   // banded M
     TrmmShape shape{};
     int* flags = nullptr;
@@ -671,6 +676,7 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.cfg = c->cfg;
     ta.slices = Y.slices;
     ta.rscale = c->rscale;
+    ta.rsum = c->rsum;
     ta.Ut = (c->at == A_F64) ? (const void*)c->U : c->Ulow;
     ta.ldu = (Y.precision == GWAS_BF16X3_REFINE) ? 3 * Y.n_pad : Y.ld;   // slices one after another
     ta.n_pad = Y.n_pad;
@@ -737,9 +743,12 @@ hipError_t finish_sub(const gwas_ctx* c, const SubScratch& sc, const void* xptr,
                       double* bo, int64_t ldbo, double* vo, int* io, hipStream_t s) {
     const Layout& Y = c->lay;
     if (Y.precision != GWAS_FP64) {
+        // the paired-digit int8 product is exact only for dosages 0, 1, 2:
+        // other values turn the SNP's results into NaN
+        const bool check012 = Y.precision == GWAS_INT8_SLICED && trmm_sliced_paired(c->cfg);
         hipError_t e = snp_cross_w((Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64, xptr, xld, Y.n, cols, c->W,
                                    Y.n_pad, Y.Qc, sc.xw, sc.ld, sc.xwpart,
-                                   (int64_t)xw_splits(Y.n) * Y.Qc * sc.ld, s);
+                                   (int64_t)xw_splits(Y.n) * Y.Qc * sc.ld, s, check012);
         if (e != hipSuccess) return e;
     }
     hipError_t e = partial_chunks(sc.part, sc.ld, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
@@ -857,7 +866,7 @@ int init_body(gwas_ctx* c, const gwas_desc* d) {
         else if (Y.precision == GWAS_BF16_REFINE)
             HIPCHK(c, convert_bf16(c->U, (__bf16*)c->Ulow, ld, n_pad, n_pad, s));
         else
-            HIPCHK(c, slice_rows(c->U, ld, n_pad, Y.slices, (int8_t*)c->Ulow, n_pad, c->rscale, s));
+            HIPCHK(c, slice_rows(c->U, ld, n_pad, Y.n, Y.slices, (int8_t*)c->Ulow, n_pad, c->rscale, c->rsum, s));
     }
     if (Y.band == 0) {
         c->sub = Y.dev_block;
@@ -954,6 +963,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->U = (double*)(w + Y.off_U);
     c->Ulow = Y.off_Ulow ? (void*)(w + Y.off_Ulow) : nullptr;
     c->rscale = Y.off_rscale ? (double*)(w + Y.off_rscale) : nullptr;
+    c->rsum = Y.off_rsum ? (int*)(w + Y.off_rsum) : nullptr;
     c->XY = (double*)(w + Y.off_XY);
     c->C = (double*)(w + Y.off_C);
     c->W = Y.off_W ? (double*)(w + Y.off_W) : nullptr;
@@ -1575,9 +1585,9 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
         float best_ms = 0.f;
-        // every admissible tile shape (the int8-slice product has one) with
-        // every candidate row group of the schedule
-        for (int cfg = 0; cfg < trmm_num_cfgs(); ++cfg) {
+        // every admissible tile shape with every candidate row group of the
+        // schedule
+        for (int cfg = 0; cfg < trmm_cfg_limit(); ++cfg) {
             if (!trmm_cfg_valid(c->at, xt, cfg)) continue;
             for (int rg : RGROUP_CANDIDATES) {
                 c->gen += 1;

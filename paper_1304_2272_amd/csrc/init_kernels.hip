@@ -299,12 +299,18 @@ __global__ void slice_bf16_kernel(const double* __restrict__ U, int64_t ld, int6
 }
 
 // One workgroup per row of L^-1 (grid-stride): block max, power-of-two
-// scale, then exact 7-bit digits (every step is a multiplication by a power
-// of two or the subtraction of a nearby integer, so no rounding occurs).
+// scale, then int8 digits in pairs: each digit rounds what the ones before
+// it leave, scaled by 127 inside a pair and by 128 from one pair to the
+// next (a subtraction of a nearby integer is exact; the scaling by 127
+// rounds at 2^-53 of the digit, far below the last digit's half unit).
+// The row sums of the paired digits over k < n are exact int32 sums
+// (|127 A_hi + A_lo| <= 8,192, n < 2^18).
 __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ U, int64_t ld,
-                                                         int64_t n_pad, int S, int8_t* __restrict__ A,
-                                                         int64_t lda, double* __restrict__ rscale) {
+                                                         int64_t n_pad, int64_t n, int S,
+                                                         int8_t* __restrict__ A, int64_t lda,
+                                                         double* __restrict__ rscale, int* __restrict__ rsum) {
     __shared__ double red[256];
+    __shared__ int ired[SLICE_PAIRS_MAX][256];
     for (int64_t r = blockIdx.x; r < n_pad; r += gridDim.x) {
         const double* col = U + r * ld;      // L^-1(r, k) = U(k, r), zero for k > r
         double m = 0.0;
@@ -322,14 +328,25 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
         const double sc = ldexp(1.0, e);
         if (threadIdx.x == 0) rscale[r] = sc;
         const int64_t base = (r / 16) * 16 * S + (r % 16);
+        int dsum[SLICE_PAIRS_MAX] = {0, 0, 0};
         for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) {
-            double t = (k <= r) ? ldexp(col[k], 6 - e) : 0.0;   // (L^-1(r,k)/sc) * 2^6, |t| <= 64
+            double t = (k <= r) ? ldexp(col[k], 6 - e) : 0.0;   // (L^-1(r,k)/sc) * 2^6, |t| < 64
             for (int sl = 0; sl < S; ++sl) {
                 const double q = rint(t);
                 A[(base + sl * 16) * lda + k] = (int8_t)q;
-                t = (t - q) * 128.0;
+                if (k < n && sl / 2 < SLICE_PAIRS_MAX) dsum[sl / 2] += (sl & 1) ? (int)q : 127 * (int)q;
+                t = (t - q) * ((sl & 1) ? 128.0 : 127.0);
             }
         }
+        for (int p = 0; p < SLICE_PAIRS_MAX; ++p) ired[p][threadIdx.x] = dsum[p];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int p = 0; p < SLICE_PAIRS_MAX; ++p) ired[p][threadIdx.x] += ired[p][threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x < (S + 1) / 2) rsum[threadIdx.x * n_pad + r] = ired[threadIdx.x][0];
+        __syncthreads();
     }
 }
 
@@ -445,12 +462,13 @@ hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, i
     return hipGetLastError();
 }
 
-hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int S, int8_t* A, int64_t lda,
-                      double* rscale, hipStream_t s) {
-    if (!U || !A || !rscale || S < 1 || S > 8 || ld < n_pad || lda < n_pad || n_pad % 16)
+hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int64_t n, int S, int8_t* A, int64_t lda,
+                      double* rscale, int* rsum, hipStream_t s) {
+    if (!U || !A || !rscale || !rsum || S < 1 || S > 2 * SLICE_PAIRS_MAX || ld < n_pad || lda < n_pad ||
+        n_pad % 16 || n < 1 || n > n_pad || n_pad >= (1 << 18))
         return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<int64_t>(n_pad, 16384);
-    hipLaunchKernelGGL(slice_rows_kernel, dim3(grid), dim3(256), 0, s, U, ld, n_pad, S, A, lda, rscale);
+    hipLaunchKernelGGL(slice_rows_kernel, dim3(grid), dim3(256), 0, s, U, ld, n_pad, n, S, A, lda, rscale, rsum);
     return hipGetLastError();
 }
 

@@ -101,6 +101,8 @@ struct TrmmArgs {
                                 // bfloat16-slice product (row r holds its slices one after
                                 // another, n_pad elements each), else 0
     const double* rscale;       // A_I8S: power-of-two scale of each row of L^-1
+    const int* rsum;            // A_I8S: rsum[p * n_pad + r] = sum over k < n of the
+                                // paired digits 127 A_2p(r, k) + A_2p+1(r, k)
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const double* C; int64_t ldc; int Qc;
@@ -118,6 +120,7 @@ hipError_t trmm_sliced_launch(const TrmmArgs& a, hipStream_t s);
 hipError_t trmm_check(const TrmmArgs& a, bool check_sched);
 
 int trmm_num_cfgs();
+int trmm_cfg_limit();              // one past the largest shape index of any product
 bool trmm_shape_sum32(int cfg);   // shape keeps float32 sums only (reduced precision)
 TrmmShape trmm_shape(int cfg);
 bool trmm_cfg_valid(int at, int xt, int cfg);
@@ -127,6 +130,9 @@ constexpr int MIN_PART_ROWS = 32;   // smallest part_rows of the floating-point 
 int trmm_sliced_cfgs();
 TrmmShape trmm_sliced_shape(int cfg = 0);
 bool trmm_sliced_direct(int cfg);    // the shape loads its operands straight into LDS
+bool trmm_sliced_paired(int cfg);    // the shape pairs digits against centred dosages
+                                     // (dosages must be 0, 1 or 2)
+bool trmm_sliced_two_per_cu(int cfg); // the shape runs two workgroups per CU
 // shape of the kernel that runs (at, xt, cfg, slices), with its schedule
 // grouping: rgroup row tiles per group, or the traffic model's choice for 0
 TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup = 0);
@@ -138,11 +144,15 @@ constexpr int RGROUP_CANDIDATES[] = {1, 2, 4, 8};   // what the autotuner tries
 hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, int64_t ldo, hipStream_t s);
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
-// and S int8 slices A_s(r,k) with L^-1(r,k)/rscale[r] = sum_s A_s(r,k) 2^(-6-7s)
-// up to 2^(-6-7S) / 2, written to sliced row (r/16)*16*S + s*16 + r%16 of A
-// (lda bytes per row).
-hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int S, int8_t* A,
-                      int64_t lda, double* rscale, hipStream_t s);
+// and S int8 digits A_s(r,k) in [-64, 64], written to sliced row
+// (r/16)*16*S + s*16 + r%16 of A (lda bytes per row).  Digits come in pairs
+// (hi A_2p, lo A_2p+1) with a radix of 127 inside a pair and 128 between
+// pairs:  L^-1(r,k)/rscale[r] = sum_p D_p(r,k) w_p up to half a unit of the
+// last digit, D_p = 127 A_2p + A_2p+1 (A_S = 0 for odd S) and
+// w_p = 2^(-6-7p) / 127^(2p+1).  rsum[p * n_pad + r] = sum_{k < n} D_p(r,k).
+constexpr int SLICE_PAIRS_MAX = 3;
+hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int64_t n, int S, int8_t* A,
+                      int64_t lda, double* rscale, int* rsum, hipStream_t s);
 
 // Host side: tile schedule for n_pad rows and `cols` SNP columns with the
 // tiles of `sh`.  Returns the number of workgroups and fills `out` (2 ints
@@ -156,10 +166,12 @@ int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, const TrmmShape& sh);
 // ldw >= n rounded up to 16 rows, zero past n.  With part (room for
 // part_cap doubles, at least xw_splits(n) * Qc * cols) K is split in chunks
 // fixed by n and the partial sums are added in order; without it, one split.
+// check012 (int8 dosages): a SNP with a dosage outside {0, 1, 2} gets NaN.
 int xw_splits(int64_t n);
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw,
-                       int64_t ldxw, double* part, int64_t part_cap, hipStream_t s);
+                       int64_t ldxw, double* part, int64_t part_cap, hipStream_t s,
+                       bool check012 = false);
 
 // Reverse mode through the per-SNP solves (one trait).  For SNP j, with the
 // Cholesky factor of S_j from R = chol(S_TL), S_BL = x^T W_L and s = 1/var,

@@ -39,7 +39,8 @@ template <typename XT, int WQ>
 __global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
                                                            int64_t cols, const double* __restrict__ W,
                                                            int64_t ldw, int Qc, double* __restrict__ out,
-                                                           int64_t ldo, int64_t split_stride, int64_t klen) {
+                                                           int64_t ldo, int64_t split_stride, int64_t klen,
+                                                           int check012) {
     constexpr int NT = 64 * XW_WAVES;
     constexpr int TC = 64 * XW_WAVES;               // SNPs per workgroup, one per thread
     constexpr int TQ = 16 * WQ;
@@ -61,6 +62,9 @@ __global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict_
 
     u4_t rx[CPC];
     double rw[(TQ * XW_BK / 2 + NT - 1) / NT][2];
+    // check012: int8 dosages outside {0, 1, 2} in this thread's SNP (bytes
+    // with a bit above bit 1 set, or both low bits)
+    uint32_t bad = 0;
     auto load = [&](int st) {
         const int64_t k0 = kbeg + (int64_t)st * XW_BK;
         const int64_t col = c0 + tid;
@@ -78,6 +82,12 @@ __global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict_
                 }
             }
             rx[c] = v;
+            if constexpr (sizeof(XT) == 1) {
+                if (check012) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) bad |= (v[w] & 0xfcfcfcfcu) | (v[w] & (v[w] >> 1) & 0x01010101u);
+                }
+            }
         }
         // W rows k0..k0+15 lie below n_pad = ldw, zero past n
 #pragma unroll
@@ -145,6 +155,13 @@ __global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict_
         if (more) store(buf ^ 1);
         __syncthreads();
     }
+    // a SNP with a dosage outside {0, 1, 2} gets NaN cross products (the
+    // centred int8 product cannot represent it)
+    __shared__ int badS[TC];
+    if (check012) {
+        badS[tid] = bad != 0;
+        __syncthreads();
+    }
     // element v of a lane: SNP (A row) lane/16 + 4v of the block, column of
     // W (B column) lane%16
     double* o = out + (int64_t)split * split_stride;
@@ -155,8 +172,10 @@ __global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict_
             const int q = q0 + qb * 16 + li;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t col = c0 + wave * 64 + cb * 16 + lg + 4 * v;
-                if (q < Qc && col < cols) o[(int64_t)q * ldo + col] = acc[cb][qb][v];
+                const int lc = wave * 64 + cb * 16 + lg + 4 * v;
+                const int64_t col = c0 + lc;
+                const double val = (check012 && badS[lc]) ? __builtin_nan("") : acc[cb][qb][v];
+                if (q < Qc && col < cols) o[(int64_t)q * ldo + col] = val;
             }
         }
 }
@@ -447,7 +466,7 @@ int xw_splits(int64_t n) { return (int)std::max<int64_t>(1, (n + XW_KSPLIT - 1) 
 
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw, int64_t ldxw,
-                       double* part, int64_t part_cap, hipStream_t s) {
+                       double* part, int64_t part_cap, hipStream_t s, bool check012) {
     if (cols <= 0) return hipSuccess;
     if (!X || !W || !xw || n < 1 || ldx < n || ldw < (n + XW_BK - 1) / XW_BK * XW_BK || ldxw < cols || Qc < 1)
         return hipErrorInvalidValue;
@@ -466,7 +485,7 @@ hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t co
     const int64_t klen = splits > 1 ? (int64_t)XW_KSPLIT : (n + XW_BK - 1) / XW_BK * XW_BK;
 #define GWAS_XW(T, WQ)                                                                                 \
     hipLaunchKernelGGL((xw_kernel<T, WQ>), grid, dim3(64 * XW_WAVES), 0, s, (const T*)X, ldx, n, cols, \
-                       W, ldw, Qc, out, ldo, stride, klen)
+                       W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8))
 #define GWAS_XW_T(T)                        \
     switch (wq) {                           \
         case 1: GWAS_XW(T, 1); break;       \

@@ -625,6 +625,7 @@ hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
 }  // namespace
 
 int trmm_num_cfgs() { return 7; }
+int trmm_cfg_limit() { return std::max(trmm_num_cfgs(), trmm_sliced_cfgs()); }
 
 bool trmm_shape_sum32(int cfg) { return cfg == 6; }
 
@@ -665,7 +666,11 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 // 128 x 256 tile and the reduced-precision products take the 128 x 128
 // tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
-    if (at == A_I8S) return 0;
+    // int8 slices: the paired-digit shape with four waves of 16 x 128, two
+    // LDS buffers and two workgroups per CU (0.50 of int8 peak at n = 50,000
+    // against 0.42 for the unpaired 32 x 256 tile, 0.49 for the paired
+    // 64 x 256 tile with three buffers)
+    if (at == A_I8S) return 5;
     if (at == A_F64) return xt == X_I8 ? 2 : 3;
     if (xt == X_I8) return 6;
     return 1;
@@ -675,7 +680,7 @@ TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup) {
     TrmmShape sh = (at == A_I8S) ? trmm_sliced_shape(cfg) : trmm_shape(cfg);
     if (sh.tm == 0) return sh;
     // workgroups per CU: the 256-thread shape is sized for two
-    const int per_cu = (at != A_I8S && cfg == 0) ? 2 : 1;
+    const int per_cu = (at != A_I8S && cfg == 0) || (at == A_I8S && trmm_sliced_two_per_cu(cfg)) ? 2 : 1;
     sh.inflight = 32 * per_cu;
     const int64_t asz = at == A_F64 ? 8 : at == A_F32 ? 4 : at == A_BF16 ? 2 : 1;
     const int64_t arows = at == A_I8S ? (int64_t)sh.tm * slices : sh.tm;
@@ -710,7 +715,8 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.at == A_I8S) {
         // the int8-slice product forms z^T z only (its mode takes the cross
         // products from x^T W)
-        if (!a.rscale || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6 || a.with_cross ||
+        if (!a.rscale || !a.rsum || a.xt != X_I8 || (a.ldu % 16) || a.slices < 4 || a.slices > 6 || a.with_cross ||
+            a.n_pad >= (1 << 18) ||
             !trmm_cfg_valid(a.at, a.xt, a.cfg))
             return hipErrorInvalidValue;
         // 32-bit buffer offsets of the shapes that load straight into LDS

@@ -51,6 +51,11 @@ def test_workspace_bytes(lib):
                  (100, 4, 0, 0, 0, 0), (100, 4, 1, -1, 0, 0), (100, 4, 1, 0, 7, 0),
                  (100, 4, 1, 0, 0, 5), (100, 4, 257, 0, 0, 0)]:
         assert lib.gwas_workspace_bytes(*args) == 0, args
+    # int8 slices: the paired digits' exact int32 sums need n_pad < 2^18
+    # (|127 A_hi + A_lo| <= 8,192 per element)
+    assert lib.gwas_workspace_bytes(2 ** 18 - 256, 4, 1, 0, 3, 1) > 0
+    assert lib.gwas_workspace_bytes(2 ** 18 - 255, 4, 1, 0, 3, 1) == 0
+    assert lib.gwas_workspace_bytes(2 ** 18, 4, 1, 0, 0, 1) > 0          # float64 has no such limit
 
 
 def _desc(n=16, p=3, t=1, **kw):
