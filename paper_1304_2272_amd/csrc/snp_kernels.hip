@@ -22,7 +22,8 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
 
 // x_j^T W[:, q] on the float64 matrix cores: C (SNPs x Qc) = X^T W with K = n.
-// A workgroup of 4 waves takes 256 SNPs (a wave 64, as 4 blocks of 16) and
+// A workgroup of WV waves (4, or 1 for narrow blocks, which then get four
+// times the workgroups) takes 64 WV SNPs (a wave 64, as 4 blocks of 16) and
 // WQ blocks of 16 columns of W, over one K split of klen rows (XW_KSPLIT,
 // or all of n in a single split).  The splits depend on n alone, so the sums
 // of a SNP do not depend on the block it comes in; with several splits each
@@ -32,17 +33,16 @@ typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
 // multiple of 16) and cleared past n in registers.
 constexpr int XW_BK = 16;
 constexpr int XW_KSPLIT = 2048;
-constexpr int XW_WAVES = 4;
 constexpr int XW_QMAX = 80;         // columns of W per workgroup (5 blocks)
 
-template <typename XT, int WQ>
-__global__ __launch_bounds__(64 * XW_WAVES) void xw_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
+template <typename XT, int WQ, int WV>
+__global__ __launch_bounds__(64 * WV) void xw_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
                                                            int64_t cols, const double* __restrict__ W,
                                                            int64_t ldw, int Qc, double* __restrict__ out,
                                                            int64_t ldo, int64_t split_stride, int64_t klen,
                                                            int check012) {
-    constexpr int NT = 64 * XW_WAVES;
-    constexpr int TC = 64 * XW_WAVES;               // SNPs per workgroup, one per thread
+    constexpr int NT = 64 * WV;
+    constexpr int TC = 64 * WV;                     // SNPs per workgroup, one per thread
     constexpr int TQ = 16 * WQ;
     constexpr int XLD = sizeof(XT) == 1 ? XW_BK : XW_BK + 1;   // LDS row of a SNP (elements)
     constexpr int WLD = XW_BK + 1;                  // LDS row of a column of W (doubles)
@@ -477,14 +477,20 @@ hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t co
     if (splits > 1 && part_cap < (int64_t)splits * Qc * cols) return hipErrorInvalidValue;
     const int qchunks = (Qc + XW_QMAX - 1) / XW_QMAX;
     const int wq = qchunks > 1 ? XW_QMAX / 16 : (Qc + 15) / 16;
-    const dim3 grid((unsigned)((cols + 64 * XW_WAVES - 1) / (64 * XW_WAVES)), (unsigned)splits, (unsigned)qchunks);
+    // one-wave workgroups when four-wave ones would not fill the chip; every
+    // sum runs over the same K steps either way
+    const bool narrow = (cols + 255) / 256 * splits * qchunks < 1024;
+    const int wv = narrow ? 1 : 4;
+    const dim3 grid((unsigned)((cols + 64 * wv - 1) / (64 * wv)), (unsigned)splits, (unsigned)qchunks);
     double* out = splits > 1 ? part : xw;
     const int64_t ldo = splits > 1 ? cols : ldxw;
     const int64_t stride = splits > 1 ? (int64_t)Qc * cols : 0;
     // rows of X per split: a multiple of XW_BK, so only the last split is ragged
     const int64_t klen = splits > 1 ? (int64_t)XW_KSPLIT : (n + XW_BK - 1) / XW_BK * XW_BK;
 #define GWAS_XW(T, WQ)                                                                                 \
-    hipLaunchKernelGGL((xw_kernel<T, WQ>), grid, dim3(64 * XW_WAVES), 0, s, (const T*)X, ldx, n, cols, \
+    if (narrow) hipLaunchKernelGGL((xw_kernel<T, WQ, 1>), grid, dim3(64), 0, s, (const T*)X, ldx, n, cols, \
+                                   W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8)); \
+    else hipLaunchKernelGGL((xw_kernel<T, WQ, 4>), grid, dim3(256), 0, s, (const T*)X, ldx, n, cols, \
                        W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8))
 #define GWAS_XW_T(T)                        \
     switch (wq) {                           \
