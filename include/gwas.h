@@ -294,11 +294,11 @@ int gwas_stream_block_noalloc(gwas_ctx* ctx, const void* XR, int64_t ldx, int64_
  *                entries may be NULL)
  *   flags        GWAS_GROUP_GRAPH: full-width sub-blocks replay one HIP
  *                graph of the grouped product, cross products and solves,
- *                captured at first use.  With GWAS_FP64 the product reads
- *                device dosages in place (the graph's argument array is
- *                updated before a replay when the pointers change); other
- *                precisions and host dosages are copied into fixed device
- *                buffers; results are copied out of fixed buffers
+ *                captured at first use.  The product and the cross
+ *                products read device dosages in place (the graph's
+ *                argument array is updated before a replay when the
+ *                pointers change); host dosages are copied into fixed
+ *                device buffers; results are copied out of fixed buffers
  *
  * All work runs on the first context's compute stream; the call returns
  * when every output is written.  Errors: GWAS_E_INVALID (incompatible or

@@ -740,7 +740,8 @@ SolveArgs solve_args_for(const gwas_ctx* c, const SubScratch& sc, int64_t cols, 
 
 // Cross products x^T W (reduced modes) and the per-SNP solves of one sub-block.
 hipError_t finish_sub(const gwas_ctx* c, const SubScratch& sc, const void* xptr, int64_t xld, int64_t cols,
-                      double* bo, int64_t ldbo, double* vo, int* io, hipStream_t s) {
+                      double* bo, int64_t ldbo, double* vo, int* io, hipStream_t s,
+                      const TrmmArgs* xargs = nullptr) {
     const Layout& Y = c->lay;
     if (Y.precision != GWAS_FP64) {
         // the paired-digit int8 product is exact only for dosages 0, 1, 2:
@@ -748,7 +749,7 @@ hipError_t finish_sub(const gwas_ctx* c, const SubScratch& sc, const void* xptr,
         const bool check012 = Y.precision == GWAS_INT8_SLICED && trmm_sliced_paired(c->cfg);
         hipError_t e = snp_cross_w((Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64, xptr, xld, Y.n, cols, c->W,
                                    Y.n_pad, Y.Qc, sc.xw, sc.ld, sc.xwpart,
-                                   (int64_t)xw_splits(Y.n) * Y.Qc * sc.ld, s, check012);
+                                   (int64_t)xw_splits(Y.n) * Y.Qc * sc.ld, s, check012, xargs);
         if (e != hipSuccess) return e;
     }
     hipError_t e = partial_chunks(sc.part, sc.ld, Y.n_pad / c->shape.part_rows, (int)Y.Q, cols,
@@ -1354,7 +1355,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                        const std::vector<const void*>& xp, const std::vector<int64_t>& xl,
                        const std::vector<double*>& bo, const std::vector<int64_t>& lb,
                        const std::vector<double*>& vo, const std::vector<int*>& io, int64_t cols,
-                       bool async_args, bool args_ready) -> int {
+                       bool async_args, bool args_ready, bool x_from_args) -> int {
         if (!args_ready) {
             for (int i = 0; i < nctx; ++i) {
                 h[i] = trmm_args_for(cs[i], xp[i], xl[i], cols);
@@ -1386,7 +1387,8 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         for (int i = 0; i < nctx; ++i) {
             hipStream_t si = (i == 0) ? s : cs[i]->s_comp;
             if (i > 0) HIPCHK(c0, hipStreamWaitEvent(si, c0->ev_fork, 0));
-            HIPCHK(c0, finish_sub(cs[i], ctx_scratch(cs[i]), xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], si));
+            HIPCHK(c0, finish_sub(cs[i], ctx_scratch(cs[i]), xp[i], xl[i], cols, bo[i], lb[i], vo[i], io[i], si,
+                                  x_from_args ? d + i : nullptr));
             if (i > 0) {
                 HIPCHK(c0, hipEventRecord(cs[i]->ev_join, si));
                 HIPCHK(c0, hipStreamWaitEvent(s, cs[i]->ev_join, 0));
@@ -1400,10 +1402,9 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         const int64_t cols = std::min<int64_t>(blk, mblk - col0);
         const int slot = (int)(k & 1);
         const bool use_graph = want_graph && cols == blk;
-        // in a float64 graph the product reads the dosages through the
-        // argument array and nothing else reads them: device dosages stay
-        // in place and the array is updated before a replay
-        const bool graph_direct = use_graph && c0->lay.precision == GWAS_FP64;
+        // in a graph the product and the cross products read the dosages
+        // through the argument array: device dosages stay in place and the
+        // array is updated before a replay
         int rc = ensure_schedule(cols);
         if (rc) return rc;
         std::vector<const void*> xp(nctx);
@@ -1414,7 +1415,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         for (int i = 0; i < nctx; ++i) {
             gwas_ctx* c = cs[i];
             const char* src = static_cast<const char*>(XR[i]) + (size_t)col0 * ldx[i] * elem;
-            if (direct_x[i] && (!use_graph || graph_direct)) {
+            if (direct_x[i]) {
                 xp[i] = src;
                 xl[i] = ldx[i];
             } else {
@@ -1465,7 +1466,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                 if (const hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal))
                     return fail_hip(c0, eb, "hipStreamBeginCapture");
                 const int erc = enqueue(g->h_args_graph, g->d_args_graph, g->d_sched_graph, g->n_sched, xp, xl,
-                                        bo, lb, vo, io, cols, false, true);
+                                        bo, lb, vo, io, cols, false, true, true);
                 hipGraph_t graph = nullptr;
                 const hipError_t ec = hipStreamEndCapture(s, &graph);
                 g->graph = graph;   // owned by the group from here on, whatever fails below
@@ -1498,7 +1499,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
         } else {
             if (k >= 2) HIPCHK(c0, hipEventSynchronize(c0->ev_done[slot]));   // slot's arguments free
             const int erc = enqueue(g->h_args[slot], g->d_args[slot], g->d_sched, g->n_sched, xp, xl, bo, lb,
-                                    vo, io, cols, true, false);
+                                    vo, io, cols, true, false, false);
             if (erc) return erc;
         }
         if (c0->timing) {

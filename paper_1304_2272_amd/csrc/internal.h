@@ -167,11 +167,13 @@ int64_t trmm_schedule_len(int64_t n_pad, int64_t cols, const TrmmShape& sh);
 // part_cap doubles, at least xw_splits(n) * Qc * cols) K is split in chunks
 // fixed by n and the partial sums are added in order; without it, one split.
 // check012 (int8 dosages): a SNP with a dosage outside {0, 1, 2} gets NaN.
+// xargs (device memory, may be null): the kernel takes X and ldx from
+// xargs->X and xargs->ldx when it runs (X and ldx here are only checked).
 int xw_splits(int64_t n);
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw,
                        int64_t ldxw, double* part, int64_t part_cap, hipStream_t s,
-                       bool check012 = false);
+                       bool check012 = false, const TrmmArgs* xargs = nullptr);
 
 // Reverse mode through the per-SNP solves (one trait).  For SNP j, with the
 // Cholesky factor of S_j from R = chol(S_TL), S_BL = x^T W_L and s = 1/var,

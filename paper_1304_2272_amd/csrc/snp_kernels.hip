@@ -36,11 +36,17 @@ constexpr int XW_KSPLIT = 2048;
 constexpr int XW_QMAX = 80;         // columns of W per workgroup (5 blocks)
 
 template <typename XT, int WQ, int WV>
-__global__ __launch_bounds__(64 * WV) void xw_kernel(const XT* __restrict__ X, int64_t ldx, int64_t n,
+__global__ __launch_bounds__(64 * WV) void xw_kernel(const XT* X, int64_t ldx, int64_t n,
                                                            int64_t cols, const double* __restrict__ W,
                                                            int64_t ldw, int Qc, double* __restrict__ out,
                                                            int64_t ldo, int64_t split_stride, int64_t klen,
-                                                           int check012) {
+                                                           int check012, const TrmmArgs* xargs) {
+    // xargs: the dosages' address and stride come from a device argument
+    // array (a replayed graph reads the block's dosages in place)
+    if (xargs) {
+        X = static_cast<const XT*>(xargs->X);
+        ldx = xargs->ldx;
+    }
     constexpr int NT = 64 * WV;
     constexpr int TC = 64 * WV;                     // SNPs per workgroup, one per thread
     constexpr int TQ = 16 * WQ;
@@ -466,7 +472,8 @@ int xw_splits(int64_t n) { return (int)std::max<int64_t>(1, (n + XW_KSPLIT - 1) 
 
 hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t cols,
                        const double* W, int64_t ldw, int Qc, double* xw, int64_t ldxw,
-                       double* part, int64_t part_cap, hipStream_t s, bool check012) {
+                       double* part, int64_t part_cap, hipStream_t s, bool check012,
+                       const TrmmArgs* xargs) {
     if (cols <= 0) return hipSuccess;
     if (!X || !W || !xw || n < 1 || ldx < n || ldw < (n + XW_BK - 1) / XW_BK * XW_BK || ldxw < cols || Qc < 1)
         return hipErrorInvalidValue;
@@ -489,9 +496,9 @@ hipError_t snp_cross_w(int xt, const void* X, int64_t ldx, int64_t n, int64_t co
     const int64_t klen = splits > 1 ? (int64_t)XW_KSPLIT : (n + XW_BK - 1) / XW_BK * XW_BK;
 #define GWAS_XW(T, WQ)                                                                                 \
     if (narrow) hipLaunchKernelGGL((xw_kernel<T, WQ, 1>), grid, dim3(64), 0, s, (const T*)X, ldx, n, cols, \
-                                   W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8)); \
+                                   W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8), xargs); \
     else hipLaunchKernelGGL((xw_kernel<T, WQ, 4>), grid, dim3(256), 0, s, (const T*)X, ldx, n, cols, \
-                       W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8))
+                       W, ldw, Qc, out, ldo, stride, klen, (int)(check012 && xt == X_I8), xargs)
 #define GWAS_XW_T(T)                        \
     switch (wq) {                           \
         case 1: GWAS_XW(T, 1); break;       \

@@ -446,10 +446,12 @@ def test_group_matches_single_contexts(precision):
             c.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "int8"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "int8", "bf16x3"])
 def test_group_graph_replays_match_eager(precision):
     # the reduced modes' graphs also hold the cross products and, for the
-    # cohort of n = 2,100 (two K splits), the reduction of their partial sums
+    # cohort of n = 2,100 (two K splits), the reduction of their partial sums;
+    # the dosages of each call are new device tensors, which the replay reads
+    # in place through its argument array
     import torch
     dev = torch.device("cuda:0")
     blk, m = 256, 1024
