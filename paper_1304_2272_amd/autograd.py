@@ -7,7 +7,10 @@ loss l built from b and var with torch.  The covariance is assembled with
 torch (input marshalling); every step of the GLS solves and of their reverse
 pass runs in the HIP library.  With dM/dh2 = sigma2 (Phi - I) =
 (M - sigma2 I) / h2 (h2 > 0) and dM/dsigma2 = M / sigma2 the library only
-needs the contractions <Mbar, M> and tr Mbar.  One trait (y is an n-vector).
+needs the contractions <Mbar, M> and tr Mbar.  As h2 -> 0 the two terms of
+dl/dh2 = (<Mbar, M> - sigma2 tr Mbar) / h2 approach each other, and its
+relative error grows like 1/h2 (about 5e-11 at h2 = 0.001 on the tests'
+workloads).  One trait (y is an n-vector).
 """
 
 from __future__ import annotations

@@ -229,6 +229,58 @@ def test_rank_deficient_snp_and_not_spd():
     assert ei.value.code == 3
 
 
+RANK_TOL = {"fp64": 1e-10, "int8": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16"])
+def test_rank_flag_is_whitened_r2_above_one_minus_tol(precision):
+    # info = p exactly when s_i <= tol S_BR, i.e. when the whitened R^2 of
+    # x_i on X_L is at least 1 - tol: collinear SNPs in every mode and, in
+    # the reduced modes, SNPs too close to collinear for their product to
+    # resolve s_i (b and var NaN).  SNPs are planted at 1 - R^2 from 0.5
+    # down to 1e-12 and at exact collinearity; those within a factor 4 of
+    # the tolerance may go either way.
+    n, p, seed = 600, 4, 303
+    prob = synth.make_problem(n, p, seed)
+    M, XL = prob["M"], prob["XL"]
+    Li = np.linalg.inv(np.linalg.cholesky(M))
+    A = Li @ XL
+    Qa, _ = np.linalg.qr(A)
+    rng = np.random.default_rng(seed)
+    gaps = np.array([0.5, 0.1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 0.0])
+    XR = np.empty((len(gaps) * 3, n))
+    target = np.empty(len(XR))
+    for k in range(len(XR)):
+        gap = gaps[k % len(gaps)]
+        u = Qa @ rng.standard_normal(Qa.shape[1])        # in the span of the whitened covariates
+        v = rng.standard_normal(n)
+        v -= Qa @ (Qa.T @ v)                             # orthogonal to it
+        zw = u / np.linalg.norm(u) * np.sqrt(1.0 - gap) + v / np.linalg.norm(v) * np.sqrt(gap)
+        XR[k] = np.linalg.solve(Li, zw)                  # x = L zw, so L^-1 x = zw
+        zx = Li @ XR[k]
+        target[k] = 1.0 - np.sum((Qa.T @ zx) ** 2) / np.sum(zx ** 2)
+    # the planted SNPs with an exact zero gap are exact combinations of X_L
+    exact = gaps[np.arange(len(XR)) % len(gaps)] == 0.0
+    XR[exact] = (XL @ rng.standard_normal((p - 1, int(exact.sum())))).T
+    target[exact] = 0.0
+    tol = RANK_TOL[precision]
+    _say(f"rank flag {precision}: tol {tol:g}, gaps {gaps[0]:g}..{gaps[-2]:g} and 0")
+    b, var, info = run(prob, XR, precision=precision)
+    flagged = info != 0
+    sure_in = target <= tol / 4
+    sure_out = target >= 4 * tol
+    _say(f"  flagged {int(flagged.sum())} of {len(XR)}; must {int(sure_in.sum())}, must not {int(sure_out.sum())}")
+    assert np.all(flagged[sure_in]) and not np.any(flagged[sure_out])
+    assert np.all(info[flagged] == p) and np.all(np.isnan(b[flagged])) and np.all(np.isnan(var[flagged]))
+    assert np.all(np.isfinite(b[~flagged])) and np.all(np.isfinite(var[~flagged]))
+    if precision == "fp64":
+        # the oracle takes the same decision outside the band around tol
+        # (a SNP planted at 1 - R^2 = tol goes either way on either side)
+        _, _, io = GLSOracle(M, XL, prob["Y"]).solve(XR)
+        clear = sure_in | sure_out
+        assert np.array_equal(info[clear], io[clear])
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16", 1e-2), ("int8", TOL_FP64)])
 def test_reduced_precision_vs_oracle(precision, tol):
     n, p, m, seed = 1500, 8, 3000, 77
