@@ -563,41 +563,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_paired_kernel(TrmmArgs la
 // 16 lanes of a 16-byte read per cycle.
 __device__ __forceinline__ int pair_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
 
-// Compiler-only ordering of memory operations around the stage barrier.
-__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
-
-// One 16-byte-per-lane buffer load straight into LDS: lane l's 16 bytes
-// land at lds + 16 l (M0 holds the instruction's LDS address).  Written out
-// because the compiler, which does not follow the three buffers through the
-// unrolled stage loop, would otherwise wait for every load in flight before
-// the first read of a stage; the loads write no registers, and the stage
-// loop orders them with explicit vmcnt waits and barriers.  Nothing else in
-// the kernel uses M0.
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void load_lds16(u4_t rsrc, uint32_t lds, uint32_t voff) {
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
-                 :: "s"(lds), "v"(voff), "s"(rsrc) : "memory", "m0");
-}
-#pragma clang diagnostic pop
-
-// Buffer descriptor words (base, range in bytes), as for the buffer loads
-// elsewhere (flags word 0x00020000), held in scalar registers.
-__device__ __forceinline__ u4_t buffer_words(const void* base, uint32_t bytes) {
-    const uint64_t b = reinterpret_cast<uint64_t>(base);
-    u4_t r;
-    r[0] = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    r[1] = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32) & 0xffffu);
-    r[2] = __builtin_amdgcn_readfirstlane(bytes);
-    r[3] = 0x00020000u;
-    return r;
-}
-
-// LDS byte address of p, wave-uniform, in a scalar register
-__device__ __forceinline__ uint32_t lds_address(const char* p) {
-    return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p);
-}
-
 // The paired-digit product with its operands loaded straight from global
 // memory into NBUF LDS buffers (2 or 3): the loads of stage kt + NBUF - 1
 // are issued at the top of stage kt, and with three buffers the end of

@@ -576,6 +576,209 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     }
 }
 
+// Float64 product with int8 dosages, its operands loaded straight from
+// global memory into three LDS buffers: the loads of stage kt + 2 are
+// issued at the top of stage kt and the end of stage kt waits only for
+// stage kt + 1's (explicit vmcnt waits and a bare s_barrier, as in the
+// paired-digit int8 product), so two stages of matrix instructions cover
+// their latency and no staging registers or LDS writes are spent on them.
+// A stage is 16 elements of K (128 bytes of a row of L^-1, 16 bytes of a
+// dosage column).  L^-1 rows sit unpadded in groups of 8 rows (1 KB, one
+// load instruction); chunk c of row r of a group goes to slot
+// 16 (c / 2) + 8 ((c % 2) xor (group parity)) + r % 8, so a fragment read
+// (16 rows, one chunk) hits distinct banks whether the LDS serves 8 or 16
+// lanes of a 16-byte read per cycle.  Dosage columns keep their 16 int8
+// bytes per stage side by side (a lane's four bytes per 16-column block are
+// one conflict-free 4-byte read) and become float64 in registers.  Rows at
+// or past n (identity rows of the padded L^-1 meet whatever follows a
+// column past n) are zeroed before the sums.  The tile and the partial-sum
+// layout are those of the 128 x 128 shape of 32 x 64 waves.
+__device__ __forceinline__ int f64_slot(int r8, int c, int parity) {
+    return (c >> 1) * 16 + (((c & 1) ^ parity) << 3) + r8;
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
+    typedef MM<double> T;
+    constexpr int WGM = 4, WGN = 2, WTM = 2, WTN = 4;
+    constexpr int TM = WGM * WTM * 16, TN = WGN * WTN * 16, NW = WGM * WGN;
+    constexpr int BK = 16;                         // K per stage
+    constexpr int AB = TM * BK * 8;                // bytes of L^-1 per stage buffer
+    constexpr int XBB = TN * BK;                   // bytes of dosages per stage buffer
+    constexpr int NA = TM / 8, NB = TN / 64;       // load instructions per stage (1 KB each)
+    static_assert(NA % NW == 0 && NB <= NW, "load instructions per wave");
+    constexpr int LA = NA / NW;
+    // s_waitcnt immediates: vmcnt(this wave's loads per stage) or vmcnt(0),
+    // with lgkmcnt(0) and any expcnt; waves below NB issue one dosage load
+    constexpr int WAIT_MORE = (LA + 1) | (7 << 4);
+    constexpr int WAIT_LESS = LA | (7 << 4);
+    constexpr int WAIT_ALL = 7 << 4;
+
+    const int e0 = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x]);
+    const int J = __builtin_amdgcn_readfirstlane(la.sched[2 * (int64_t)blockIdx.x + 1]);
+    if (e0 < 0) return;
+    const int I = e0 & SCHED_ROW_MASK;
+    const TrmmArgs a = GROUPED ? la.group[e0 >> SCHED_CTX_SHIFT] : la;
+    if ((int64_t)J * TN >= a.cols) return;
+
+    __shared__ __attribute__((aligned(1024))) char A0[AB];
+    __shared__ __attribute__((aligned(1024))) char A1[AB];
+    __shared__ __attribute__((aligned(1024))) char A2[AB];
+    __shared__ __attribute__((aligned(1024))) char B0[XBB];
+    __shared__ __attribute__((aligned(1024))) char B1[XBB];
+    __shared__ __attribute__((aligned(1024))) char B2[XBB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WGN, wc = wave % WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    const int64_t r0 = (int64_t)I * TM;
+    const int64_t c0 = (int64_t)J * TN;
+    const int64_t kend = a.full_k ? a.n_pad : std::min<int64_t>(r0 + TM, a.n_pad);
+    const int nk = (int)(kend / BK);
+    const int64_t row_bytes = a.ldu * 8;
+
+    const u4_t rsA = buffer_words(reinterpret_cast<const char*>(a.Ut) + r0 * row_bytes, (uint32_t)(TM * row_bytes));
+    const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
+    const int64_t xbytes = ((xcols - 1) * a.ldx + a.n + 15) / 16 * 16;
+    const u4_t rsB = buffer_words(reinterpret_cast<const int8_t*>(a.X) + c0 * a.ldx, (uint32_t)xbytes);
+    // lane l of an L^-1 load instruction (group q of 8 rows) fetches the
+    // chunk that belongs in slot l; lane l of a dosage load, column l of its 64
+    const int lr8 = lane & 7;
+    const int lc_even = 2 * (lane >> 4) + ((lane >> 3) & 1);       // chunk for an even group
+    const int lc_odd = 2 * (lane >> 4) + (((lane >> 3) & 1) ^ 1);  // chunk for an odd group
+    const bool has_b = wave < NB;
+    auto load = [&](int kt, char* Ab, char* Bb) {
+#pragma unroll
+        for (int c = 0; c < LA; ++c) {
+            const int q = wave + c * NW;
+            const int ch = (q & 1) ? lc_odd : lc_even;
+            load_lds16(rsA, lds_address(Ab + q * 1024),
+                       (uint32_t)((q * 8 + lr8) * row_bytes + kt * (BK * 8) + ch * 16));
+        }
+        if (has_b)
+            load_lds16(rsB, lds_address(Bb + wave * 1024),
+                       (uint32_t)((wave * 64 + lane) * a.ldx + kt * BK));
+    };
+
+    d4_t acc[WTM][WTN];
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    // this lane's fragment addresses within a stage buffer: rows
+    // wr*32 + i*16 + li, chunks 2 lg and 2 lg + 1; dosage bytes 4 lg.. of
+    // columns wc*64 + j*16 + li
+    int aoff[WTM][2];
+#pragma unroll
+    for (int i = 0; i < WTM; ++i) {
+        const int row = wr * WTM * 16 + i * 16 + li;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) aoff[i][h] = (row >> 3) * 1024 + f64_slot(row & 7, 2 * lg + h, (row >> 3) & 1) * 16;
+    }
+    const int boff = (wc * WTN * 16 + li) * BK + lg * 4;
+
+    auto stage = [&](int kt, const char* Ar, const char* Br, char* An, char* Bn) {
+        const bool ahead = kt + 2 < nk;
+        if (ahead) load(kt + 2, An, Bn);
+        u4_t fa[WTM][2];
+        uint32_t fb[WTN];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) fa[i][h] = *reinterpret_cast<const u4_t*>(Ar + aoff[i][h]);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + boff + j * 16 * BK);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            double xb[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * st));
+#pragma unroll
+            for (int i = 0; i < WTM; ++i) {
+                const u2_t w2 = (st & 1) ? u2_t{fa[i][st >> 1][2], fa[i][st >> 1][3]}
+                                         : u2_t{fa[i][st >> 1][0], fa[i][st >> 1][1]};
+                const double av = __builtin_bit_cast(double, w2);
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j] = T::mma(av, xb[j], acc[i][j]);
+            }
+        }
+        // the stage's matrix instructions stay ahead of its barrier
+        __builtin_amdgcn_sched_barrier(0);
+        if (!ahead) __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+        else if (has_b) __builtin_amdgcn_s_waitcnt(WAIT_MORE);
+        else __builtin_amdgcn_s_waitcnt(WAIT_LESS);
+        compiler_fence();
+        __builtin_amdgcn_s_barrier();
+        compiler_fence();
+    };
+
+    load(0, A0, B0);
+    if (nk > 1) {
+        load(1, A1, B1);
+        if (has_b) __builtin_amdgcn_s_waitcnt(WAIT_MORE);
+        else __builtin_amdgcn_s_waitcnt(WAIT_LESS);
+    } else {
+        __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    }
+    compiler_fence();
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
+    for (int kt = 0; kt < nk; kt += 3) {
+        stage(kt, A0, B0, A2, B2);
+        if (kt + 1 < nk) stage(kt + 1, A1, B1, A0, B0);
+        if (kt + 2 < nk) stage(kt + 2, A2, B2, A1, B1);
+    }
+
+    // Epilogue (as the staged float64 tiles): per column, sums over this
+    // wave's 32 rows; rows at or past n are zeroed first
+    const int Q = a.with_cross ? a.Qc + 1 : 1;
+    const int64_t rw = r0 + wr * WTM * 16;
+    const int64_t pb = rw / (WTM * 16);
+    const int64_t cbase = c0 + wc * WTN * 16 + li;
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (rw + i * 16 + T::ROW_G * lg + T::ROW_V * v >= a.n)
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j][v] = 0.0;
+    if (a.with_cross) {
+        for (int q = 0; q < a.Qc; ++q) {
+            const double* Cq = a.C + q * a.ldc + rw + T::ROW_G * lg;
+            double cv[WTM][4];
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + T::ROW_V * v];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+                double sum = 0.0;
+#pragma unroll
+                for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * cv[i][v];
+                sum = wave_sum16(sum);
+                const int64_t col = cbase + j * 16;
+                if (lg == 0 && col < a.cols) a.part[(pb * Q + q) * a.ldp + col] = sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * acc[i][j][v];
+        sum = wave_sum16(sum);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+    }
+}
+
 // Tile shapes of the triangular product.  MINB is the workgroups per CU
 // the register budget is sized for.
 typedef Shape<2, 2, 4, 4, 2> Cfg0;   // 128 x 128, 256 threads, waves of 64 x 64
@@ -618,13 +821,23 @@ hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
         case 6:
             if constexpr (!F64 && I8) return launch_trmm<AT, XT, Cfg6>(a, s);
             else return hipErrorInvalidValue;
+        case 7:
+            if constexpr (F64 && I8) {
+                if (a.group)
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<true>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                else
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<false>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int trmm_num_cfgs() { return 7; }
+int trmm_num_cfgs() { return 8; }
 int trmm_cfg_limit() { return std::max(trmm_num_cfgs(), trmm_sliced_cfgs()); }
 
 bool trmm_shape_sum32(int cfg) { return cfg == 6; }
@@ -638,6 +851,7 @@ TrmmShape trmm_shape(int cfg) {
         case 4: return shape_of<Cfg4>();
         case 5: return shape_of<Cfg5>();
         case 6: return shape_of<Cfg6>();
+        case 7: return shape_of<Cfg2>();   // the float64 direct-load kernel: Cfg2's tile
         default: return TrmmShape{0, 0, 0, 0, 0, 0};
     }
 }
@@ -647,6 +861,8 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
     // 64 x 128 waves fit two per SIMD only with float32 sums and int8 dosages
     if (cfg == 6) return at != A_F64 && xt == X_I8;
+    // float64 with int8 dosages loaded straight into LDS
+    if (cfg == 7) return at == A_F64 && xt == X_I8;
     if (at == A_F64) return true;
     // The reduced-precision products also carry float64 partial sums; 64 x 64
     // waves of them only fit two waves per SIMD without spilling when the
@@ -657,7 +873,9 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 
 // Measured on MI355X at n = 50,000 with int8 dosages (one 50,000-SNP block):
 // float64 is fastest in the 128 x 128 tile of 32 x 64 waves (67.5 TFLOP/s,
-// against 66.0 in the 128 x 256 tile, 67.3 in the 256 x 128 tile); float32
+// against 66.0 in the 128 x 256 tile, 67.3 in the 256 x 128 tile), and
+// that tile a little faster again with its operands loaded straight into
+// LDS (shape 7: 67.8 against 67.35 TFLOP/s in the same run); float32
 // and bfloat16 in the 256 x 256 tile of 64 x 128 waves with float32 sums
 // (141 and 1,180 TFLOP/s, against 131 and 870 in the 128 x 256 tile with
 // float64 sums; b moves from 6e-11 to 4e-10 of the float64 path for
@@ -671,7 +889,7 @@ int trmm_default_cfg(int at, int xt) {
     // against 0.42 for the unpaired 32 x 256 tile, 0.49 for the paired
     // 64 x 256 tile with three buffers)
     if (at == A_I8S) return 5;
-    if (at == A_F64) return xt == X_I8 ? 2 : 3;
+    if (at == A_F64) return xt == X_I8 ? 7 : 3;
     if (xt == X_I8) return 6;
     return 1;
 }
@@ -679,8 +897,9 @@ int trmm_default_cfg(int at, int xt) {
 TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup) {
     TrmmShape sh = (at == A_I8S) ? trmm_sliced_shape(cfg) : trmm_shape(cfg);
     if (sh.tm == 0) return sh;
-    // workgroups per CU: the 256-thread shape is sized for two
-    const int per_cu = (at != A_I8S && cfg == 0) || (at == A_I8S && trmm_sliced_two_per_cu(cfg)) ? 2 : 1;
+    // workgroups per CU: the 256-thread shape and the float64 direct-load
+    // shape are sized for two
+    const int per_cu = (at != A_I8S && (cfg == 0 || cfg == 7)) || (at == A_I8S && trmm_sliced_two_per_cu(cfg)) ? 2 : 1;
     sh.inflight = 32 * per_cu;
     const int64_t asz = at == A_F64 ? 8 : at == A_F32 ? 4 : at == A_BF16 ? 2 : 1;
     const int64_t arows = at == A_I8S ? (int64_t)sh.tm * slices : sh.tm;
@@ -729,10 +948,11 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     }
     const TrmmShape sh = trmm_geom(a.at, a.xt, a.cfg, a.slices, a.rgroup);
     if (a.n_pad % sh.tm) return hipErrorInvalidValue;
-    // 32-bit buffer offsets of the SUM32 shapes: a tile's rows of L^-1 and
-    // its dosage columns up to the last stage
-    if (a.at != A_I8S && trmm_shape_sum32(a.cfg)) {
-        const int64_t asz = a.at == A_F32 ? 4 : 2;
+    // 32-bit buffer offsets of the SUM32 shapes and of the float64
+    // direct-load shape: a tile's rows of L^-1 and its dosage columns up to
+    // the last stage
+    if (a.at != A_I8S && (trmm_shape_sum32(a.cfg) || a.cfg == 7)) {
+        const int64_t asz = a.at == A_F64 ? 8 : a.at == A_F32 ? 4 : 2;
         if ((int64_t)sh.tm * a.ldu * asz > INT32_MAX || ((int64_t)sh.tn * a.ldx + a.n_pad) * (int64_t)xs > INT32_MAX)
             return hipErrorInvalidValue;
     }

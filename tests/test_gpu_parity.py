@@ -295,7 +295,7 @@ def test_reduced_precision_vs_oracle(precision, tol):
     assert err < tol
 
 
-TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6], "int8": [0, 1, 2, 3, 4, 5]}
+TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5, 7], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6], "int8": [0, 1, 2, 3, 4, 5]}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
