@@ -125,7 +125,7 @@ def measured_traffic(leg, workload_name):
     if not rec.get("kernel_sources") or rec.get("kernel_source_sha256") != h.hexdigest():
         return None, "kernel changed since the counters were taken"
     return rec["traffic_bytes_per_launch"], (
-        f"FETCH_SIZE+WRITE_SIZE per launch over the {rec['launches']} launches of one 50,000-SNP block, "
+        f"FETCH_SIZE+WRITE_SIZE per launch over {rec['launches']} launches ({rec['columns']} SNP columns), "
         f"calibrated on a plain element-wise kernel; algorithmic {rec['algorithmic_bytes_per_launch']:.3g} B "
         f"per launch")
 

@@ -34,7 +34,7 @@ CSRC = os.path.join("paper_1304_2272_amd", "csrc")
 def kernel_sources(kernel):
     """Source files (relative to the repository root) whose text decides the
     named kernel's code."""
-    own = "sliced_kernels.hip" if "sliced" in kernel else "trmm_kernels.hip"
+    own = "sliced_kernels.hip" if ("sliced" in kernel or "paired" in kernel) else "trmm_kernels.hip"
     return [os.path.join(CSRC, own), os.path.join(CSRC, "trmm_common.h")]
 
 
