@@ -141,13 +141,13 @@ def cpu_model():
 
 
 def cpu_baseline(workload, seed, n_s, m_s):
-    """The oracle on one pinned host core, on a bounded sample of the workload
-    (its first n_s individuals and m_s SNPs).  Its factorisation costs
-    O(n^3) and each SNP two triangular solves with the factors of M
-    (O(n^2)), so the full-size figures are extrapolated from the sample:
-    SNPs/s by (n_s/n)^2, the factorisation by (n/n_s)^3."""
-    from threadpoolctl import threadpool_limits
-    from oracle import GLSOracle
+    """The plain C oracle (single-threaded float64, no BLAS) on one pinned
+    host core, on a bounded sample of the workload (its first n_s
+    individuals and m_s SNPs).  Its factorisation costs O(n^3) and each SNP
+    two triangular solves with the Cholesky factor of M (O(n^2)), so the
+    full-size figures are extrapolated from the sample: SNPs/s by
+    (n_s/n)^2, the factorisation by (n/n_s)^3."""
+    from oracle import GLSPlain
     from paper_1304_2272_amd import synth
     n, m = workload["n"], workload["m"]
     prob = synth.make_problem(n_s, workload["p"], seed)
@@ -156,12 +156,11 @@ def cpu_baseline(workload, seed, n_s, m_s):
     core = min(old)
     os.sched_setaffinity(0, {core})
     try:
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            orc = GLSOracle(prob["M"], prob["XL"], prob["Y"])
-            t1 = time.perf_counter()
-            orc.solve(XR)
-            t2 = time.perf_counter()
+        t0 = time.perf_counter()
+        orc = GLSPlain(prob["M"], prob["XL"], prob["Y"])
+        t1 = time.perf_counter()
+        orc.solve(XR)
+        t2 = time.perf_counter()
     finally:
         os.sched_setaffinity(0, old)
     rate_s = m_s / (t2 - t1)
@@ -169,7 +168,7 @@ def cpu_baseline(workload, seed, n_s, m_s):
     t_factor = (t1 - t0) * (n / n_s) ** 3
     return {
         "value": rate, "unit": "SNP/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle (numpy/LAPACK, one BLAS thread, pinned to core {core}) on the same recipe "
+        "sample": (f"plain C oracle (single-threaded float64, no BLAS, pinned to core {core}) on the same recipe "
                    f"restricted to the first {n_s} individuals and {m_s} SNPs: {rate_s:.1f} SNP/s there, "
                    f"scaled by (n_s/n)^2 = {(n_s / n) ** 2:.4g} for its O(n^2) per-SNP solves"),
         "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_before": sorted(old),
@@ -611,8 +610,8 @@ def main():
     ap.add_argument("--c2-blocks", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--band-widths", default="256,1024,4096", help="half-bandwidths of the banded-M leg")
-    ap.add_argument("--cpu-n", type=int, default=6144)
-    ap.add_argument("--cpu-snps", type=int, default=4096)
+    ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--cpu-snps", type=int, default=512)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

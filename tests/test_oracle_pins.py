@@ -8,9 +8,16 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import GLSOracle, GLSWhitenedQR, gls_literal
+from oracle import GLSOracle, GLSPlain, GLSWhitenedQR, gls_literal
 from oracle import gls as oracle_gls
 from paper_1304_2272_amd import synth
+
+
+@pytest.fixture(params=["numpy", "plain_c"])
+def Oracle(request):
+    """Both oracles meet the same pins: the numpy/LAPACK definition and the
+    plain single-threaded C one."""
+    return GLSOracle if request.param == "numpy" else GLSPlain
 
 
 def _rel(a, b):
@@ -62,7 +69,7 @@ def _frac_mm(A, B):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_p1_exact_rationals(seed):
+def test_p1_exact_rationals(seed, Oracle):
     rng = np.random.default_rng(100 + seed)
     n, p, m = 7, 3, 4
     A = rng.integers(-3, 4, size=(n, n))
@@ -70,7 +77,7 @@ def test_p1_exact_rationals(seed):
     XL = np.column_stack([np.ones(n, dtype=np.int64), rng.integers(-4, 5, size=n)])
     y = rng.integers(-9, 10, size=n)
     XR = rng.integers(0, 3, size=(m, n))
-    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    b, var, info = Oracle(M, XL, y).solve(XR)
     Mf = [[Fraction(int(v)) for v in row] for row in M]
     for i in range(m):
         Xi = [[Fraction(int(XL[r, 0])), Fraction(int(XL[r, 1])), Fraction(int(XR[i, r]))] for r in range(n)]
@@ -100,10 +107,10 @@ def _gauss_jordan_inverse(M):
     return aug[:, n:]
 
 
-def test_p2_explicit_inverse():
+def test_p2_explicit_inverse(Oracle):
     M, XL, y, XR = _problem(40, 4, 25, seed=3)
     Minv = _gauss_jordan_inverse(M)
-    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    b, var, _ = Oracle(M, XL, y).solve(XR)
     for i in range(XR.shape[0]):
         Xi = np.column_stack([XL, XR[i]])
         N = Xi.T @ Minv @ Xi
@@ -114,11 +121,11 @@ def test_p2_explicit_inverse():
 
 # -- P3: QR-based GLS through symmetric whitening (Section 2's alternative) --
 
-def test_p3_qr_whitening():
+def test_p3_qr_whitening(Oracle):
     M, XL, y, XR = _problem(60, 5, 20, seed=4)
     w, V = np.linalg.eigh(M)
     Wh = (V / np.sqrt(w)) @ V.T                        # M^{-1/2}, symmetric
-    b, _, _ = GLSOracle(M, XL, y).solve(XR)
+    b, _, _ = Oracle(M, XL, y).solve(XR)
     for i in range(XR.shape[0]):
         Xi = np.column_stack([XL, XR[i]])
         Q, R = np.linalg.qr(Wh @ Xi)
@@ -129,32 +136,32 @@ def test_p3_qr_whitening():
 # -- P4: planted coefficients, noise-free (fixes bbar_T = X_L^T ybar) -------
 
 @pytest.mark.parametrize("p", [2, 4, 8])
-def test_p4_planted_b(p):
+def test_p4_planted_b(p, Oracle):
     prob = synth.make_problem(300, p, seed=11, noise=False)
     XR = synth.snp_block(300, 11, 0, 50)
     beta = prob["beta"][:, 0]
-    b, _, info = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    b, _, info = Oracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
     assert (info == 0).all()
     want = np.concatenate([beta, [0.0]])
     assert np.max(np.abs(b[:, 0, :] - want)) < 1e-10 * max(1.0, np.max(np.abs(beta)))
     # plant a SNP effect on SNP k
     k, gamma = 17, 0.75
     y2 = prob["Y"][:, 0] + gamma * XR[k]
-    b2, _, _ = GLSOracle(prob["M"], prob["XL"], y2).solve(XR[k:k + 1])
+    b2, _, _ = Oracle(prob["M"], prob["XL"], y2).solve(XR[k:k + 1])
     assert np.max(np.abs(b2[0, 0] - np.concatenate([beta, [gamma]]))) < 1e-10
 
 
 # -- P5: M = I gives OLS; M = diag(1/w) gives weighted least squares --------
 
-def test_p5_ols_and_wls():
+def test_p5_ols_and_wls(Oracle):
     rng = np.random.default_rng(5)
     n, p, m = 80, 4, 12
     XL = np.column_stack([np.ones(n), rng.standard_normal((n, p - 2))])
     y = rng.standard_normal(n)
     XR = rng.integers(0, 3, size=(m, n)).astype(np.float64)
-    b, _, _ = GLSOracle(np.eye(n), XL, y).solve(XR)
+    b, _, _ = Oracle(np.eye(n), XL, y).solve(XR)
     w = rng.uniform(0.2, 5.0, n)
-    bw, _, _ = GLSOracle(np.diag(1.0 / w), XL, y).solve(XR)
+    bw, _, _ = Oracle(np.diag(1.0 / w), XL, y).solve(XR)
     for i in range(m):
         Xi = np.column_stack([XL, XR[i]])
         ref = np.linalg.lstsq(Xi, y, rcond=None)[0]
@@ -166,14 +173,14 @@ def test_p5_ols_and_wls():
 
 # -- P6: n = p, square invertible X_i: b_i = X_i^-1 y whatever M ------------
 
-def test_p6_square_design():
+def test_p6_square_design(Oracle):
     rng = np.random.default_rng(6)
     n = p = 4
     M = _spd(n, rng, cond=10.0)
     XL = np.column_stack([np.ones(n), rng.standard_normal((n, p - 2))])
     y = rng.standard_normal(n)
     XR = rng.integers(0, 3, size=(6, n)).astype(np.float64)
-    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    b, var, info = Oracle(M, XL, y).solve(XR)
     for i in range(6):
         Xi = np.column_stack([XL, XR[i]])
         if abs(np.linalg.det(Xi)) < 1e-8:
@@ -185,36 +192,36 @@ def test_p6_square_design():
 
 # -- P7: invariances ----------------------------------------------------------
 
-def test_p7_invariances():
+def test_p7_invariances(Oracle):
     M, XL, y, XR = _problem(50, 4, 10, seed=7)
-    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    b, var, _ = Oracle(M, XL, y).solve(XR)
     # scaling M leaves b unchanged (variance scales)
-    bs, vs, _ = GLSOracle(3.5 * M, XL, y).solve(XR)
+    bs, vs, _ = Oracle(3.5 * M, XL, y).solve(XR)
     assert _rel(bs, b) < 1e-12
     assert _rel(vs, 3.5 * var) < 1e-12
     # consistent permutation of individuals
     perm = np.random.default_rng(8).permutation(50)
-    bp, _, _ = GLSOracle(M[np.ix_(perm, perm)], XL[perm], y[perm]).solve(XR[:, perm])
+    bp, _, _ = Oracle(M[np.ix_(perm, perm)], XL[perm], y[perm]).solve(XR[:, perm])
     assert _rel(bp, b) < 1e-11
     # x -> x + c 1 leaves the SNP coefficient unchanged (intercept absorbs it)
-    bc, vc, _ = GLSOracle(M, XL, y).solve(XR + 2.5)
+    bc, vc, _ = Oracle(M, XL, y).solve(XR + 2.5)
     assert _rel(bc[:, 0, -1], b[:, 0, -1]) < 1e-10
     assert _rel(vc, var) < 1e-10
     # x -> a x divides it by a
-    ba, _, _ = GLSOracle(M, XL, y).solve(-1.7 * XR)
+    ba, _, _ = Oracle(M, XL, y).solve(-1.7 * XR)
     assert _rel(ba[:, 0, -1], b[:, 0, -1] / -1.7) < 1e-11
     # duplicate SNP columns give identical results
-    bd, _, _ = GLSOracle(M, XL, y).solve(np.vstack([XR[3], XR[3]]))
+    bd, _, _ = Oracle(M, XL, y).solve(np.vstack([XR[3], XR[3]]))
     assert np.array_equal(bd[0], bd[1])
 
 
 # -- P8: Frisch-Waugh-Lovell closed form for the SNP coefficient -------------
 
-def test_p8_fwl_closed_form():
+def test_p8_fwl_closed_form(Oracle):
     M, XL, y, XR = _problem(70, 6, 15, seed=9)
     Minv = _gauss_jordan_inverse(M)
     P = Minv - Minv @ XL @ np.linalg.inv(XL.T @ Minv @ XL) @ XL.T @ Minv
-    b, var, _ = GLSOracle(M, XL, y).solve(XR)
+    b, var, _ = Oracle(M, XL, y).solve(XR)
     for i in range(XR.shape[0]):
         x = XR[i]
         s = x @ P @ x
@@ -224,22 +231,22 @@ def test_p8_fwl_closed_form():
 
 # -- literal per-SNP form, multiple traits, rank deficiency -------------------
 
-def test_literal_and_traits():
+def test_literal_and_traits(Oracle):
     M, XL, _, XR = _problem(30, 3, 8, seed=10)
     Y = np.random.default_rng(12).standard_normal((30, 5))
-    b, _, _ = GLSOracle(M, XL, Y).solve(XR)
+    b, _, _ = Oracle(M, XL, Y).solve(XR)
     assert b.shape == (8, 5, 3)
     assert _rel(b, gls_literal(M, XL, Y, XR)) < 1e-11
     for j in range(5):
-        bj, _, _ = GLSOracle(M, XL, Y[:, j]).solve(XR)
+        bj, _, _ = Oracle(M, XL, Y[:, j]).solve(XR)
         assert _rel(b[:, j], bj[:, 0]) < 1e-13
 
 
-def test_rank_deficient_snp_flagged():
+def test_rank_deficient_snp_flagged(Oracle):
     M, XL, y, XR = _problem(40, 4, 5, seed=13)
     XR[2] = 2.0                     # monomorphic: collinear with the intercept
     XR[4] = 0.0                     # all-zero column
-    b, var, info = GLSOracle(M, XL, y).solve(XR)
+    b, var, info = Oracle(M, XL, y).solve(XR)
     assert list(info) == [0, 0, 4, 0, 4]
     assert np.isnan(b[2]).all() and np.isnan(b[4]).all() and np.isnan(var[2])
     assert np.isfinite(b[[0, 1, 3]]).all()
@@ -391,3 +398,31 @@ def test_whitened_qr_keeps_snp_digits_at_high_condition():
     kappa = ev[-1] / ev[0]
     assert se_q < 4.0 * kappa * 2.0 ** -53
     assert _rel(vq, vs) < 1e-11 and _rel(vo, vs) < 1e-9
+
+
+# -- the two oracles against each other on random shapes ----------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plain_c_oracle_matches_numpy_oracle(seed):
+    # two implementations of Eq. (1) that share nothing but the definition
+    # (LU with LAPACK against a hand-written Cholesky and elimination)
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(5, 400))
+    p = int(rng.integers(2, min(12, n) + 1))
+    m = int(rng.integers(1, 60))
+    t = int(rng.integers(1, 4))
+    M, XL, _, XR = _problem(n, p, m, seed=900 + seed)
+    Y = rng.standard_normal((n, t))
+    b0, v0, i0 = GLSOracle(M, XL, Y).solve(XR)
+    b1, v1, i1 = GLSPlain(M, XL, Y).solve(XR)
+    assert np.array_equal(i0, i1)
+    ok = i0 == 0
+    assert _rel(b1[ok], b0[ok]) < 1e-10 and _rel(v1[ok], v0[ok]) < 1e-10
+
+
+def test_plain_c_oracle_refuses_a_non_spd_m():
+    M, XL, y, _ = _problem(20, 3, 1, seed=31)
+    M = M.copy()
+    M[7, 7] = -1.0
+    with pytest.raises(np.linalg.LinAlgError):
+        GLSPlain(M, XL, y)
