@@ -329,7 +329,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * GWAS_INT8_SLICED: 0 stages its operands through registers, 1 and 2 load
  * them straight into LDS, 2 with a wider tile; 3 to 5 add the two digits of
  * a pair into one sum against centred dosages, 3 staging through registers,
- * 4 and 5 loading straight into three or two LDS buffers, 5 the default;
+ * 4 and 5 loading straight into three or two LDS buffers, 4 the default;
  * for GWAS_FP64 with int8 dosages, 7, the default, loads both operands
  * straight into LDS); *best_rgroup (may be NULL) the row group.
  * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged

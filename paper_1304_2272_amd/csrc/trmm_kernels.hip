@@ -884,11 +884,12 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 // 128 x 256 tile and the reduced-precision products take the 128 x 128
 // tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
-    // int8 slices: the paired-digit shape with four waves of 16 x 128, two
-    // LDS buffers and two workgroups per CU (0.50 of int8 peak at n = 50,000
-    // against 0.42 for the unpaired 32 x 256 tile, 0.49 for the paired
-    // 64 x 256 tile with three buffers)
-    if (at == A_I8S) return 5;
+    // int8 slices: the paired-digit 64 x 256 tile loaded straight into three
+    // LDS buffers, one workgroup per CU (fractions of int8 peak at n = 30k,
+    // 50k, 75k, 100k: 0.470, 0.485, 0.494, 0.505); the two-workgroup
+    // 32 x 256 shape is a little faster at 50k (0.50) but falls to 0.33 from
+    // 75k on, and the unpaired register-staged tile gives 0.42-0.44
+    if (at == A_I8S) return 4;
     if (at == A_F64) return xt == X_I8 ? 7 : 3;
     if (xt == X_I8) return 6;
     return 1;
