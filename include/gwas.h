@@ -329,7 +329,8 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * GWAS_INT8_SLICED: 0 stages its operands through registers, 1 and 2 load
  * them straight into LDS, 2 with a wider tile; 3 to 5 add the two digits of
  * a pair into one sum against centred dosages, 3 staging through registers,
- * 4 and 5 loading straight into three or two LDS buffers, 4 the default;
+ * 4 to 6 loading straight into three or two LDS buffers, 6 (128-byte
+ * stages) the default;
  * for GWAS_FP64 with int8 dosages, 7, the default, loads both operands
  * straight into LDS); *best_rgroup (may be NULL) the row group.
  * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged
@@ -340,7 +341,7 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * modes (16 u kappa_i on the SNP coefficient and var) either way.
  *
  * The environment variable GWAS_TRMM_CFG (read by gwas_init) overrides the
- * default shape with one the autotuner would try (0..7, 0..5 for
+ * default shape with one the autotuner would try (0..7, 0..6 for
  * GWAS_INT8_SLICED; ignored when the shape does not apply to the precision
  * and dosage type): a measurement and test aid.
  */

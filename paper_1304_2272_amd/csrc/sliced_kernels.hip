@@ -562,29 +562,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_paired_kernel(TrmmArgs la
 // the rows that share banks to distinct slots, whether the LDS serves 8 or
 // 16 lanes of a 16-byte read per cycle.
 __device__ __forceinline__ int pair_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+// The same for 128-byte stage rows (8 chunks): chunk c of row r in slot
+// c ^ ((r % 8) ^ bit 3 of r).
+__device__ __forceinline__ int pair_swz8(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 // The paired-digit product with its operands loaded straight from global
 // memory into NBUF LDS buffers (2 or 3): the loads of stage kt + NBUF - 1
 // are issued at the top of stage kt, and with three buffers the end of
 // stage kt waits only for stage kt + 1's loads, so two stages of matrix
 // instructions cover their latency (the stage barrier is a bare s_barrier:
-// a memory fence there would wait for every load in flight).  Shapes of
-// four waves run two workgroups per CU, whose barriers fall at different
-// times.  Reads past the dosage block return zero
+// a memory fence there would wait for every load in flight).  A stage is
+// BK = 64 or 128 bytes of K (one or two instruction steps per barrier).
+// Shapes of four waves run two workgroups per CU, whose barriers fall at
+// different times.  Reads past the dosage block return zero
 // through the buffer range; elements k >= n of a column may hold other
 // data, which meets zero digits of every row below n, and rows at or past
 // n get a zero scale.
-template <int S, int WGM, int WGN, int WTN, int NBUF, bool GROUPED>
+template <int S, int WGM, int WGN, int WTN, int NBUF, int BK, bool GROUPED>
 __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(TrmmArgs la) {
     static_assert(NBUF == 2 || NBUF == 3, "two or three stage buffers");
+    static_assert(BK == 64 || BK == 128, "stage rows of 64 or 128 bytes of K");
     constexpr int LOOK = NBUF - 1;                // stages loaded ahead
     constexpr int NP = (S + 1) / 2;
-    constexpr int BK = 64;                        // int8 K per stage (one 64-byte row)
+    constexpr int CPR = BK / 16;                  // 16-byte chunks per stage row
+    constexpr int RPI = 1024 / BK;                // rows per load instruction (1 KB)
     constexpr int TMR = WGM * 16;
     constexpr int TMS = TMR * S;
     constexpr int TN = WGN * WTN * 16;
     constexpr int NW = WGM * WGN;
-    constexpr int NA = TMS / 16, NB = TN / 16;    // load instructions (16 rows, 1 KB) per stage
+    constexpr int NA = TMS / RPI, NB = TN / RPI;  // load instructions per stage
     static_assert(NB % NW == 0, "every wave issues the same number of dosage loads");
     // instruction q is issued by wave q % NW: the first NA % NW waves issue
     // one more L^-1 load per stage than the others
@@ -603,12 +609,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
     const TrmmArgs a = GROUPED ? la.group[__builtin_amdgcn_readfirstlane(e0 >> SCHED_CTX_SHIFT)] : la;
     if ((int64_t)J * TN >= a.cols) return;
 
-    __shared__ __attribute__((aligned(1024))) char A0[TMS * BK];
-    __shared__ __attribute__((aligned(1024))) char A1[TMS * BK];
-    __shared__ __attribute__((aligned(1024))) char A2[NBUF == 3 ? TMS * BK : 16];
-    __shared__ __attribute__((aligned(1024))) char B0[TN * BK];
-    __shared__ __attribute__((aligned(1024))) char B1[TN * BK];
-    __shared__ __attribute__((aligned(1024))) char B2[NBUF == 3 ? TN * BK : 16];
+    __shared__ __attribute__((aligned(1024))) char Abuf[NBUF][TMS * BK];
+    __shared__ __attribute__((aligned(1024))) char Bbuf[NBUF][TN * BK];
+    char* const A0 = Abuf[0];
+    char* const A1 = Abuf[1];
+    char* const A2 = Abuf[NBUF - 1];
+    char* const B0 = Bbuf[0];
+    char* const B1 = Bbuf[1];
+    char* const B2 = Bbuf[NBUF - 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -625,24 +633,27 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
     const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
     const int64_t xbytes = ((xcols - 1) * a.ldx + a.n + 15) / 16 * 16;
     const u4_t rsB = buffer_words(reinterpret_cast<const int8_t*>(a.X) + c0 * a.ldx, (uint32_t)xbytes);
-    // lane l of a load instruction fills slot l % 4 of row l / 4 of its
-    // 16 rows with the chunk that belongs there
-    const int lrow = lane >> 2;
-    const int lchunk = (lane & 3) ^ pair_swz(lrow);
-    // instruction q of a stage (16 rows) is issued by wave q % NW
+    // lane l of a load instruction fills slot l % CPR of row l / CPR of its
+    // RPI rows with the chunk that belongs there (for 128-byte rows the
+    // swizzle of the row depends on the parity of the instruction's group)
+    const int lrow = lane / CPR;
+    auto lchunk = [&](int q) {
+        return BK == 64 ? (lane & 3) ^ pair_swz(lrow) : (lane & 7) ^ pair_swz8(q * RPI + lrow);
+    };
+    // instruction q of a stage (RPI rows) is issued by wave q % NW
     auto load = [&](int kt, char* Ab, char* Bb) {
 #pragma unroll
         for (int c = 0; c < LA; ++c) {
             const int q = wave + c * NW;
             if (NA % NW != 0 && q >= NA) break;
-            load_lds16(rsA, lds_address(Ab + q * 16 * BK),
-                       (uint32_t)((q * 16 + lrow) * a.ldu + kt * BK + lchunk * 16));
+            load_lds16(rsA, lds_address(Ab + q * 1024),
+                       (uint32_t)((q * RPI + lrow) * a.ldu + kt * BK + lchunk(q) * 16));
         }
 #pragma unroll
         for (int c = 0; c < LB; ++c) {
             const int q = wave + c * NW;
-            load_lds16(rsB, lds_address(Bb + q * 16 * BK),
-                       (uint32_t)((q * 16 + lrow) * a.ldx + kt * BK + lchunk * 16));
+            load_lds16(rsB, lds_address(Bb + q * 1024),
+                       (uint32_t)((q * RPI + lrow) * a.ldx + kt * BK + lchunk(q) * 16));
         }
     };
 
@@ -652,37 +663,41 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
 #pragma unroll
         for (int j = 0; j < WTN; ++j) acc[p][j] = i4_t{0, 0, 0, 0};
 
-    const int slot = (lg ^ pair_swz(li)) * 16;
     const bool more_a = NA % NW == 0 || wave < NA % NW;   // wave-uniform
     auto stage = [&](int kt, const char* Ar, const char* Br, char* An, char* Bn) {
         const bool ahead = kt + LOOK < nk;
         if (ahead) load(kt + LOOK, An, Bn);
-        u4_t fa[S], fb[WTN];
 #pragma unroll
-        for (int i = 0; i < S; ++i)
-            fa[i] = *reinterpret_cast<const u4_t*>(Ar + (wr * S * 16 + i * 16 + li) * BK + slot);
+        for (int ks = 0; ks < BK / 64; ++ks) {
+            // chunk 4 ks + lg of the fragment's rows (row bases are multiples of 16)
+            const int slot = (BK == 64 ? lg ^ pair_swz(li) : (4 * ks + lg) ^ pair_swz8(li)) * 16;
+            u4_t fa[S], fb[WTN];
 #pragma unroll
-        for (int j = 0; j < WTN; ++j)
-            fb[j] = *reinterpret_cast<const u4_t*>(Br + (wc * WTN * 16 + j * 16 + li) * BK + slot);
-        // hi digits against 127 (x - 1), then lo digits against x - 1, one
-        // dosage fragment at a time (its byte maps just before its
-        // instructions); the two instructions into one accumulator are
-        // WTN * NP instructions apart
+            for (int i = 0; i < S; ++i)
+                fa[i] = *reinterpret_cast<const u4_t*>(Ar + (wr * S * 16 + i * 16 + li) * BK + slot);
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int j = 0; j < WTN; ++j)
+                fb[j] = *reinterpret_cast<const u4_t*>(Br + (wc * WTN * 16 + j * 16 + li) * BK + slot);
+            // hi digits against 127 (x - 1), then lo digits against x - 1,
+            // one dosage fragment at a time (its byte maps just before its
+            // instructions); the two instructions into one accumulator are
+            // WTN * NP instructions apart
 #pragma unroll
-            for (int j = 0; j < WTN; ++j) {
-                u4_t xb;
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int w = 0; w < 4; ++w) xb[w] = h == 0 ? centred_hi(fb[j][w]) : centred_lo(fb[j][w]);
+                for (int j = 0; j < WTN; ++j) {
+                    u4_t xb;
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    if (2 * p + h >= S) continue;
-                    acc[p][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(reinterpret_cast<const i4_t&>(fa[2 * p + h]),
-                                                                     reinterpret_cast<const i4_t&>(xb), acc[p][j],
-                                                                     0, 0, 0);
+                    for (int w = 0; w < 4; ++w) xb[w] = h == 0 ? centred_hi(fb[j][w]) : centred_lo(fb[j][w]);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        if (2 * p + h >= S) continue;
+                        acc[p][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            reinterpret_cast<const i4_t&>(fa[2 * p + h]), reinterpret_cast<const i4_t&>(xb), acc[p][j],
+                            0, 0, 0);
+                    }
                 }
-            }
+        }
         // the stage's matrix instructions stay ahead of its barrier (the
         // compiler would sink them below it, and the wait for the next
         // stage's loads would no longer overlap them)
@@ -757,12 +772,13 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
 // 2, loaded straight into LDS with waves of 16 x 80 (32 x 320); paired
 // digits: 3, waves of 16 x 128 staged through registers (64 x 256); 4, the
 // same tile loaded straight into three LDS buffers; 5, 4 waves of 16 x 128
-// (32 x 256), two LDS buffers, two workgroups per CU.
-int trmm_sliced_cfgs() { return 6; }
+// (32 x 256), two LDS buffers, two workgroups per CU; 6, as 4 with 128-byte
+// stages in two LDS buffers (all 160 KB of a CU's LDS).
+int trmm_sliced_cfgs() { return 7; }
 TrmmShape trmm_sliced_shape(int cfg) {
     switch (cfg) {
         case 2: return TrmmShape{2 * 16, 4 * 5 * 16, 16, 512, 1, 32};
-        case 3: case 4: return TrmmShape{4 * 16, 2 * 8 * 16, 16, 512, 1, 32};
+        case 3: case 4: case 6: return TrmmShape{4 * 16, 2 * 8 * 16, 16, 512, 1, 32};
         case 5: return TrmmShape{2 * 16, 2 * 8 * 16, 16, 256, 1, 32};
         default: return TrmmShape{2 * 16, 4 * 4 * 16, 16, 512, 1, 32};
     }
@@ -781,8 +797,9 @@ hipError_t launch_sliced(const TrmmArgs& a, hipStream_t s) {
         else if (a.cfg == 1) hipLaunchKernelGGL((trmm_sliced_lds_kernel<S, 2, 4, 4, G>), grid, block, 0, s, a); \
         else if (a.cfg == 2) hipLaunchKernelGGL((trmm_sliced_lds_kernel<S, 2, 4, 5, G>), grid, block, 0, s, a); \
         else if (a.cfg == 3) hipLaunchKernelGGL((trmm_paired_kernel<S, 4, 2, 8, G>), grid, block, 0, s, a);    \
-        else if (a.cfg == 4) hipLaunchKernelGGL((trmm_paired_lds_kernel<S, 4, 2, 8, 3, G>), grid, block, 0, s, a); \
-        else if (a.cfg == 5) hipLaunchKernelGGL((trmm_paired_lds_kernel<S, 2, 2, 8, 2, G>), grid, block4, 0, s, a); \
+        else if (a.cfg == 4) hipLaunchKernelGGL((trmm_paired_lds_kernel<S, 4, 2, 8, 3, 64, G>), grid, block, 0, s, a); \
+        else if (a.cfg == 5) hipLaunchKernelGGL((trmm_paired_lds_kernel<S, 2, 2, 8, 2, 64, G>), grid, block4, 0, s, a); \
+        else if (a.cfg == 6) hipLaunchKernelGGL((trmm_paired_lds_kernel<S, 4, 2, 8, 2, 128, G>), grid, block, 0, s, a); \
         else return hipErrorInvalidValue;                                                               \
         return hipGetLastError();
     switch (a.slices) {

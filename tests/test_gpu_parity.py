@@ -295,7 +295,7 @@ def test_reduced_precision_vs_oracle(precision, tol):
     assert err < tol
 
 
-TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5, 7], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6], "int8": [0, 1, 2, 3, 4, 5]}
+TILE_SHAPES = {"fp64": [0, 1, 2, 3, 4, 5, 7], "fp32": [1, 2, 3, 5, 6], "bf16": [1, 2, 3, 5, 6], "int8": [0, 1, 2, 3, 4, 5, 6]}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
@@ -398,9 +398,9 @@ def test_int8_slices(slices, tol):
 def test_int8_slice_shapes_agree_bit_for_bit(n, p, m, dev_block, slices, monkeypatch):
     # the register-staged shape (0), the shapes that load straight into LDS
     # (1, and 2 with wider waves) and the paired-digit shapes (3 staged
-    # through registers, 4 and 5 loaded straight into three or two LDS
-    # buffers: two digits per accumulator against centred dosages, plus row
-    # sums) form
+    # through registers, 4 to 6 loaded straight into three or two LDS
+    # buffers, 6 with 128-byte stages: two digits per accumulator against
+    # centred dosages, plus row sums) form
     # the same exact integers per digit pair, so their results are equal
     # bit for bit; strided device dosages with garbage past n give the same
     # bits as compact ones
@@ -454,7 +454,7 @@ def test_int8_dosages_outside_0_1_2(n, m, dev_block, monkeypatch):
     b0, v0, i0 = run(prob, XR, **kw)
     bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
     assert np.array_equal(i0, io) and normwise(b0[io == 0], bo[io == 0]) < TOL_FP64
-    for cfg in (3, 4, 5):
+    for cfg in (3, 4, 5, 6):
         monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
         _say(f"  paired shape {cfg}")
         b, var, info = run(prob, XR, **kw)
