@@ -133,6 +133,7 @@ bool trmm_sliced_direct(int cfg);    // the shape loads its operands straight in
 bool trmm_sliced_paired(int cfg);    // the shape pairs digits against centred dosages
                                      // (dosages must be 0, 1 or 2)
 bool trmm_sliced_two_per_cu(int cfg); // the shape runs two workgroups per CU
+int trmm_sliced_default_cfg();        // the int8-slice shape used unless tuned
 // shape of the kernel that runs (at, xt, cfg, slices), with its schedule
 // grouping: rgroup row tiles per group, or the traffic model's choice for 0
 TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup = 0);

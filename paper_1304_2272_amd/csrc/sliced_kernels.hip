@@ -784,6 +784,12 @@ TrmmShape trmm_sliced_shape(int cfg) {
     }
 }
 bool trmm_sliced_two_per_cu(int cfg) { return cfg == 5; }
+// The paired-digit 64 x 256 tile with 128-byte stages in two LDS buffers,
+// one workgroup per CU: 0.509 of int8 peak at n = 50k and 100k, against
+// 0.493 and 0.496 with 64-byte stages in three buffers (shape 4); the
+// two-workgroup 32 x 256 shape is a little faster at 50k (0.50) but falls to
+// 0.33 from 75k on, and the unpaired register-staged tile gives 0.42-0.44.
+int trmm_sliced_default_cfg() { return 6; }
 bool trmm_sliced_paired(int cfg) { return cfg >= 3; }
 bool trmm_sliced_direct(int cfg) { return cfg == 1 || cfg == 2 || cfg >= 4; }
 

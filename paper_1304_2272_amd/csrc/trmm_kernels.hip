@@ -884,13 +884,7 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 // 128 x 256 tile and the reduced-precision products take the 128 x 128
 // tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
-    // int8 slices: the paired-digit 64 x 256 tile with 128-byte stages in two
-    // LDS buffers, one workgroup per CU (0.509 of int8 peak at n = 50k and
-    // 100k, against 0.493 and 0.496 with 64-byte stages in three buffers);
-    // the two-workgroup 32 x 256 shape is a little faster at 50k (0.50) but
-    // falls to 0.33 from 75k on, and the unpaired register-staged tile
-    // gives 0.42-0.44
-    if (at == A_I8S) return 6;
+    if (at == A_I8S) return trmm_sliced_default_cfg();
     if (at == A_F64) return xt == X_I8 ? 7 : 3;
     if (xt == X_I8) return 6;
     return 1;
