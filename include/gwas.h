@@ -154,7 +154,13 @@ typedef struct gwas_desc {
                                 W = w rounded up to a multiple of 256 rows
                                 (block bidiagonal) and each streamed block is
                                 solved by block forward substitution, about
-                                3 n W flops per SNP instead of n^2.
+                                3 n W flops per SNP instead of n^2.  With
+                                int8 dosages and W <= 1,024 a sub-block walks
+                                all block rows in one launch, Z on chip; else
+                                (or with the environment variable
+                                GWAS_BAND_STEP=1 at gwas_init, a measurement
+                                and test aid) one launch per block row, with
+                                the same results bit for bit.
                                 gwas_stream_group, gwas_autotune,
                                 gwas_stream_block_noalloc and the
                                 gwas_backward_* calls return GWAS_E_INVALID

@@ -227,6 +227,225 @@ __global__ __launch_bounds__(BT_NT) void band_step_kernel(BandArgs a) {
     }
 }
 
+// The whole block forward substitution of a sub-block in one launch, for
+// int8 dosages and blocks of W = 128 WTM rows (256 to 1,024).  Workgroup b
+// owns SNP columns [b TN, (b + 1) TN) and walks every block row; Z_{i-1} of
+// its columns stays in LDS as float64 from one block row to the next, and
+// the dosages of the block row sit there as bytes.  Wave w holds 16 WTM rows
+// of Z_i and streams the same rows of U_ii^T and Gt_i^T from global memory
+// (every workgroup reads the same block, so they come from L2) straight into
+// registers, one stage ahead: rows are not shared between waves, so inside
+// a block row no wave waits for another.  Two barriers per block row hand
+// Z_i over.  Waves w and w + 4 share a SIMD; they take row slices w and
+// 7 - w, so each SIMD gets the same share of the triangular U_ii^T part.
+// Per accumulator the matrix instructions, their K order (the triangular
+// part up to the wave's last row, then all of Gt_i^T) and the partial sums
+// per 32-row slice are those of band_step_kernel; the stages it runs past a
+// wave's last row multiply zeros of U_ii^T, so both kernels give the same
+// values.  MINW waves per SIMD: 4 for two workgroups per CU.
+template <int WTM, int WTN, int MINW>
+__global__ __launch_bounds__(512, MINW) void band_walk_kernel(BandArgs a) {
+    constexpr int NW = 8, RW = 16 * WTM, W = NW * RW, TN = 16 * WTN;
+    constexpr int ZS = W * 8 + 16;            // bytes per Z column in LDS
+    constexpr int XS = W + 16;                // bytes per dosage column in LDS
+    constexpr int XCH = TN * W / 16;          // 16-byte dosage chunks of a block row
+    constexpr int XPT = (XCH + 511) / 512;    // ... per thread
+    constexpr int NG = W / 16;                // stages of the Gt_i^T part
+    static_assert(WTM % 2 == 0, "32-row partial-sum slices");
+    __shared__ __attribute__((aligned(16))) char Zs[TN * ZS];
+    __shared__ __attribute__((aligned(16))) char Xs[TN * XS];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rb = (wave < 4 ? wave : 11 - wave) * RW;   // first row of this wave in a block
+    const int nU = rb / 16 + WTM;                          // stages of the U_ii^T part
+    const int64_t c0 = (int64_t)blockIdx.x * TN;
+    const int8_t* X = static_cast<const int8_t*>(a.X);
+    const int64_t WW = (int64_t)W * W;
+
+    // this thread's dosage chunks of block row i (zero past n and past the
+    // sub-block), loaded a block row ahead and held in registers while the
+    // block row before is done (XPRE), or, with the wave's 96 or 128 rows
+    // taking the registers, loaded when the block row before is done (its
+    // time then dwarfs the one wait)
+    constexpr bool XPRE = WTM <= 4;
+    u4_t xr[XPT];
+    auto xload = [&](int64_t i) {
+#pragma unroll
+        for (int c = 0; c < XPT; ++c) {
+            const int q = tid + 512 * c;
+            xr[c] = u4_t{0u, 0u, 0u, 0u};
+            if (XCH % 512 == 0 || q < XCH) {
+                const int64_t col = c0 + q / (W / 16);
+                const int64_t g = i * W + (q % (W / 16)) * 16;
+                if (col < a.cols) {
+                    const int8_t* src = X + col * a.ldx + g;
+                    if (g + 16 <= a.n) {
+                        xr[c] = *reinterpret_cast<const u4_t*>(src);
+                    } else {
+                        int8_t tmp[16] __attribute__((aligned(16)));
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) tmp[e] = g + e < a.n ? src[e] : (int8_t)0;
+                        xr[c] = *reinterpret_cast<const u4_t*>(tmp);
+                    }
+                }
+            }
+        }
+    };
+    auto xstore = [&]() {
+#pragma unroll
+        for (int c = 0; c < XPT; ++c) {
+            const int q = tid + 512 * c;
+            if (XCH % 512 == 0 || q < XCH)
+                *reinterpret_cast<u4_t*>(Xs + (q / (W / 16)) * XS + (q % (W / 16)) * 16) = xr[c];
+        }
+    };
+    // a lane's 4 doubles of K (4 lg ..) of its row in each 16-row fragment:
+    // stage s of block row i, of U_ii^T for s < nU, else of Gt_i^T
+    auto aload = [&](u4_t (&r)[WTM][2], int64_t i, int s) {
+        const bool pu = s < nU;
+        const double* base = (pu ? a.Ut : a.Gt) + i * WW + (int64_t)(rb + li) * W + 16 * (pu ? s : s - nU) + 4 * lg;
+#pragma unroll
+        for (int f = 0; f < WTM; ++f) {
+            r[f][0] = *reinterpret_cast<const u4_t*>(base + f * 16 * W);
+            r[f][1] = *reinterpret_cast<const u4_t*>(base + f * 16 * W + 2);
+        }
+    };
+
+    d4_t acc[WTM][WTN];
+#pragma unroll
+    for (int f = 0; f < WTM; ++f)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[f][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    auto stage = [&](const u4_t (&r)[WTM][2], int s) {
+        double fa[WTM][4];
+#pragma unroll
+        for (int f = 0; f < WTM; ++f) {
+            fa[f][0] = __builtin_bit_cast(double, u2_t{r[f][0][0], r[f][0][1]});
+            fa[f][1] = __builtin_bit_cast(double, u2_t{r[f][0][2], r[f][0][3]});
+            fa[f][2] = __builtin_bit_cast(double, u2_t{r[f][1][0], r[f][1][1]});
+            fa[f][3] = __builtin_bit_cast(double, u2_t{r[f][1][2], r[f][1][3]});
+        }
+        if (s < nU) {
+            // dosages of columns j*16 + li, K = 16 s + 4 lg + e
+            uint32_t fb[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                fb[j] = *reinterpret_cast<const uint32_t*>(Xs + (j * 16 + li) * XS + 16 * s + 4 * lg);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double xb[WTN];
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * e));
+#pragma unroll
+                for (int f = 0; f < WTM; ++f)
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j)
+                        acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[f][e], xb[j], acc[f][j], 0, 0, 0);
+            }
+        } else {
+            // Z_{i-1} of columns j*16 + li, K = 16 (s - nU) + 4 lg + e
+            double zb[WTN][4];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+                const char* p = Zs + (j * 16 + li) * ZS + (16 * (s - nU) + 4 * lg) * 8;
+                const u4_t lo = *reinterpret_cast<const u4_t*>(p);
+                const u4_t hi = *reinterpret_cast<const u4_t*>(p + 16);
+                zb[j][0] = __builtin_bit_cast(double, u2_t{lo[0], lo[1]});
+                zb[j][1] = __builtin_bit_cast(double, u2_t{lo[2], lo[3]});
+                zb[j][2] = __builtin_bit_cast(double, u2_t{hi[0], hi[1]});
+                zb[j][3] = __builtin_bit_cast(double, u2_t{hi[2], hi[3]});
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int f = 0; f < WTM; ++f)
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j)
+                        acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[f][e], zb[j][e], acc[f][j], 0, 0, 0);
+        }
+    };
+
+    u4_t ra[WTM][2], rn[WTM][2];
+    xload(0);
+    xstore();
+    if (XPRE && a.nb > 1) xload(1);
+    aload(ra, 0, 0);
+    __syncthreads();
+    const int Q = a.Qc + 1;
+    for (int64_t i = 0; i < a.nb; ++i) {
+        // nU and NG are even, so stages go in pairs and ra ends up holding
+        // stage 0 of the next block row
+        const int nS = nU + (i > 0 ? NG : 0);
+        for (int s = 0; s < nS; s += 2) {
+            aload(rn, i, s + 1);
+            stage(ra, s);
+            if (s + 2 < nS) aload(ra, i, s + 2);
+            else if (i + 1 < a.nb) aload(ra, i + 1, 0);
+            stage(rn, s + 1);
+        }
+        // every wave is done with Z_{i-1} and the dosages of block row i
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < WTM; ++f)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    *reinterpret_cast<double*>(Zs + (j * 16 + li) * ZS + (rb + f * 16 + lg + 4 * v) * 8) =
+                        acc[f][j][v];
+        if (i + 1 < a.nb) {
+            if (!XPRE) xload(i + 1);
+            xstore();
+            if (XPRE && i + 2 < a.nb) xload(i + 2);
+        }
+        // partial sums per 32-row slice (rows i W + rb + 32 h ..)
+#pragma unroll
+        for (int h = 0; h < WTM / 2; ++h) {
+            const int64_t rw = i * W + rb + 32 * h;
+            const int64_t pb = rw / 32;
+            for (int qq = 0; qq < a.Qc; ++qq) {
+                const double* Cq = a.C + qq * a.ldc + rw + lg;
+                double cv[2][4];
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) cv[f][v] = Cq[f * 16 + 4 * v];
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 2; ++f)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) sum += acc[2 * h + f][j][v] * cv[f][v];
+                    sum = wave_sum16(sum);
+                    const int64_t col = c0 + j * 16 + li;
+                    if (lg == 0 && col < a.cols) a.part[(pb * Q + qq) * a.ldp + col] = sum;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+                double sum = 0.0;
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sum += acc[2 * h + f][j][v] * acc[2 * h + f][j][v];
+                sum = wave_sum16(sum);
+                const int64_t col = c0 + j * 16 + li;
+                if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < WTM; ++f)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) acc[f][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        // Z_i and the next block row's dosages are in place
+        __syncthreads();
+    }
+}
+
 // Block (row0.., col0..) of M, rows x cols, from LAPACK lower band storage
 // (M(i, j) at AB[(i - j) + j*ldab] for j <= i <= j + w): entries above the
 // diagonal, outside the band or past n are zero, the diagonal past n one.
@@ -270,6 +489,48 @@ hipError_t band_step(const BandArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(band_step_kernel<int8_t>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
     else
         hipLaunchKernelGGL(band_step_kernel<double>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+bool band_walk_fits(int xt, int64_t W) { return xt == X_I8 && W >= 256 && W <= 1024; }
+
+hipError_t band_walk(const BandArgs& a, hipStream_t s) {
+    if (a.cols <= 0) return hipSuccess;
+    if (!band_walk_fits(a.xt, a.W) || a.nb < 1 || !a.Ut || !a.Gt || !a.X || !a.part || !a.C)
+        return hipErrorInvalidValue;
+    if (a.n < 1 || a.n > a.nb * a.W || a.ldx < a.n || a.ldp < a.cols || a.ldc < a.nb * a.W || a.Qc < 1)
+        return hipErrorInvalidValue;
+    // 16-byte dosage chunks: the array, its stride and every block's first
+    // row are 16-byte aligned; so are the rows of U_ii^T and Gt_i^T
+    if ((reinterpret_cast<uintptr_t>(a.X) % 16) || (a.ldx % 16) || (reinterpret_cast<uintptr_t>(a.Ut) % 16) ||
+        (reinterpret_cast<uintptr_t>(a.Gt) % 16))
+        return hipErrorInvalidValue;
+    // columns per workgroup: 32 once a sub-block fills the chip with them,
+    // else 16; 16 always for W of 768 and 1,024, whose Z columns fill the
+    // LDS.  W = 256: two workgroups per CU (75 KB of LDS, at most 128 VGPRs
+    // each); larger W keeps 64 to 128 rows per wave in more registers, one
+    // workgroup per CU.
+    const bool wide = a.cols > 8192;
+    const int tn = wide ? 32 : 16;
+    const int64_t grid = (a.cols + tn - 1) / tn;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    if (a.W == 256) {
+        if (wide)
+            hipLaunchKernelGGL((band_walk_kernel<2, 2, 4>), dim3((unsigned)grid), dim3(512), 0, s, a);
+        else
+            hipLaunchKernelGGL((band_walk_kernel<2, 1, 4>), dim3((unsigned)grid), dim3(512), 0, s, a);
+    } else if (a.W == 512) {
+        if (wide)
+            hipLaunchKernelGGL((band_walk_kernel<4, 2, 2>), dim3((unsigned)grid), dim3(512), 0, s, a);
+        else
+            hipLaunchKernelGGL((band_walk_kernel<4, 1, 2>), dim3((unsigned)grid), dim3(512), 0, s, a);
+    } else if (a.W == 768) {
+        const int64_t g16 = (a.cols + 15) / 16;
+        hipLaunchKernelGGL((band_walk_kernel<6, 1, 2>), dim3((unsigned)g16), dim3(512), 0, s, a);
+    } else {
+        const int64_t g16 = (a.cols + 15) / 16;
+        hipLaunchKernelGGL((band_walk_kernel<8, 1, 2>), dim3((unsigned)g16), dim3(512), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -262,6 +262,7 @@ struct gwas_ctx {
     hipEvent_t ev_join = nullptr;   // grouped calls: this context's per-SNP work is done
     int at = A_F64;
     int cfg = 0;
+    bool band_walk = false;         // banded M: all block rows of a sub-block in one launch
     int64_t sub = 0;                // sub-block width of gwas_stream_block (dev_block, or the autotuner's)
     int rgroup = 0;                 // schedule row group (0: the traffic model's choice)
     char* xbuf[2] = {nullptr, nullptr};
@@ -939,6 +940,11 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->shape = trmm_geom(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c->cfg, slices);
     // the banded product has its own fixed tile (128 x 128, 32-row slices)
     if (d->band > 0) c->shape = TrmmShape{128, 128, band_part_rows(), 512, 1, 32};
+    if (d->band > 0) {
+        c->band_walk = band_walk_fits(d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, Y.W);
+        // one launch per block row instead, for measurement and tests
+        if (const char* e = getenv("GWAS_BAND_STEP")) c->band_walk = c->band_walk && atoi(e) == 0;
+    }
     auto bail = [&](int code) {
         release(c);
         c->magic = CTX_DEAD;
@@ -1042,6 +1048,24 @@ int settle(gwas_ctx* c) {
 // product's.
 hipError_t band_product(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, hipStream_t s) {
     const Layout& Y = c->lay;
+    if (c->band_walk) {
+        BandArgs ba{};
+        ba.xt = X_I8;
+        ba.W = Y.W;
+        ba.nb = Y.nb;
+        ba.Ut = c->Ub;
+        ba.Gt = c->Gt;
+        ba.X = xptr;
+        ba.ldx = xld;
+        ba.n = Y.n;
+        ba.cols = cols;
+        ba.C = c->C;
+        ba.ldc = Y.n_pad;
+        ba.Qc = Y.Qc;
+        ba.part = c->part;
+        ba.ldp = Y.dev_block;
+        return band_walk(ba, s);
+    }
     for (int64_t i = 0; i < Y.nb; ++i) {
         BandArgs ba{};
         ba.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;

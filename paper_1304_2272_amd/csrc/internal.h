@@ -209,7 +209,7 @@ hipError_t snp_backward(const BackArgs& a, hipStream_t s);
 //   C    n_pad x Qc whitened [Xbar_L | Ybar], ld ldc
 struct BandArgs {
     int xt;
-    int64_t W, blk;
+    int64_t W, blk, nb;           // block order, block row (band_step), block rows (band_walk)
     const double* Ut; const double* Gt;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const double* Zprev; double* Zcur; int64_t ldz;
@@ -217,7 +217,13 @@ struct BandArgs {
     double* part; int64_t ldp;
 };
 hipError_t band_step(const BandArgs& a, hipStream_t s);
-int band_part_rows();   // rows per partial-sum slice of band_step (32)
+int band_part_rows();   // rows per partial-sum slice of band_step and band_walk (32)
+// All nb block rows of a sub-block in one launch (int8 dosages, W of 256 to
+// 1,024: band_walk_fits): Ut and Gt point at block row 0's U_00 and Gt_0, Z
+// stays on chip (Zprev, Zcur unused); the same partial sums as nb calls of
+// band_step.
+bool band_walk_fits(int xt, int64_t W);
+hipError_t band_walk(const BandArgs& a, hipStream_t s);
 // out (rows x cols, ld ldo) = block (row0.., col0..) of the SPD M given in
 // LAPACK lower band storage of half-bandwidth w (M(i,j) at AB[(i-j) + j*ldab],
 // j <= i <= j + w); zero above the diagonal and outside the band, identity

@@ -102,3 +102,40 @@ def test_banded_calls_that_need_the_dense_factor_are_refused():
             assert ei.value.code == 1
         b, _, info = ctx.stream_block(XR)        # the context stays usable
         assert (info == 0).all()
+
+
+@pytest.mark.parametrize("n,w,p,m", [
+    (3000, 200, 5, 9000),      # W = 256, 12 block rows; 32 columns per workgroup, ragged last workgroup
+    (2600, 400, 4, 9000),      # W = 512, 6 block rows (the last one partly past n)
+    (1100, 256, 3, 700),       # W = 256, 5 block rows; 16 columns per workgroup
+    (2000, 700, 3, 600),       # W = 768, 3 block rows
+    (2500, 1000, 4, 300),      # W = 1,024, 3 block rows
+])
+def test_banded_one_launch_equals_block_row_launches(n, w, p, m, monkeypatch):
+    # int8 dosages with W of 256 to 1,024 run every block row of a sub-block
+    # in one launch, Z kept on chip; the launch per block row (GWAS_BAND_STEP=1)
+    # gives the same bits, a SNP's result does not depend on the call it
+    # comes in, and a sample of SNPs agrees with the oracle on the dense M
+    seed = 5500 + n + w
+    _say(f"banded one launch n={n} w={w} p={p} m={m}")
+    prob = synth.banded_problem(n, p, seed, w)
+    XR = synth.snp_block(n, seed, 0, m, dtype=np.int8)
+    monkeypatch.delenv("GWAS_BAND_STEP", raising=False)
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], x_dtype="i8", band=w) as ctx:
+        b1, v1, i1 = ctx.stream_block(XR)
+        cut = m - 513 if m > 8192 else m // 3
+        parts = [ctx.stream_block(XR[:cut]), ctx.stream_block(XR[cut:])]
+    monkeypatch.setenv("GWAS_BAND_STEP", "1")
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], x_dtype="i8", band=w) as ctx:
+        b2, v2, i2 = ctx.stream_block(XR)
+    assert (i1 == 0).all() and np.array_equal(i1, i2)
+    assert np.array_equal(b1, b2) and np.array_equal(v1, v2)
+    assert np.array_equal(np.concatenate([q[0] for q in parts]), b1)
+    assert np.array_equal(np.concatenate([q[1] for q in parts]), v1)
+    rng = np.random.default_rng(seed)
+    pick = np.unique(np.concatenate([[0, 31, 32, m - 1], rng.choice(m, 60, replace=False)]))
+    bo, vo, io = GLSOracle(synth.band_to_dense(prob["M_band"]), prob["XL"], prob["Y"]).solve(XR[pick])
+    err = normwise(b1[pick], bo)
+    verr = float(np.max(np.abs(v1[pick] - vo) / vo))
+    _say(f"  bit-equal to the per-block-row launches; oracle sample normwise {err:.3e}, var {verr:.3e}")
+    assert err < TOL and verr < TOL
