@@ -434,8 +434,10 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
     """Banded M (relatives grouped near the diagonal, Section 5.1) at
     n = 50,000, p = 8: for each half-bandwidth w, int8 dosages in pinned host
     memory queued as in the main legs.  The algorithmic work of a banded
-    forward substitution is 2 n w flops per SNP; the kernels run
-    n_pad (3 W + 128) with blocks of W = w rounded up to 256 rows."""
+    forward substitution is 2 n w flops per SNP; with blocks of W = w rounded
+    up to 256 rows the kernels run 3.125 n_pad W (int8 dosages with W up to
+    1,024: one launch per sub-block, each wave's triangular part stopping at
+    its own rows) or n_pad (3 W + 128) (one launch per block row)."""
     import torch
     from paper_1304_2272_amd import binding, synth
     dev = torch.device("cuda:0")
@@ -468,15 +470,20 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
         n_pad = ctx.query()["n_pad"]
         ctx.close()
         W = -(-w // 256) * 256
+        # the library's choice of kernel for int8 dosages (GWAS_BAND_STEP=1
+        # forces the launch per block row)
+        walk = W <= 1024 and int(os.environ.get("GWAS_BAND_STEP", "0") or 0) == 0
         alg = 2.0 * n * w * kcols / (kms * 1e-3) / 1e12
-        exe = float(n_pad) * (3 * W + 128) * kcols / (kms * 1e-3) / 1e12
+        exe = float(n_pad) * (3.125 * W if walk else 3 * W + 128) * kcols / (kms * 1e-3) / 1e12
         rate = steps * step / el
         res[str(w)] = {"snps_per_s": rate, "init_s": init_s, "block_order": W, "n_pad": n_pad,
                        "product_ms_per_sub_block": kms / max(launches, 1),
                        "roofline": {"bound": "mfma", "achieved": alg, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                                     "frac": alg / PEAK_TFLOPS["fp64"],
                                     "work": "algorithmic 2 n w flops per SNP"},
-                       "executed_tflops": exe, "rank_flags": int((oi.numpy()[:steps * step] != 0).sum())}
+                       "executed_tflops": exe, "executed_frac": exe / PEAK_TFLOPS["fp64"],
+                       "kernel": "one launch per sub-block" if walk else "one launch per block row",
+                       "rank_flags": int((oi.numpy()[:steps * step] != 0).sum())}
         log(f"[banded w={w}] init {init_s:.2f} s, {rate:.1f} SNP/s; product {alg:.2f} TFLOP/s algorithmic "
             f"(2nw), {exe:.2f} executed ({exe / PEAK_TFLOPS['fp64']:.3f} of peak)")
         del Mb, XL, Y, pr
