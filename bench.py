@@ -552,12 +552,19 @@ def run_main(args):
     h2d_peak = pinned_h2d_peak()
 
     others = {}
+    pick = set(x for x in args.other_workloads.split(",") if x)
     if not args.no_other_workloads and args.workload == "n50000_p8":
-        others["n1000_p4"] = compact_c1(args.seed + 1)
-        others["n20000_p4"] = compact_c2(args.seed + 2, args.c2_blocks)
-        others["cohorts8_t64"] = compact_c4(args.seed + 3, args.c4_steps)
-        others["n10000_p4_grad"] = compact_c5(args.seed + 4)
-        others["banded_n50000_p8"] = compact_banded(args.seed + 5, [int(x) for x in args.band_widths.split(",") if x])
+        if "n1000_p4" in pick:
+            others["n1000_p4"] = compact_c1(args.seed + 1)
+        if "n20000_p4" in pick:
+            others["n20000_p4"] = compact_c2(args.seed + 2, args.c2_blocks)
+        if "cohorts8_t64" in pick:
+            others["cohorts8_t64"] = compact_c4(args.seed + 3, args.c4_steps)
+        if "n10000_p4_grad" in pick:
+            others["n10000_p4_grad"] = compact_c5(args.seed + 4)
+        if "banded_n50000_p8" in pick:
+            others["banded_n50000_p8"] = compact_banded(args.seed + 5,
+                                                        [int(x) for x in args.band_widths.split(",") if x])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -614,6 +621,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1306)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")
+    ap.add_argument("--other-workloads", default="n1000_p4,n20000_p4,cohorts8_t64,n10000_p4_grad,banded_n50000_p8",
+                    help="which compact workloads follow the main one")
     ap.add_argument("--c2-blocks", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--band-widths", default="256,1024,4096", help="half-bandwidths of the banded-M leg")
