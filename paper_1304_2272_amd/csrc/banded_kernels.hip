@@ -236,8 +236,9 @@ __global__ __launch_bounds__(BT_NT) void band_step_kernel(BandArgs a) {
 // (every workgroup reads the same block, so they come from L2) straight into
 // registers, one stage ahead: rows are not shared between waves, so inside
 // a block row no wave waits for another.  Two barriers per block row hand
-// Z_i over.  Waves w and w + 4 share a SIMD; they take row slices w and
-// 7 - w, so each SIMD gets the same share of the triangular U_ii^T part.
+// Z_i over.  The waves of a workgroup are dealt to the four SIMDs in turn,
+// so waves w and w + 4 share one; they take row slices w and 7 - w, and
+// each SIMD gets the same share of the triangular U_ii^T part.
 // Per accumulator the matrix instructions, their K order (the triangular
 // part up to the wave's last row, then all of Gt_i^T) and the partial sums
 // per 32-row slice are those of band_step_kernel; the stages it runs past a

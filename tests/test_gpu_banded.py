@@ -29,6 +29,7 @@ def normwise(b, bref):
     (700, 650, 3, 2, 400, "f64", 128),      # one block row (W = 768 >= n), two traits
     (5000, 1000, 3, 1, 900, "i8", 0),       # W = 1024, 5 block rows
     (1290, 256, 5, 1, 333, "f64", 128),     # w = W exactly
+    (1800, 400, 4, 3, 500, "i8", 0),        # W = 512 in one launch, three traits
 ])
 def test_banded_vs_oracle(n, w, p, t, m, x_dtype, dev_block):
     seed = 5100 + n + w
