@@ -337,8 +337,8 @@ int gwas_stream_group(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
  * a pair into one sum against centred dosages, 3 staging through registers,
  * 4 to 6 loading straight into three or two LDS buffers, 6 (128-byte
  * stages) the default;
- * for GWAS_FP64 with int8 dosages, 7, the default, loads both operands
- * straight into LDS); *best_rgroup (may be NULL) the row group.
+ * for GWAS_FP64, 7, the default, loads both operands straight into LDS,
+ * int8 or float64 dosages); *best_rgroup (may be NULL) the row group.
  * For GWAS_FP64 and GWAS_INT8_SLICED, results of later calls are unchanged
  * up to float64 rounding order.  For the float32 and bfloat16 products a
  * shape also decides how their sums are kept: the 256 x 256 shape (6, the

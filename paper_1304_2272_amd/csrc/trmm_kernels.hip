@@ -593,20 +593,30 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 // or past n (identity rows of the padded L^-1 meet whatever follows a
 // column past n) are zeroed before the sums.  The tile and the partial-sum
 // layout are those of the 128 x 128 shape of 32 x 64 waves.
+//
+// With float64 dosages (XT = double) the dosage columns take the layout of
+// the rows of L^-1 (128 bytes a stage, groups of 8 columns, the same
+// swizzle), a stage holds 32 KB, and two buffers (loads one stage ahead)
+// keep two workgroups per CU; elements k >= n of the last stage are zeroed
+// in registers, since the bytes past a column's n belong to whatever
+// follows it.
 __device__ __forceinline__ int f64_slot(int r8, int c, int parity) {
     return (c >> 1) * 16 + (((c & 1) ^ parity) << 3) + r8;
 }
 
-template <bool GROUPED>
-__global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
+template <typename XT, bool GROUPED>
+__global__ __launch_bounds__(512, sizeof(XT) == 8 ? 4 : 2) void trmm_f64_lds_kernel(TrmmArgs la) {
     typedef MM<double> T;
+    constexpr bool XD = sizeof(XT) == 8;
+    constexpr int NBUF = XD ? 2 : 3, LOOK = NBUF - 1;
     constexpr int WGM = 4, WGN = 2, WTM = 2, WTN = 4;
     constexpr int TM = WGM * WTM * 16, TN = WGN * WTN * 16, NW = WGM * WGN;
     constexpr int BK = 16;                         // K per stage
     constexpr int AB = TM * BK * 8;                // bytes of L^-1 per stage buffer
-    constexpr int XBB = TN * BK;                   // bytes of dosages per stage buffer
-    constexpr int NA = TM / 8, NB = TN / 64;       // load instructions per stage (1 KB each)
-    static_assert(NA % NW == 0 && NB <= NW, "load instructions per wave");
+    constexpr int XBB = TN * BK * (int)sizeof(XT); // bytes of dosages per stage buffer
+    // load instructions per stage (1 KB each): L^-1, dosages
+    constexpr int NA = TM / 8, NB = XD ? TN / 8 : TN / 64;
+    static_assert(NA % NW == 0 && (XD ? NB % NW == 0 : NB <= NW), "load instructions per wave");
     constexpr int LA = NA / NW;
     // s_waitcnt immediates: vmcnt(this wave's loads per stage) or vmcnt(0),
     // with lgkmcnt(0) and any expcnt; waves below NB issue one dosage load
@@ -621,12 +631,14 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
     const TrmmArgs a = GROUPED ? la.group[e0 >> SCHED_CTX_SHIFT] : la;
     if ((int64_t)J * TN >= a.cols) return;
 
-    __shared__ __attribute__((aligned(1024))) char A0[AB];
-    __shared__ __attribute__((aligned(1024))) char A1[AB];
-    __shared__ __attribute__((aligned(1024))) char A2[AB];
-    __shared__ __attribute__((aligned(1024))) char B0[XBB];
-    __shared__ __attribute__((aligned(1024))) char B1[XBB];
-    __shared__ __attribute__((aligned(1024))) char B2[XBB];
+    __shared__ __attribute__((aligned(1024))) char Abuf[NBUF][AB];
+    __shared__ __attribute__((aligned(1024))) char Bbuf[NBUF][XBB];
+    char* const A0 = Abuf[0];
+    char* const A1 = Abuf[1];
+    char* const A2 = Abuf[NBUF - 1];
+    char* const B0 = Bbuf[0];
+    char* const B1 = Bbuf[1];
+    char* const B2 = Bbuf[NBUF - 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -641,10 +653,12 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
 
     const u4_t rsA = buffer_words(reinterpret_cast<const char*>(a.Ut) + r0 * row_bytes, (uint32_t)(TM * row_bytes));
     const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
-    const int64_t xbytes = ((xcols - 1) * a.ldx + a.n + 15) / 16 * 16;
-    const u4_t rsB = buffer_words(reinterpret_cast<const int8_t*>(a.X) + c0 * a.ldx, (uint32_t)xbytes);
+    const int64_t xbytes = (((xcols - 1) * a.ldx + a.n) * (int64_t)sizeof(XT) + 15) / 16 * 16;
+    const u4_t rsB = buffer_words(reinterpret_cast<const char*>(a.X) + c0 * a.ldx * (int64_t)sizeof(XT),
+                                  (uint32_t)xbytes);
     // lane l of an L^-1 load instruction (group q of 8 rows) fetches the
-    // chunk that belongs in slot l; lane l of a dosage load, column l of its 64
+    // chunk that belongs in slot l; lane l of an int8 dosage load, column l
+    // of its 64 (float64 dosages: as L^-1, groups of 8 columns)
     const int lr8 = lane & 7;
     const int lc_even = 2 * (lane >> 4) + ((lane >> 3) & 1);       // chunk for an even group
     const int lc_odd = 2 * (lane >> 4) + (((lane >> 3) & 1) ^ 1);  // chunk for an odd group
@@ -657,9 +671,17 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
             load_lds16(rsA, lds_address(Ab + q * 1024),
                        (uint32_t)((q * 8 + lr8) * row_bytes + kt * (BK * 8) + ch * 16));
         }
-        if (has_b)
-            load_lds16(rsB, lds_address(Bb + wave * 1024),
-                       (uint32_t)((wave * 64 + lane) * a.ldx + kt * BK));
+        if constexpr (XD) {
+#pragma unroll
+            for (int c = 0; c < NB / NW; ++c) {
+                const int q = wave + c * NW;
+                const int ch = (q & 1) ? lc_odd : lc_even;
+                load_lds16(rsB, lds_address(Bb + q * 1024),
+                           (uint32_t)((q * 8 + lr8) * a.ldx * 8 + kt * (BK * 8) + ch * 16));
+            }
+        } else if (has_b) {
+            load_lds16(rsB, lds_address(Bb + wave * 1024), (uint32_t)((wave * 64 + lane) * a.ldx + kt * BK));
+        }
     };
 
     d4_t acc[WTM][WTN];
@@ -679,35 +701,75 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
         for (int h = 0; h < 2; ++h) aoff[i][h] = (row >> 3) * 1024 + f64_slot(row & 7, 2 * lg + h, (row >> 3) & 1) * 16;
     }
     const int boff = (wc * WTN * 16 + li) * BK + lg * 4;
+    int boffd[WTN][2];                   // float64 dosages: columns laid out as rows of L^-1
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        const int col = wc * WTN * 16 + j * 16 + li;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) boffd[j][h] = (col >> 3) * 1024 + f64_slot(col & 7, 2 * lg + h, (col >> 3) & 1) * 16;
+    }
 
     auto stage = [&](int kt, const char* Ar, const char* Br, char* An, char* Bn) {
-        const bool ahead = kt + 2 < nk;
-        if (ahead) load(kt + 2, An, Bn);
-        u4_t fa[WTM][2];
-        uint32_t fb[WTN];
+        const bool ahead = kt + LOOK < nk;
+        if (ahead) load(kt + LOOK, An, Bn);
+        if constexpr (XD) {
+            // float64 dosages: K = 16 kt + 4 lg + st at or past n reads as
+            // zero; one 16-byte piece (two K) of each fragment at a time
+            const int kl = (int)a.n - (kt * BK + 4 * lg);
 #pragma unroll
-        for (int i = 0; i < WTM; ++i)
+            for (int h = 0; h < 2; ++h) {
+                u4_t fa[WTM], fd[WTN];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) fa[i][h] = *reinterpret_cast<const u4_t*>(Ar + aoff[i][h]);
+                for (int i = 0; i < WTM; ++i) fa[i] = *reinterpret_cast<const u4_t*>(Ar + aoff[i][h]);
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + boff + j * 16 * BK);
+                for (int j = 0; j < WTN; ++j) fd[j] = *reinterpret_cast<const u4_t*>(Br + boffd[j][h]);
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            double xb[WTN];
+                for (int e = 0; e < 2; ++e) {
+                    const int st = 2 * h + e;
+                    double xb[WTN];
 #pragma unroll
-            for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * st));
+                    for (int j = 0; j < WTN; ++j) {
+                        const u2_t x2 = e ? u2_t{fd[j][2], fd[j][3]} : u2_t{fd[j][0], fd[j][1]};
+                        xb[j] = st < kl ? __builtin_bit_cast(double, x2) : 0.0;
+                    }
 #pragma unroll
-            for (int i = 0; i < WTM; ++i) {
-                const u2_t w2 = (st & 1) ? u2_t{fa[i][st >> 1][2], fa[i][st >> 1][3]}
-                                         : u2_t{fa[i][st >> 1][0], fa[i][st >> 1][1]};
-                const double av = __builtin_bit_cast(double, w2);
+                    for (int i = 0; i < WTM; ++i) {
+                        const u2_t w2 = e ? u2_t{fa[i][2], fa[i][3]} : u2_t{fa[i][0], fa[i][1]};
+                        const double av = __builtin_bit_cast(double, w2);
 #pragma unroll
-                for (int j = 0; j < WTN; ++j) acc[i][j] = T::mma(av, xb[j], acc[i][j]);
+                        for (int j = 0; j < WTN; ++j) acc[i][j] = T::mma(av, xb[j], acc[i][j]);
+                    }
+                }
+            }
+        } else {
+            u4_t fa[WTM][2];
+            uint32_t fb[WTN];
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) fa[i][h] = *reinterpret_cast<const u4_t*>(Ar + aoff[i][h]);
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + boff + j * 16 * BK);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                double xb[WTN];
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * st));
+#pragma unroll
+                for (int i = 0; i < WTM; ++i) {
+                    const u2_t w2 = (st & 1) ? u2_t{fa[i][st >> 1][2], fa[i][st >> 1][3]}
+                                             : u2_t{fa[i][st >> 1][0], fa[i][st >> 1][1]};
+                    const double av = __builtin_bit_cast(double, w2);
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j) acc[i][j] = T::mma(av, xb[j], acc[i][j]);
+                }
             }
         }
         // the stage's matrix instructions stay ahead of its barrier
         __builtin_amdgcn_sched_barrier(0);
-        if (!ahead) __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+        // three buffers: wait only for stage kt + 1 (kt + 2 stays in
+        // flight); two: for everything
+        if (LOOK == 1 || !ahead) __builtin_amdgcn_s_waitcnt(WAIT_ALL);
         else if (has_b) __builtin_amdgcn_s_waitcnt(WAIT_MORE);
         else __builtin_amdgcn_s_waitcnt(WAIT_LESS);
         compiler_fence();
@@ -716,7 +778,7 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
     };
 
     load(0, A0, B0);
-    if (nk > 1) {
+    if (LOOK == 2 && nk > 1) {
         load(1, A1, B1);
         if (has_b) __builtin_amdgcn_s_waitcnt(WAIT_MORE);
         else __builtin_amdgcn_s_waitcnt(WAIT_LESS);
@@ -726,10 +788,17 @@ __global__ __launch_bounds__(512, 2) void trmm_f64_lds_kernel(TrmmArgs la) {
     compiler_fence();
     __builtin_amdgcn_s_barrier();
     compiler_fence();
-    for (int kt = 0; kt < nk; kt += 3) {
-        stage(kt, A0, B0, A2, B2);
-        if (kt + 1 < nk) stage(kt + 1, A1, B1, A0, B0);
-        if (kt + 2 < nk) stage(kt + 2, A2, B2, A1, B1);
+    if constexpr (NBUF == 3) {
+        for (int kt = 0; kt < nk; kt += 3) {
+            stage(kt, A0, B0, A2, B2);
+            if (kt + 1 < nk) stage(kt + 1, A1, B1, A0, B0);
+            if (kt + 2 < nk) stage(kt + 2, A2, B2, A1, B1);
+        }
+    } else {
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(kt, A0, B0, A1, B1);
+            if (kt + 1 < nk) stage(kt + 1, A1, B1, A0, B0);
+        }
     }
 
     // Epilogue (as the staged float64 tiles): per column, sums over this
@@ -824,9 +893,15 @@ hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
         case 7:
             if constexpr (F64 && I8) {
                 if (a.group)
-                    hipLaunchKernelGGL((trmm_f64_lds_kernel<true>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<int8_t, true>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
                 else
-                    hipLaunchKernelGGL((trmm_f64_lds_kernel<false>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<int8_t, false>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                return hipGetLastError();
+            } else if constexpr (F64) {
+                if (a.group)
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<double, true>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
+                else
+                    hipLaunchKernelGGL((trmm_f64_lds_kernel<double, false>), dim3((unsigned)a.n_sched), dim3(512), 0, s, a);
                 return hipGetLastError();
             } else {
                 return hipErrorInvalidValue;
@@ -861,8 +936,8 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
     // 64 x 128 waves fit two per SIMD only with float32 sums and int8 dosages
     if (cfg == 6) return at != A_F64 && xt == X_I8;
-    // float64 with int8 dosages loaded straight into LDS
-    if (cfg == 7) return at == A_F64 && xt == X_I8;
+    // float64 loaded straight into LDS
+    if (cfg == 7) return at == A_F64;
     if (at == A_F64) return true;
     // The reduced-precision products also carry float64 partial sums; 64 x 64
     // waves of them only fit two waves per SIMD without spilling when the
@@ -880,12 +955,14 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 // (141 and 1,180 TFLOP/s, against 131 and 870 in the 128 x 256 tile with
 // float64 sums; b moves from 6e-11 to 4e-10 of the float64 path for
 // float32, and not measurably for bfloat16, whose rounding of L^-1
-// dominates).  With float64 dosages the float64 product keeps the
-// 128 x 256 tile and the reduced-precision products take the 128 x 128
-// tile of 64 x 32 waves.
+// dominates).  With float64 dosages the float64 product is faster loaded
+// straight into LDS too (shape 7 against the 128 x 256 register-staged
+// tile: 0.845 against 0.804 of peak at n = 50,000, 0.753 against 0.707 at
+// n = 20,000 in calls of 5,000 SNPs), and the reduced-precision products
+// take the 128 x 128 tile of 64 x 32 waves.
 int trmm_default_cfg(int at, int xt) {
     if (at == A_I8S) return trmm_sliced_default_cfg();
-    if (at == A_F64) return xt == X_I8 ? 7 : 3;
+    if (at == A_F64) return 7;
     if (xt == X_I8) return 6;
     return 1;
 }

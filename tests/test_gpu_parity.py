@@ -321,6 +321,36 @@ def test_every_tile_shape(precision, monkeypatch):
             assert normwise(b, ref) < 1e-13
 
 
+@pytest.mark.parametrize("n,m,dev_block", [(3000, 700, 384), (1290, 300, 128)])
+def test_fp64_direct_load_float64_dosages(n, m, dev_block, monkeypatch):
+    # the float64 tile loaded straight into LDS (7) with float64 dosages,
+    # non-integer ones included, against the oracle; the elements past n of
+    # each column (NaN here) never reach the sums, so a strided block gives
+    # the bits of a packed one; the register-staged tile (3) agrees to
+    # rounding
+    import torch
+    p, seed = 5, 812
+    prob = synth.make_problem(n, p, seed, k=max(50, n // 3))
+    XR = synth.snp_block(n, seed, 0, m)
+    XR[::3] += np.random.default_rng(seed).uniform(-0.4, 0.4, size=XR[::3].shape)   # imputed dosages
+    monkeypatch.setenv("GWAS_TRMM_CFG", "7")
+    _say(f"fp64 shape 7, float64 dosages n={n} m={m} dev_block={dev_block}")
+    b, var, info = run(prob, XR, precision="fp64", x_dtype="f64", dev_block=dev_block)
+    dev = torch.device("cuda:0")
+    big = torch.full((m, n + 48), float("nan"), dtype=torch.float64, device=dev)
+    big[:, :n] = torch.from_numpy(XR).to(dev)
+    bs, vs, is_ = run(prob, big[:, :n], precision="fp64", x_dtype="f64", dev_block=dev_block)
+    assert np.array_equal(b, bs.cpu().numpy()) and np.array_equal(var, vs.cpu().numpy())
+    bo, vo, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    assert np.array_equal(info, io) and (io == 0).all()
+    err = normwise(b, bo)
+    _say(f"  normwise {err:.3e} against the oracle")
+    assert err < TOL_FP64 and float(np.max(np.abs(var - vo) / vo)) < TOL_FP64
+    monkeypatch.setenv("GWAS_TRMM_CFG", "3")
+    b3, _, _ = run(prob, XR, precision="fp64", x_dtype="f64", dev_block=dev_block)
+    assert normwise(b, b3) < 1e-13
+
+
 def rounding_bound(prob, XR, b_ref, u_store, u_acc):
     """First-order bound of each SNP's normwise error of b when z = L^-1 x
     is formed from L^-1 rounded with unit roundoff u_store and summed with
