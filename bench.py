@@ -268,6 +268,8 @@ def stream_leg(name, prob_dev, blocks, steps, w, p, t=1):
         "n2_tflops": float(n) * float(n) * kcols / (kms * 1e-3) / 1e12 if kms > 0 else 0.0,
         "rank_flags": int((out_i.array != 0).sum()),
     }
+    if name == "int8":
+        rec["slices"] = SLICES
     return rec, (out_b, out_v, out_i)
 
 
@@ -610,6 +612,7 @@ def run_main(args):
 
 
 def main():
+    global SLICES
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -626,11 +629,13 @@ def main():
     ap.add_argument("--c2-blocks", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--band-widths", default="256,1024,4096", help="half-bandwidths of the banded-M leg")
+    ap.add_argument("--slices", type=int, default=SLICES, help="int8 digits per entry of L^-1 in the int8 leg (4..6)")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--cpu-snps", type=int, default=512)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    SLICES = args.slices
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
