@@ -503,6 +503,8 @@ def run_main(args):
     w = dict(WORKLOADS[args.workload])
     if args.step_snps:
         w["step"] = args.step_snps
+    if args.x_dtype:
+        w["x_dtype"] = args.x_dtype
     n, p, step = w["n"], w["p"], w["step"]
     dev = torch.device("cuda:0")
     legs = [x for x in args.legs.split(",") if x]
@@ -578,6 +580,8 @@ def run_main(args):
 
     r = res["fp64"]
     traffic, traffic_note = measured_traffic("fp64", args.workload)
+    if w["x_dtype"] != WORKLOADS[args.workload]["x_dtype"]:
+        traffic, traffic_note = None, "no counter record for this dosage type"
     m = r["snps"]
     line = {
         "metric": METRIC if (n, p) == (50_000, 8) else METRIC.replace("n=50k,p=8", f"n={n // 1000}k,p={p}"),
@@ -621,6 +625,8 @@ def main():
     ap.add_argument("--legs", default="fp64,fp32,int8,bf16x3,bf16")
     ap.add_argument("--host-blocks", type=int, default=20, help="distinct pinned host blocks (cycled)")
     ap.add_argument("--step-snps", type=int, default=0)
+    ap.add_argument("--x-dtype", choices=["i8", "f64"], default=None,
+                    help="dosage type of the main legs (default: the workload's)")
     ap.add_argument("--seed", type=int, default=1306)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")

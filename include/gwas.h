@@ -104,8 +104,10 @@ extern "C" {
                                   entry (each rounds what the ones before it
                                   leave: their sum is L^-1 to about 2^-27
                                   relative); float64 dosages are cut into
-                                  three slices the same way while staged,
-                                  int8 dosages are exact in bfloat16.  The
+                                  three slices the same way, once per
+                                  sub-block before its product (3 n_pad x 2
+                                  bytes of workspace per column), int8
+                                  dosages are exact in bfloat16.  The
                                   products of slices i + j <= 2 (six; three
                                   with int8 dosages) run on bfloat16 matrix
                                   cores into the same float32 sums (float64

@@ -41,7 +41,7 @@ struct Layout {
     int p, t, q1, Qc, precision, x_dtype, slices;
     size_t off_L, off_U, off_Ulow, off_rscale, off_rsum, off_XY, off_C, off_W, off_S, off_consts, off_flags,
         off_sched, off_sched_tail, off_region;
-    size_t off_xbuf[2], off_part, off_red, off_xw, off_xwpart, off_b[2], off_v[2], off_i[2];
+    size_t off_xbuf[2], off_part, off_red, off_xw, off_xwpart, off_xsl, off_b[2], off_v[2], off_i[2];
     size_t off_tmp;
     size_t sched_len;
     // gwas_stream_block_noalloc: sub-block width whose per-SNP scratch fits
@@ -59,17 +59,26 @@ constexpr size_t NOALLOC_ALIGN = 256;
 // Offsets, in a buffer of per-SNP scratch for `cols` columns, of the
 // product's partial sums, their chunk totals and (reduced modes) the cross
 // products x^T W with their split-K partials; [4] is the end.
-void noalloc_offsets(const Layout& L, int64_t cols, size_t off[5]) {
+// The product's dosage operand: the dosages as handed over, or (the
+// bfloat16-slice mode with float64 dosages) their three bfloat16 slices.
+int prod_xt_of(int precision, int x_dtype) {
+    if (x_dtype == GWAS_X_I8) return X_I8;
+    return precision == GWAS_BF16X3_REFINE ? X_BF16S : X_F64;
+}
+
+void noalloc_offsets(const Layout& L, int64_t cols, size_t off[6]) {
     const bool red = L.precision != GWAS_FP64;
-    const size_t sz[4] = {
+    const bool xsl = L.precision == GWAS_BF16X3_REFINE && L.x_dtype == GWAS_X_F64;
+    const size_t sz[5] = {
         (size_t)L.npb_max * L.Q * cols * 8, (size_t)chunks_of(L.npb_max) * L.Q * cols * 8,
-        red ? (size_t)L.Qc * cols * 8 : 0, red ? (size_t)xw_splits(L.n) * L.Qc * cols * 8 : 0};
+        red ? (size_t)L.Qc * cols * 8 : 0, red ? (size_t)xw_splits(L.n) * L.Qc * cols * 8 : 0,
+        xsl ? (size_t)L.n_pad * 3 * cols * 2 : 0};
     size_t o = 0;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
         off[i] = o;
         o = (o + sz[i] + NOALLOC_ALIGN - 1) / NOALLOC_ALIGN * NOALLOC_ALIGN;
     }
-    off[4] = o;
+    off[5] = o;
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -149,10 +158,11 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_flags = take(256);
     // room for the schedule and partial sums of every tile shape
     const int at = atype_of(precision);
-    const int xt = x_dtype == GWAS_X_I8 ? X_I8 : X_F64;
+    const int xd = x_dtype == GWAS_X_I8 ? X_I8 : X_F64;     // the dosages as handed over
+    const int xt = prod_xt_of(precision, x_dtype);          // the product's dosage operand
     // the reverse pass runs the float64 product with its default shape
     L.sched_len = band > 0 ? 1 : (size_t)trmm_schedule_len(L.n_pad, L.dev_block,
-                                            trmm_geom(A_F64, xt, trmm_default_cfg(A_F64, xt), 0));
+                                            trmm_geom(A_F64, xd, trmm_default_cfg(A_F64, xd), 0));
     // every admissible shape with the model's and every candidate row group
     for (int c = 0; c < trmm_cfg_limit() && band == 0; ++c) {
         if (!trmm_cfg_valid(at, xt, c)) continue;
@@ -169,9 +179,9 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
         int64_t lo = 0, hi = L.dev_block / TILE_N;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) / 2;
-            size_t off[5];
+            size_t off[6];
             noalloc_offsets(L, mid * TILE_N, off);
-            if (off[4] <= NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+            if (off[5] <= NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
         }
         L.na_cols = band > 0 ? 0 : lo * TILE_N;   // the banded path has no schedule-driven product
         L.na_sched_len = 0;
@@ -195,6 +205,8 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_red = rtake((size_t)chunks_of(L.npb_max) * L.Q * L.dev_block * 8);
     L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
     L.off_xwpart = (precision != GWAS_FP64) ? rtake((size_t)xw_splits(n) * L.Qc * L.dev_block * 8) : 0;
+    // bfloat16-slice mode with float64 dosages: the sub-block's three dosage slices
+    L.off_xsl = xt == X_BF16S ? rtake((size_t)L.n_pad * 3 * L.dev_block * 2) : 0;
     for (int s = 0; s < 2; ++s) {
         L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
         L.off_v[s] = rtake((size_t)L.dev_block * 8);
@@ -270,6 +282,7 @@ struct gwas_ctx {
     double* red = nullptr;          // chunk totals of part
     double* xw = nullptr;
     double* xwpart = nullptr;       // split-K partial sums of xw
+    __bf16* xsl = nullptr;          // bfloat16 slices of the sub-block's float64 dosages (X_BF16S)
     double* bbuf[2] = {nullptr, nullptr};
     double* vbuf[2] = {nullptr, nullptr};
     int* ibuf[2] = {nullptr, nullptr};
@@ -669,11 +682,14 @@ int upload_noalloc_schedule(gwas_ctx* c) {
     return GWAS_OK;
 }
 
-TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols) {
+// xs: where the sub-block's bfloat16 dosage slices are (X_BF16S; NULL: the
+// context's own buffer)
+TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols,
+                       const __bf16* xs = nullptr) {
     const Layout& Y = c->lay;
     TrmmArgs ta{};
     ta.at = c->at;
-    ta.xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    ta.xt = prod_xt_of(Y.precision, Y.x_dtype);
     ta.cfg = c->cfg;
     ta.slices = Y.slices;
     ta.rscale = c->rscale;
@@ -683,6 +699,12 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.n_pad = Y.n_pad;
     ta.X = xptr;
     ta.ldx = xld;
+    ta.Xd = xptr;
+    ta.ldxd = xld;
+    if (ta.xt == X_BF16S) {
+        ta.X = xs ? xs : c->xsl;
+        ta.ldx = 3 * Y.n_pad;
+    }
     ta.n = Y.n;
     ta.cols = cols;
     ta.C = c->C;
@@ -695,6 +717,17 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.rgroup = c->rgroup;
     ta.n_sched = trmm_schedule_len(Y.n_pad, cols, c->shape);
     return ta;
+}
+
+// The bfloat16-slice mode with float64 dosages cuts a sub-block's dosages
+// into three bfloat16 slices (out, 3 n_pad per column) before its product;
+// other modes have nothing to do.  xargs: read the dosages' address from a
+// device argument record when the kernel runs (replayed graphs).
+hipError_t cut_dosages(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, __bf16* out, hipStream_t s,
+                       const TrmmArgs* xargs = nullptr) {
+    const Layout& Y = c->lay;
+    if (prod_xt_of(Y.precision, Y.x_dtype) != X_BF16S) return hipSuccess;
+    return slice_x_bf16(static_cast<const double*>(xptr), xld, Y.n, Y.n_pad, cols, out, 3 * Y.n_pad, s, xargs);
 }
 
 // Device scratch of the per-SNP stage of one sub-block: the product's
@@ -931,13 +964,14 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->lay = make_layout(d->n, d->p, d->t, d->dev_block, d->precision, d->x_dtype, slices, d->band, d->ldm);
     const Layout& Y = c->lay;
     c->at = atype_of(d->precision);
-    c->cfg = trmm_default_cfg(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64);
+    const int pxt = prod_xt_of(d->precision, d->x_dtype);
+    c->cfg = trmm_default_cfg(c->at, pxt);
     if (const char* e = getenv("GWAS_TRMM_CFG")) {
         // tile-shape override for measurement; ignored when not valid here
         const int v = atoi(e);
-        if (trmm_cfg_valid(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, v)) c->cfg = v;
+        if (trmm_cfg_valid(c->at, pxt, v)) c->cfg = v;
     }
-    c->shape = trmm_geom(c->at, d->x_dtype == GWAS_X_I8 ? X_I8 : X_F64, c->cfg, slices);
+    c->shape = trmm_geom(c->at, pxt, c->cfg, slices);
     // the banded product has its own fixed tile (128 x 128, 32-row slices)
     if (d->band > 0) c->shape = TrmmShape{128, 128, band_part_rows(), 512, 1, 32};
     if (d->band > 0) {
@@ -990,6 +1024,7 @@ int gwas_init(gwas_ctx** out, const gwas_desc* d) {
     c->red = (double*)(w + Y.off_red);
     c->xw = Y.off_xw ? (double*)(w + Y.off_xw) : nullptr;
     c->xwpart = Y.off_xwpart ? (double*)(w + Y.off_xwpart) : nullptr;
+    c->xsl = Y.off_xsl ? (__bf16*)(w + Y.off_xsl) : nullptr;
     c->tmp = (double*)(w + Y.off_tmp);
     if (Y.band > 0) {
         c->Ub = (double*)(w + Y.off_Ub);
@@ -1181,6 +1216,7 @@ int enqueue_block(gwas_ctx* c, const void* XR, int64_t ldx, int64_t mblk, double
         if (Y.band > 0) {
             HIPCHK(c, band_product(c, xptr, xld, cols, c->s_comp));
         } else {
+            HIPCHK(c, cut_dosages(c, xptr, xld, cols, c->xsl, c->s_comp));
             TrmmArgs ta = trmm_args_for(c, xptr, xld, cols);
             ta.sched = sched;
             HIPCHK(c, trmm_stream(ta, c->s_comp));
@@ -1257,11 +1293,11 @@ int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t 
     if (mblk == 0) return GWAS_OK;
     const Layout& Y = c->lay;
     if (Y.na_cols <= 0) {
-        size_t off[5];
+        size_t off[6];
         noalloc_offsets(Y, TILE_N, off);
         char msg[200];
         snprintf(msg, sizeof(msg), "gwas_stream_block_noalloc: the scratch of %d SNP columns needs %zu bytes, "
-                 "more than the static buffer's %zu", TILE_N, off[4], NOALLOC_SCRATCH_BYTES);
+                 "more than the static buffer's %zu", TILE_N, off[5], NOALLOC_SCRATCH_BYTES);
         c->err = msg;
         return GWAS_E_INVALID;
     }
@@ -1279,8 +1315,9 @@ int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t 
     // behind the blocks queued on the context's own streams
     HIPCHK(c, hipEventRecord(c->ev_na, c->s_comp));
     HIPCHK(c, hipStreamWaitEvent(s, c->ev_na, 0));
-    size_t off[5];
+    size_t off[6];
     noalloc_offsets(Y, Y.na_cols, off);
+    __bf16* xs = reinterpret_cast<__bf16*>(c->nscratch + off[4]);   // dosage slices (X_BF16S)
     // the float64 mode takes its cross terms from the partial sums (no x^T W)
     const bool red = Y.precision != GWAS_FP64;
     const SubScratch sc{reinterpret_cast<double*>(c->nscratch + off[0]), reinterpret_cast<double*>(c->nscratch + off[1]),
@@ -1290,7 +1327,8 @@ int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t 
     for (int64_t col0 = 0; col0 < mblk; col0 += Y.na_cols) {
         const int64_t cols = std::min<int64_t>(Y.na_cols, mblk - col0);
         const void* xptr = xr + (size_t)col0 * ldx * elem;
-        TrmmArgs ta = trmm_args_for(c, xptr, ldx, cols);
+        HIPCHK(c, cut_dosages(c, xptr, ldx, cols, xs, s));
+        TrmmArgs ta = trmm_args_for(c, xptr, ldx, cols, xs);
         ta.part = sc.part;
         ta.ldp = sc.ld;
         ta.sched = c->sched_na;
@@ -1398,6 +1436,8 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
             c0->err = "grouped schedule does not match the contexts' tile shape";
             return GWAS_E_INVALID;
         }
+        for (int i = 0; i < nctx; ++i)
+            HIPCHK(c0, cut_dosages(cs[i], xp[i], xl[i], cols, cs[i]->xsl, s, x_from_args ? d + i : nullptr));
         TrmmArgs la = h[0];
         la.group = d;
         la.sched = sched;
@@ -1509,8 +1549,12 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                 if (k >= 2) HIPCHK(c0, hipEventSynchronize(c0->ev_done[slot]));
                 for (int i = 0; i < nctx; ++i) {
                     TrmmArgs a = g->h_args_graph[i];
-                    a.X = xp[i];
-                    a.ldx = xl[i];
+                    a.Xd = xp[i];
+                    a.ldxd = xl[i];
+                    if (a.xt != X_BF16S) {   // bfloat16 slices stay in the context's buffer
+                        a.X = xp[i];
+                        a.ldx = xl[i];
+                    }
                     HIPCHK(c0, trmm_check(a, false));
                     g->h_args_upd[slot][i] = a;
                 }
@@ -1570,7 +1614,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
     if (int rc = settle(c)) return rc;   // blocks queued by gwas_stream_block_async
     HIPCHK(c, join_user(c, c->s_comp));
     HIPCHK(c, hipStreamSynchronize(c->s_comp));
-    const int xt = (Y.x_dtype == GWAS_X_I8) ? X_I8 : X_F64;
+    const int xt = prod_xt_of(Y.precision, Y.x_dtype);   // the product's dosage operand
     const char* cache = getenv("GWAS_TUNE_CACHE");
     char keyline[160];
     snprintf(keyline, sizeof(keyline), "gfx950 n_pad=%lld precision=%d x_dtype=%d cols=%lld",
@@ -1606,6 +1650,8 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
             xptr = c->xbuf[0];
             xld = Y.n_pad;
         }
+        // bfloat16-slice mode with float64 dosages: the slices the products read
+        HIPCHK(c, cut_dosages(c, xptr, xld, cols, c->xsl, c->s_comp));
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
@@ -1654,7 +1700,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
             auto launch_all = [&]() -> int {
                 for (int64_t q = 0; q < reps; ++q) {
                     TrmmArgs ta = trmm_args_for(c, static_cast<const char*>(xptr) + (size_t)(q * w) * xld * elem,
-                                                xld, w);
+                                                xld, w, c->xsl ? c->xsl + (size_t)(q * w) * 3 * Y.n_pad : nullptr);
                     ta.sched = c->sched_tail;
                     HIPCHK(c, trmm_stream(ta, c->s_comp));
                 }

@@ -298,6 +298,25 @@ __global__ void slice_bf16_kernel(const double* __restrict__ U, int64_t ld, int6
         }
 }
 
+// Float64 dosage columns cut the same way, zero from row n on.
+__global__ void slice_x_bf16_kernel(const double* __restrict__ X, int64_t ldx, int64_t n, int64_t n_pad,
+                                    int64_t cols, __bf16* __restrict__ out, int64_t ldo, const TrmmArgs* xargs) {
+    if (xargs) {
+        X = static_cast<const double*>(xargs->Xd);
+        ldx = xargs->ldxd;
+    }
+    for (int64_t j = blockIdx.x; j < cols; j += gridDim.x)
+        for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) {
+            double v = k < n ? X[k + j * ldx] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const __bf16 h = (__bf16)v;
+                out[k + i * n_pad + j * ldo] = h;
+                v -= (double)h;
+            }
+        }
+}
+
 // One workgroup per row of L^-1 (grid-stride): block max, power-of-two
 // scale, then int8 digits in pairs: each digit rounds what the ones before
 // it leave, scaled by 127 inside a pair and by 128 from one pair to the
@@ -459,6 +478,16 @@ hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, i
     if (!U || !out || ld < n_pad || ldo < 3 * n_pad) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<int64_t>(n_pad, 8192);
     hipLaunchKernelGGL(slice_bf16_kernel, dim3(grid), dim3(256), 0, s, U, ld, n_pad, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t slice_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, int64_t cols, __bf16* out,
+                        int64_t ldo, hipStream_t s, const TrmmArgs* xargs) {
+    if (cols <= 0) return hipSuccess;
+    if ((!X && !xargs) || !out || n < 1 || n > n_pad || (!xargs && ldx < n) || ldo < 3 * n_pad)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(cols, 16384);
+    hipLaunchKernelGGL(slice_x_bf16_kernel, dim3(grid), dim3(256), 0, s, X, ldx, n, n_pad, cols, out, ldo, xargs);
     return hipGetLastError();
 }
 

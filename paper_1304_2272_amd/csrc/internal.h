@@ -78,7 +78,12 @@ __host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64
 constexpr int64_t X_DIRECT_MAX_LD_BYTES = int64_t(4) << 20;
 
 enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2, A_I8S = 3 };
-enum XType : int { X_F64 = 0, X_I8 = 1 };
+// Dosage operand of the product: float64, int8, or (the bfloat16-slice mode
+// with float64 dosages) three bfloat16 slices of each float64 column, cut
+// once per sub-block by slice_x_bf16: slice i of column j at
+// X + j*ldx + i*n_pad, zero from row n on.
+enum XType : int { X_F64 = 0, X_I8 = 1, X_BF16S = 2 };
+inline int64_t x_elem_bytes(int xt) { return xt == X_I8 ? 1 : xt == X_BF16S ? 2 : 8; }
 
 // Z = L^-1 X for one sub-block, never stored: for every slice of part_rows
 // rows of Z (one wave's rows) and SNP column j the kernel writes partial
@@ -105,6 +110,8 @@ struct TrmmArgs {
                                 // paired digits 127 A_2p(r, k) + A_2p+1(r, k)
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
+    const void* Xd; int64_t ldxd;  // the dosages as handed over (float64 or int8): X and ldx,
+                                // or the columns X_BF16S slices are cut from
     const double* C; int64_t ldc; int Qc;
     int with_cross;
     double* part; int64_t ldp;
@@ -143,6 +150,12 @@ constexpr int RGROUP_CANDIDATES[] = {1, 2, 4, 8};   // what the autotuner tries
 // out[k + i*n_pad + r*ldo], i = 0..2 (ldo >= 3 n_pad): slice i rounds what
 // slices 0..i-1 leave, so their sum is L^-1(r, k) to about 2^-27 relative.
 hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, int64_t ldo, hipStream_t s);
+// The same cut for cols float64 dosage columns (column j at X + j*ldx,
+// elements k < n): out[k + i*n_pad + j*ldo], i = 0..2, zero for n <= k < n_pad.
+// With xargs (a device argument record) X and ldx are read from its Xd and
+// ldxd when the kernel runs.
+hipError_t slice_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, int64_t cols, __bf16* out,
+                        int64_t ldo, hipStream_t s, const TrmmArgs* xargs = nullptr);
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
 // and S int8 digits A_s(r,k) in [-64, 64], written to sliced row

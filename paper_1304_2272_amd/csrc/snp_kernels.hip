@@ -44,8 +44,8 @@ __global__ __launch_bounds__(64 * WV) void xw_kernel(const XT* X, int64_t ldx, i
     // xargs: the dosages' address and stride come from a device argument
     // array (a replayed graph reads the block's dosages in place)
     if (xargs) {
-        X = static_cast<const XT*>(xargs->X);
-        ldx = xargs->ldx;
+        X = static_cast<const XT*>(xargs->Xd);
+        ldx = xargs->ldxd;
     }
     constexpr int NT = 64 * WV;
     constexpr int TC = 64 * WV;                     // SNPs per workgroup, one per thread

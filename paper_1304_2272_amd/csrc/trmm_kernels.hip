@@ -103,7 +103,8 @@ template <int WGM_, int WGN_, int WTM_, int WTN_, int MINB_, bool SUM32_ = false
 // (slice i of L^-1, slice j of the dosages) with i + j <= 2, smallest
 // first, all into the same sums.  Three slices of L^-1 with int8 dosages
 // (exact in bfloat16): (2,0), (1,0), (0,0); with float64 dosages, cut into
-// three slices as well: (2,0), (1,1), (0,2), (1,0), (0,1), (0,0).
+// three slices as well (once per sub-block, before the product):
+// (2,0), (1,1), (0,2), (1,0), (0,1), (0,0).
 __device__ __forceinline__ int seg_a(int nseg, int s) {
     if (nseg == 3) return 2 - s;
     if (nseg == 6) return s == 0 ? 2 : (s == 1 || s == 3) ? 1 : 0;
@@ -124,6 +125,9 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     typedef MM<AT> T;
     constexpr int BK = T::BK;
     constexpr bool LOWP = sizeof(AT) < 8;
+    // dosages given as three bfloat16 slices (the bfloat16-slice product
+    // with float64 dosages): segment s reads slice seg_x(s)
+    constexpr bool XSL = std::is_same<XT, __bf16>::value;
     // reduced-precision sums move to float64 registers every FLUSH_STAGES
     // stages unless the shape keeps float32 sums only
     constexpr bool SUM64 = LOWP && !S::SUM32;
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     const int nseg = (sizeof(AT) == 2 && a.slices == 3) ? (sizeof(XT) == 1 ? 3 : 6) : 1;
     const kidx_t nkt = nk * (kidx_t)nseg;
     const int64_t seg_bytes = a.n_pad * (int64_t)sizeof(AT);
-    int xj_next = 0;   // dosage slice of the stage held in the staging registers
+    int xj_next = 0;   // dosage slice of the segment being loaded (bfloat16 slices)
     const char* Ut = reinterpret_cast<const char*>(a.Ut);
     const int64_t row_bytes = a.ldu * (int64_t)sizeof(AT);
     const XT* X = reinterpret_cast<const XT*>(a.X);
@@ -210,7 +214,8 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         // the tile's last column: the caller's array need not extend to ldx
         // there
         const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
-        const int64_t xbytes = ((xcols - 1) * a.ldx + a.n) * (int64_t)sizeof(XT);
+        // bfloat16 slices of float64 dosages: the last column's third slice
+        const int64_t xbytes = ((xcols - 1) * a.ldx + (XSL ? 2 * a.n_pad : 0) + a.n) * (int64_t)sizeof(XT);
         rsB = __builtin_amdgcn_make_buffer_rsrc(const_cast<XT*>(X + c0 * a.ldx), (short)0,
                                                 (int)((xbytes + 15) / 16 * 16), 0x00020000);
         voA = (tid >> 3) * (int)row_bytes + (tid & 7) * 16;
@@ -218,11 +223,13 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
     }
     auto load_buf = [&](int kt) {
         int ai = 0;
+        int xo = 0;   // bytes to the dosage slice of the segment (bfloat16 slices)
         if (nseg > 1) {
             const int seg = kt / (int)nk;
             kt -= seg * (int)nk;
             ai = seg_a(nseg, seg);
             xj_next = seg_x(nseg, seg);
+            if constexpr (XSL) xo = xj_next * (int)(a.n_pad * (int64_t)sizeof(XT));
         }
 #pragma unroll
         for (int c = 0; c < CA; ++c)
@@ -231,7 +238,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
 #pragma unroll
         for (int c = 0; c < CB; ++c)
             rb[c] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 rsB, voB + (int)(c * (NT / CPC) * a.ldx * (int64_t)sizeof(XT)) + kt * XB, 0, 0));
+                                                 rsB, voB + (int)(c * (NT / CPC) * a.ldx * (int64_t)sizeof(XT)) + kt * XB + xo, 0, 0));
         if ((kt + 1) * BK > (int)a.n) {
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
@@ -252,11 +259,13 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             return;
         }
         int64_t aoff = 0;
+        const XT* Xs = X;   // the segment's dosage slice (bfloat16 slices)
         if (nseg > 1) {
             const kidx_t seg = kt / nk;
             kt -= seg * nk;
             aoff = seg_a(nseg, (int)seg) * seg_bytes;
             xj_next = seg_x(nseg, (int)seg);
+            if constexpr (XSL) Xs = X + xj_next * a.n_pad;
         }
 #pragma unroll
         for (int c = 0; c < CA; ++c) {
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                     const int idx = tid + c * NT;
                     if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
                         const int col = idx / CPC, ch = idx % CPC;
-                        rb[c] = *reinterpret_cast<const u4_t*>(X + (c0 + col) * a.ldx + kt * BK + ch * EPC);
+                        rb[c] = *reinterpret_cast<const u4_t*>(Xs + (c0 + col) * a.ldx + kt * BK + ch * EPC);
                     }
                 }
                 return;
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 const int col = idx / CPC, ch = idx % CPC;
                 const int64_t gcol = c0 + col;
                 const int64_t k0 = kt * BK + ch * EPC;
-                const XT* src = X + gcol * a.ldx + k0;
+                const XT* src = Xs + gcol * a.ldx + k0;
                 if constexpr (sizeof(AT) == 8) {
                     // A chunk whose column is in the block and whose first
                     // element is below n lies inside the caller's array (ldx
@@ -339,24 +348,15 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
             if (B_CHUNKS % NT == 0 || idx < B_CHUNKS) {
                 const int col = idx / CPC, ch = idx % CPC;
                 AT* dst = reinterpret_cast<AT*>(Bs[buf] + col * ROW_STRIDE) + ch * EPC;
-                const XT* x = reinterpret_cast<const XT*>(&rb[c]);
+                if constexpr (XSL) {
+                    // bfloat16 slices of float64 dosages go in as they are
+                    *reinterpret_cast<u4_t*>(dst) = rb[c];
+                } else {
+                    const XT* x = reinterpret_cast<const XT*>(&rb[c]);
 #pragma unroll
-                for (int e = 0; e < EPC; ++e) {
-                    if constexpr (sizeof(XT) == 1) {
-                        dst[e] = from_i8<AT>((int8_t)x[e]);
-                    } else if constexpr (sizeof(AT) == 2) {
-                        // slice xj of a float64 dosage: what the slices
-                        // before it leave, rounded to bfloat16 (each
-                        // remainder is exact in float64)
-                        double v = (double)x[e];
-                        if (nseg > 1) {
-                            for (int q = 0; q < xj_next; ++q) v -= (double)(__bf16)v;
-                            dst[e] = (__bf16)v;
-                        } else {
-                            dst[e] = from_f64<AT>(v);
-                        }
-                    } else {
-                        dst[e] = from_f64<AT>((double)x[e]);
+                    for (int e = 0; e < EPC; ++e) {
+                        if constexpr (sizeof(XT) == 1) dst[e] = from_i8<AT>((int8_t)x[e]);
+                        else dst[e] = from_f64<AT>((double)x[e]);
                     }
                 }
             }
@@ -888,7 +888,7 @@ hipError_t launch_cfg(const TrmmArgs& a, hipStream_t s) {
             if constexpr (F64) return launch_trmm<AT, XT, Cfg4>(a, s);
             else return hipErrorInvalidValue;
         case 6:
-            if constexpr (!F64 && I8) return launch_trmm<AT, XT, Cfg6>(a, s);
+            if constexpr (!F64 && (I8 || std::is_same<XT, __bf16>::value)) return launch_trmm<AT, XT, Cfg6>(a, s);
             else return hipErrorInvalidValue;
         case 7:
             if constexpr (F64 && I8) {
@@ -934,8 +934,11 @@ TrmmShape trmm_shape(int cfg) {
 bool trmm_cfg_valid(int at, int xt, int cfg) {
     if (at == A_I8S) return xt == X_I8 && cfg >= 0 && cfg < trmm_sliced_cfgs();
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
-    // 64 x 128 waves fit two per SIMD only with float32 sums and int8 dosages
-    if (cfg == 6) return at != A_F64 && xt == X_I8;
+    // bfloat16 slices of float64 dosages feed the bfloat16 product only
+    if (xt == X_BF16S && at != A_BF16) return false;
+    // 64 x 128 waves fit two per SIMD only with float32 sums and one- or
+    // two-byte dosages
+    if (cfg == 6) return at != A_F64 && (xt == X_I8 || xt == X_BF16S);
     // float64 loaded straight into LDS
     if (cfg == 7) return at == A_F64;
     if (at == A_F64) return true;
@@ -963,7 +966,7 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 int trmm_default_cfg(int at, int xt) {
     if (at == A_I8S) return trmm_sliced_default_cfg();
     if (at == A_F64) return 7;
-    if (xt == X_I8) return 6;
+    if (xt == X_I8 || xt == X_BF16S) return 6;
     return 1;
 }
 
@@ -976,7 +979,7 @@ TrmmShape trmm_geom(int at, int xt, int cfg, int slices, int rgroup) {
     sh.inflight = 32 * per_cu;
     const int64_t asz = at == A_F64 ? 8 : at == A_F32 ? 4 : at == A_BF16 ? 2 : 1;
     const int64_t arows = at == A_I8S ? (int64_t)sh.tm * slices : sh.tm;
-    const int64_t xsz = xt == X_I8 ? 1 : 8;
+    const int64_t xsz = x_elem_bytes(xt);
     sh.rgroup = rgroup > 0 ? std::min(rgroup, sh.inflight)
                            : row_group_for(arows * asz, (int64_t)sh.tn * xsz, sh.inflight);
     return sh;
@@ -1002,8 +1005,10 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if (a.n_pad % NPAD_ALIGN || a.ldu < a.n_pad || a.n > a.n_pad || a.n < 1) return hipErrorInvalidValue;
     if (a.ldx < a.n || a.ldp < a.cols) return hipErrorInvalidValue;
     if (a.with_cross && (!a.C || a.ldc < a.n_pad || a.Qc < 1)) return hipErrorInvalidValue;
-    const size_t xs = a.xt == X_I8 ? 1 : 8;
+    const size_t xs = (size_t)x_elem_bytes(a.xt);
     if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
+    // bfloat16 dosage slices: three per column, n_pad elements each
+    if (a.xt == X_BF16S && (a.at != A_BF16 || a.slices != 3 || a.ldx < 3 * a.n_pad)) return hipErrorInvalidValue;
     if (a.at == A_I8S) {
         // the int8-slice product forms z^T z only (its mode takes the cross
         // products from x^T W)
@@ -1052,6 +1057,8 @@ hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
         if (a.at == A_F64) return launch_cfg<double, double>(a, s);
         if (a.at == A_F32) return launch_cfg<float, double>(a, s);
         if (a.at == A_BF16) return launch_cfg<__bf16, double>(a, s);
+    } else if (a.xt == X_BF16S) {
+        if (a.at == A_BF16) return launch_cfg<__bf16, __bf16>(a, s);
     } else if (a.xt == X_I8) {
         if (a.at == A_F64) return launch_cfg<double, int8_t>(a, s);
         if (a.at == A_F32) return launch_cfg<float, int8_t>(a, s);

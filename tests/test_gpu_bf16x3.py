@@ -1,6 +1,6 @@
 """The bfloat16-slice product (GWAS_BF16X3_REFINE) against the CPU oracle:
 L^-1 as three bfloat16 slices, float64 dosages (here non-integer, as
-imputation gives them) cut into three slices while staged, and the products
+imputation gives them) cut into three slices once per sub-block, and the products
 of slices i + j <= 2 summed on bfloat16 matrix cores in float32.  Every SNP is
 held to the stated error of the float32 mode (16 u kappa_i on the SNP
 coefficient and var with u = 2^-24), and the normwise error of b to at most
@@ -81,7 +81,7 @@ def test_int8_dosages_vs_oracle(n, p, m):
     check(prob, XR, "i8")
 
 
-@pytest.mark.parametrize("x_dtype,cfgs", [("i8", [1, 2, 3, 5, 6]), ("f64", [1, 2, 5])])
+@pytest.mark.parametrize("x_dtype,cfgs", [("i8", [1, 2, 3, 5, 6]), ("f64", [1, 2, 5, 6])])
 def test_every_tile_shape(x_dtype, cfgs, monkeypatch):
     n, p, m, seed = 900, 5, 700, 3500
     prob = synth.make_problem(n, p, seed, k=300)
@@ -129,3 +129,35 @@ def test_more_accurate_than_one_bfloat16_slice():
     e1 = normwise(b1, bo)
     _say(f"  one slice {e1:.3e}, three slices {e3:.3e}")
     assert e3 < 1e-3 * e1
+
+
+def test_float64_dosages_grouped_and_replayed():
+    # the dosage slices are cut per context before a grouped product; in a
+    # replayed graph the cut reads each call's new dosages through the
+    # argument array: every member equals its own single-context call bit
+    # for bit
+    import torch
+    dev = torch.device("cuda:0")
+    blk, m = 256, 768
+    probs = [synth.make_problem(n, 4, 3900 + i, t=2, k=300) for i, n in enumerate((600, 1100, 1700))]
+    ctxs = [binding.GwasContext(pr["M"], pr["XL"], pr["Y"], precision="bf16x3", x_dtype="f64", dev_block=blk)
+            for pr in probs]
+    try:
+        for call in range(2):
+            _say(f"bf16x3 float64 dosages: 3 cohorts grouped, eager and graph, call {call}")
+            XRs = [torch.from_numpy(synth.imputed_block(pr["n"], 40 + call, 0, m)).to(dev) for pr in probs]
+            single = [c.stream_block(X) for c, X in zip(ctxs, XRs)]
+            eager = binding.stream_group(ctxs, XRs)
+            replay = binding.stream_group(ctxs, XRs, graph=True)
+            torch.cuda.synchronize()
+            for (bs, vs, is_), (be, ve, ie), (bg, vg, ig) in zip(single, eager, replay):
+                assert torch.equal(bs, be) and torch.equal(vs, ve) and torch.equal(is_, ie)
+                assert torch.equal(bs, bg) and torch.equal(vs, vg) and torch.equal(is_, ig)
+        for pr, c in zip(probs, ctxs):
+            X = synth.imputed_block(pr["n"], 41, 0, 200)
+            b, _, _ = c.stream_block(X)
+            bo, _, _ = GLSOracle(pr["M"], pr["XL"], pr["Y"]).solve(X)
+            assert normwise(b, bo) < 1e-8
+    finally:
+        for c in ctxs:
+            c.close()
