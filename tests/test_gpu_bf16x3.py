@@ -161,3 +161,22 @@ def test_float64_dosages_grouped_and_replayed():
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_float64_dosages_autotuned():
+    # the autotuner times the products on the cut slices, with every tile
+    # shape and sub-block width it tries
+    n, p, m, seed = 1500, 4, 2048, 3950
+    prob = synth.make_problem(n, p, seed)
+    XR = synth.imputed_block(n, seed, 0, m)
+    bo, _, _ = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    with binding.GwasContext(prob["M"], prob["XL"], prob["Y"], precision="bf16x3", x_dtype="f64",
+                             dev_block=1024) as ctx:
+        best = ctx.autotune(XR, 1024)
+        sub = ctx.query()["dev_block"]
+        _say(f"autotune bf16x3 float64 dosages: tile shape {best[0]}, row group {best[1]}, sub-block width {sub}")
+        assert best[0] in (1, 2, 5, 6) and sub in (256, 512, 1024)
+        b, _, _ = ctx.stream_block(XR)
+        b2, _, _ = ctx.stream_block(XR)
+    assert np.array_equal(b, b2)
+    assert normwise(b, bo) < 1e-8
