@@ -59,20 +59,26 @@ constexpr size_t NOALLOC_ALIGN = 256;
 // Offsets, in a buffer of per-SNP scratch for `cols` columns, of the
 // product's partial sums, their chunk totals and (reduced modes) the cross
 // products x^T W with their split-K partials; [4] is the end.
-// The product's dosage operand: the dosages as handed over, or (the
-// bfloat16-slice mode with float64 dosages) their three bfloat16 slices.
+// The product's dosage operand: the dosages as handed over, or float64
+// dosages cut once per sub-block into bfloat16 for the bfloat16 products
+// (three slices for the bfloat16-slice mode, one rounding for the bfloat16
+// mode).
 int prod_xt_of(int precision, int x_dtype) {
     if (x_dtype == GWAS_X_I8) return X_I8;
-    return precision == GWAS_BF16X3_REFINE ? X_BF16S : X_F64;
+    if (precision == GWAS_BF16X3_REFINE) return X_BF16S;
+    return precision == GWAS_BF16_REFINE ? X_BF16 : X_F64;
 }
+bool x_cut(int xt) { return xt == X_BF16S || xt == X_BF16; }
+// elements per column of the cut dosages (their leading dimension)
+int64_t x_cut_ld(int xt, int64_t n_pad) { return xt == X_BF16S ? 3 * n_pad : n_pad; }
 
 void noalloc_offsets(const Layout& L, int64_t cols, size_t off[6]) {
     const bool red = L.precision != GWAS_FP64;
-    const bool xsl = L.precision == GWAS_BF16X3_REFINE && L.x_dtype == GWAS_X_F64;
+    const int xt = prod_xt_of(L.precision, L.x_dtype);
     const size_t sz[5] = {
         (size_t)L.npb_max * L.Q * cols * 8, (size_t)chunks_of(L.npb_max) * L.Q * cols * 8,
         red ? (size_t)L.Qc * cols * 8 : 0, red ? (size_t)xw_splits(L.n) * L.Qc * cols * 8 : 0,
-        xsl ? (size_t)L.n_pad * 3 * cols * 2 : 0};
+        x_cut(xt) ? (size_t)x_cut_ld(xt, L.n_pad) * cols * x_elem_bytes(xt) : 0};
     size_t o = 0;
     for (int i = 0; i < 5; ++i) {
         off[i] = o;
@@ -205,8 +211,8 @@ Layout make_layout(int64_t n, int p, int t, int64_t dev_block, int precision, in
     L.off_red = rtake((size_t)chunks_of(L.npb_max) * L.Q * L.dev_block * 8);
     L.off_xw = (precision != GWAS_FP64) ? rtake((size_t)L.Qc * L.dev_block * 8) : 0;
     L.off_xwpart = (precision != GWAS_FP64) ? rtake((size_t)xw_splits(n) * L.Qc * L.dev_block * 8) : 0;
-    // bfloat16-slice mode with float64 dosages: the sub-block's three dosage slices
-    L.off_xsl = xt == X_BF16S ? rtake((size_t)L.n_pad * 3 * L.dev_block * 2) : 0;
+    // float64 dosages cut into bfloat16 (three slices, or one rounding)
+    L.off_xsl = x_cut(xt) ? rtake((size_t)x_cut_ld(xt, L.n_pad) * L.dev_block * x_elem_bytes(xt)) : 0;
     for (int s = 0; s < 2; ++s) {
         L.off_b[s] = rtake((size_t)p * t * L.dev_block * 8);
         L.off_v[s] = rtake((size_t)L.dev_block * 8);
@@ -282,7 +288,7 @@ struct gwas_ctx {
     double* red = nullptr;          // chunk totals of part
     double* xw = nullptr;
     double* xwpart = nullptr;       // split-K partial sums of xw
-    __bf16* xsl = nullptr;          // bfloat16 slices of the sub-block's float64 dosages (X_BF16S)
+    __bf16* xsl = nullptr;          // the sub-block's float64 dosages cut into bfloat16 (X_BF16S, X_BF16)
     double* bbuf[2] = {nullptr, nullptr};
     double* vbuf[2] = {nullptr, nullptr};
     int* ibuf[2] = {nullptr, nullptr};
@@ -682,7 +688,7 @@ int upload_noalloc_schedule(gwas_ctx* c) {
     return GWAS_OK;
 }
 
-// xs: where the sub-block's bfloat16 dosage slices are (X_BF16S; NULL: the
+// xs: where the sub-block's cut dosages are (X_BF16S, X_BF16; NULL: the
 // context's own buffer)
 TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols,
                        const __bf16* xs = nullptr) {
@@ -701,9 +707,9 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     ta.ldx = xld;
     ta.Xd = xptr;
     ta.ldxd = xld;
-    if (ta.xt == X_BF16S) {
+    if (x_cut(ta.xt)) {
         ta.X = xs ? xs : c->xsl;
-        ta.ldx = 3 * Y.n_pad;
+        ta.ldx = x_cut_ld(ta.xt, Y.n_pad);
     }
     ta.n = Y.n;
     ta.cols = cols;
@@ -719,15 +725,20 @@ TrmmArgs trmm_args_for(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t
     return ta;
 }
 
-// The bfloat16-slice mode with float64 dosages cuts a sub-block's dosages
-// into three bfloat16 slices (out, 3 n_pad per column) before its product;
-// other modes have nothing to do.  xargs: read the dosages' address from a
-// device argument record when the kernel runs (replayed graphs).
+// Float64 dosages of the bfloat16 products are cut into bfloat16 once per
+// sub-block, before its product (into out: three slices, 3 n_pad per column,
+// for the bfloat16-slice mode; one rounding, n_pad per column, for the
+// bfloat16 mode); other modes have nothing to do.  xargs: read the dosages'
+// address from a device argument record when the kernel runs (replayed
+// graphs).
 hipError_t cut_dosages(const gwas_ctx* c, const void* xptr, int64_t xld, int64_t cols, __bf16* out, hipStream_t s,
                        const TrmmArgs* xargs = nullptr) {
     const Layout& Y = c->lay;
-    if (prod_xt_of(Y.precision, Y.x_dtype) != X_BF16S) return hipSuccess;
-    return slice_x_bf16(static_cast<const double*>(xptr), xld, Y.n, Y.n_pad, cols, out, 3 * Y.n_pad, s, xargs);
+    const int xt = prod_xt_of(Y.precision, Y.x_dtype);
+    const double* X = static_cast<const double*>(xptr);
+    if (xt == X_BF16S) return slice_x_bf16(X, xld, Y.n, Y.n_pad, cols, out, 3 * Y.n_pad, s, xargs);
+    if (xt == X_BF16) return convert_x_bf16(X, xld, Y.n, Y.n_pad, cols, out, Y.n_pad, s, xargs);
+    return hipSuccess;
 }
 
 // Device scratch of the per-SNP stage of one sub-block: the product's
@@ -1317,7 +1328,7 @@ int gwas_stream_block_noalloc(gwas_ctx* c, const void* XR, int64_t ldx, int64_t 
     HIPCHK(c, hipStreamWaitEvent(s, c->ev_na, 0));
     size_t off[6];
     noalloc_offsets(Y, Y.na_cols, off);
-    __bf16* xs = reinterpret_cast<__bf16*>(c->nscratch + off[4]);   // dosage slices (X_BF16S)
+    __bf16* xs = reinterpret_cast<__bf16*>(c->nscratch + off[4]);   // cut dosages (X_BF16S, X_BF16)
     // the float64 mode takes its cross terms from the partial sums (no x^T W)
     const bool red = Y.precision != GWAS_FP64;
     const SubScratch sc{reinterpret_cast<double*>(c->nscratch + off[0]), reinterpret_cast<double*>(c->nscratch + off[1]),
@@ -1551,7 +1562,7 @@ int stream_group_impl(gwas_ctx* const* ctxs, int32_t nctx, const void* const* XR
                     TrmmArgs a = g->h_args_graph[i];
                     a.Xd = xp[i];
                     a.ldxd = xl[i];
-                    if (a.xt != X_BF16S) {   // bfloat16 slices stay in the context's buffer
+                    if (!x_cut(a.xt)) {   // cut dosages stay in the context's buffer
                         a.X = xp[i];
                         a.ldx = xl[i];
                     }
@@ -1700,7 +1711,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
             auto launch_all = [&]() -> int {
                 for (int64_t q = 0; q < reps; ++q) {
                     TrmmArgs ta = trmm_args_for(c, static_cast<const char*>(xptr) + (size_t)(q * w) * xld * elem,
-                                                xld, w, c->xsl ? c->xsl + (size_t)(q * w) * 3 * Y.n_pad : nullptr);
+                                                xld, w, c->xsl ? c->xsl + (size_t)(q * w) * x_cut_ld(xt, Y.n_pad) : nullptr);
                     ta.sched = c->sched_tail;
                     HIPCHK(c, trmm_stream(ta, c->s_comp));
                 }

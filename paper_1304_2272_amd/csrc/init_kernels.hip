@@ -317,6 +317,17 @@ __global__ void slice_x_bf16_kernel(const double* __restrict__ X, int64_t ldx, i
         }
 }
 
+__global__ void convert_x_bf16_kernel(const double* __restrict__ X, int64_t ldx, int64_t n, int64_t n_pad,
+                                      int64_t cols, __bf16* __restrict__ out, int64_t ldo, const TrmmArgs* xargs) {
+    if (xargs) {
+        X = static_cast<const double*>(xargs->Xd);
+        ldx = xargs->ldxd;
+    }
+    for (int64_t j = blockIdx.x; j < cols; j += gridDim.x)
+        for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x)
+            out[k + j * ldo] = k < n ? (__bf16)(float)X[k + j * ldx] : (__bf16)0.f;
+}
+
 // One workgroup per row of L^-1 (grid-stride): block max, power-of-two
 // scale, then int8 digits in pairs: each digit rounds what the ones before
 // it leave, scaled by 127 inside a pair and by 128 from one pair to the
@@ -488,6 +499,16 @@ hipError_t slice_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, 
         return hipErrorInvalidValue;
     const unsigned grid = (unsigned)std::min<int64_t>(cols, 16384);
     hipLaunchKernelGGL(slice_x_bf16_kernel, dim3(grid), dim3(256), 0, s, X, ldx, n, n_pad, cols, out, ldo, xargs);
+    return hipGetLastError();
+}
+
+hipError_t convert_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, int64_t cols, __bf16* out,
+                          int64_t ldo, hipStream_t s, const TrmmArgs* xargs) {
+    if (cols <= 0) return hipSuccess;
+    if ((!X && !xargs) || !out || n < 1 || n > n_pad || (!xargs && ldx < n) || ldo < n_pad)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(cols, 16384);
+    hipLaunchKernelGGL(convert_x_bf16_kernel, dim3(grid), dim3(256), 0, s, X, ldx, n, n_pad, cols, out, ldo, xargs);
     return hipGetLastError();
 }
 

@@ -78,12 +78,13 @@ __host__ __device__ inline int64_t consts_len(int q1, int t) { return 2 * (int64
 constexpr int64_t X_DIRECT_MAX_LD_BYTES = int64_t(4) << 20;
 
 enum AType : int { A_F64 = 0, A_F32 = 1, A_BF16 = 2, A_I8S = 3 };
-// Dosage operand of the product: float64, int8, or (the bfloat16-slice mode
-// with float64 dosages) three bfloat16 slices of each float64 column, cut
-// once per sub-block by slice_x_bf16: slice i of column j at
-// X + j*ldx + i*n_pad, zero from row n on.
-enum XType : int { X_F64 = 0, X_I8 = 1, X_BF16S = 2 };
-inline int64_t x_elem_bytes(int xt) { return xt == X_I8 ? 1 : xt == X_BF16S ? 2 : 8; }
+// Dosage operand of the product: float64, int8, or float64 dosages cut once
+// per sub-block into bfloat16 for the bfloat16 products: three slices of
+// each column for the bfloat16-slice mode (X_BF16S, slice_x_bf16: slice i of
+// column j at X + j*ldx + i*n_pad), one rounding for the bfloat16 mode
+// (X_BF16, convert_x_bf16: column j at X + j*ldx); zero from row n on.
+enum XType : int { X_F64 = 0, X_I8 = 1, X_BF16S = 2, X_BF16 = 3 };
+inline int64_t x_elem_bytes(int xt) { return xt == X_I8 ? 1 : (xt == X_BF16S || xt == X_BF16) ? 2 : 8; }
 
 // Z = L^-1 X for one sub-block, never stored: for every slice of part_rows
 // rows of Z (one wave's rows) and SNP column j the kernel writes partial
@@ -111,7 +112,7 @@ struct TrmmArgs {
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const void* Xd; int64_t ldxd;  // the dosages as handed over (float64 or int8): X and ldx,
-                                // or the columns X_BF16S slices are cut from
+                                // or the float64 columns X_BF16S and X_BF16 are cut from
     const double* C; int64_t ldc; int Qc;
     int with_cross;
     double* part; int64_t ldp;
@@ -156,6 +157,11 @@ hipError_t slice_bf16(const double* U, int64_t ld, int64_t n_pad, __bf16* out, i
 // ldxd when the kernel runs.
 hipError_t slice_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, int64_t cols, __bf16* out,
                         int64_t ldo, hipStream_t s, const TrmmArgs* xargs = nullptr);
+// Float64 dosage columns rounded to bfloat16 (through float32, as the
+// bfloat16 product's staging rounds them): out[k + j*ldo], zero for
+// n <= k < n_pad; xargs as for slice_x_bf16.
+hipError_t convert_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad, int64_t cols, __bf16* out,
+                          int64_t ldo, hipStream_t s, const TrmmArgs* xargs = nullptr);
 
 // Row r of L^-1 (column r of U, U[k + r*ld]) -> rscale[r] = 2^e >= max |L^-1(r,k)|
 // and S int8 digits A_s(r,k) in [-64, 64], written to sliced row

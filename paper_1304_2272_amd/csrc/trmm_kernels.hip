@@ -215,7 +215,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
         // there
         const int64_t xcols = std::min<int64_t>(TN, a.cols - c0);
         // bfloat16 slices of float64 dosages: the last column's third slice
-        const int64_t xbytes = ((xcols - 1) * a.ldx + (XSL ? 2 * a.n_pad : 0) + a.n) * (int64_t)sizeof(XT);
+        const int64_t xbytes = ((xcols - 1) * a.ldx + (XSL && nseg > 1 ? 2 * a.n_pad : 0) + a.n) * (int64_t)sizeof(XT);
         rsB = __builtin_amdgcn_make_buffer_rsrc(const_cast<XT*>(X + c0 * a.ldx), (short)0,
                                                 (int)((xbytes + 15) / 16 * 16), 0x00020000);
         voA = (tid >> 3) * (int)row_bytes + (tid & 7) * 16;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(S::NT, S::MINB) void trmm_stream_kernel(TrmmArgs la
                 const int col = idx / CPC, ch = idx % CPC;
                 AT* dst = reinterpret_cast<AT*>(Bs[buf] + col * ROW_STRIDE) + ch * EPC;
                 if constexpr (XSL) {
-                    // bfloat16 slices of float64 dosages go in as they are
+                    // dosages cut to bfloat16 go in as they are
                     *reinterpret_cast<u4_t*>(dst) = rb[c];
                 } else {
                     const XT* x = reinterpret_cast<const XT*>(&rb[c]);
@@ -935,10 +935,10 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
     if (at == A_I8S) return xt == X_I8 && cfg >= 0 && cfg < trmm_sliced_cfgs();
     if (cfg < 0 || cfg >= trmm_num_cfgs()) return false;
     // bfloat16 slices of float64 dosages feed the bfloat16 product only
-    if (xt == X_BF16S && at != A_BF16) return false;
+    if ((xt == X_BF16S || xt == X_BF16) && at != A_BF16) return false;
     // 64 x 128 waves fit two per SIMD only with float32 sums and one- or
     // two-byte dosages
-    if (cfg == 6) return at != A_F64 && (xt == X_I8 || xt == X_BF16S);
+    if (cfg == 6) return at != A_F64 && (xt == X_I8 || xt == X_BF16S || xt == X_BF16);
     // float64 loaded straight into LDS
     if (cfg == 7) return at == A_F64;
     if (at == A_F64) return true;
@@ -966,7 +966,7 @@ bool trmm_cfg_valid(int at, int xt, int cfg) {
 int trmm_default_cfg(int at, int xt) {
     if (at == A_I8S) return trmm_sliced_default_cfg();
     if (at == A_F64) return 7;
-    if (xt == X_I8 || xt == X_BF16S) return 6;
+    if (xt == X_I8 || xt == X_BF16S || xt == X_BF16) return 6;
     return 1;
 }
 
@@ -1009,6 +1009,7 @@ hipError_t trmm_check(const TrmmArgs& a, bool check_sched) {
     if ((reinterpret_cast<uintptr_t>(a.X) % 16) || ((a.ldx * xs) % 16)) return hipErrorInvalidValue;
     // bfloat16 dosage slices: three per column, n_pad elements each
     if (a.xt == X_BF16S && (a.at != A_BF16 || a.slices != 3 || a.ldx < 3 * a.n_pad)) return hipErrorInvalidValue;
+    if (a.xt == X_BF16 && (a.at != A_BF16 || a.slices == 3 || a.ldx < a.n_pad)) return hipErrorInvalidValue;
     if (a.at == A_I8S) {
         // the int8-slice product forms z^T z only (its mode takes the cross
         // products from x^T W)
@@ -1057,7 +1058,7 @@ hipError_t trmm_stream(const TrmmArgs& a, hipStream_t s) {
         if (a.at == A_F64) return launch_cfg<double, double>(a, s);
         if (a.at == A_F32) return launch_cfg<float, double>(a, s);
         if (a.at == A_BF16) return launch_cfg<__bf16, double>(a, s);
-    } else if (a.xt == X_BF16S) {
+    } else if (a.xt == X_BF16S || a.xt == X_BF16) {
         if (a.at == A_BF16) return launch_cfg<__bf16, __bf16>(a, s);
     } else if (a.xt == X_I8) {
         if (a.at == A_F64) return launch_cfg<double, int8_t>(a, s);

@@ -351,6 +351,25 @@ def test_fp64_direct_load_float64_dosages(n, m, dev_block, monkeypatch):
     assert normwise(b, b3) < 1e-13
 
 
+def test_bf16_float64_dosages_every_tile_shape(monkeypatch):
+    # float64 (imputed) dosages are rounded to bfloat16 once per sub-block
+    # for the bfloat16 product; every tile shape that reads them gives the
+    # oracle's answer to the bfloat16 mode's accuracy, the default among them
+    n, p, m, seed = 700, 5, 900, 124
+    prob = synth.make_problem(n, p, seed, k=300)
+    XR = synth.imputed_block(n, seed, 0, m)
+    bo, _, io = GLSOracle(prob["M"], prob["XL"], prob["Y"]).solve(XR)
+    for cfg in (None, 1, 2, 5, 6):
+        if cfg is None:
+            monkeypatch.delenv("GWAS_TRMM_CFG", raising=False)
+        else:
+            monkeypatch.setenv("GWAS_TRMM_CFG", str(cfg))
+        b, _, info = run(prob, XR, precision="bf16", x_dtype="f64", dev_block=384)
+        err = normwise(b, bo)
+        _say(f"bf16 float64 dosages, tile shape {cfg}: err {err:.3e}")
+        assert np.array_equal(info, io) and err < 1e-2
+
+
 def rounding_bound(prob, XR, b_ref, u_store, u_acc):
     """First-order bound of each SNP's normwise error of b when z = L^-1 x
     is formed from L^-1 rounded with unit roundoff u_store and summed with
