@@ -56,9 +56,6 @@ struct Layout {
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
 constexpr size_t NOALLOC_ALIGN = 256;
 
-// Offsets, in a buffer of per-SNP scratch for `cols` columns, of the
-// product's partial sums, their chunk totals and (reduced modes) the cross
-// products x^T W with their split-K partials; [4] is the end.
 // The product's dosage operand: the dosages as handed over, or float64
 // dosages cut once per sub-block into bfloat16 for the bfloat16 products
 // (three slices for the bfloat16-slice mode, one rounding for the bfloat16
@@ -72,6 +69,10 @@ bool x_cut(int xt) { return xt == X_BF16S || xt == X_BF16; }
 // elements per column of the cut dosages (their leading dimension)
 int64_t x_cut_ld(int xt, int64_t n_pad) { return xt == X_BF16S ? 3 * n_pad : n_pad; }
 
+// Offsets, in a buffer of per-SNP scratch for `cols` columns, of the
+// product's partial sums, their chunk totals, (reduced modes) the cross
+// products x^T W with their split-K partials and (bfloat16 products with
+// float64 dosages) the cut dosages; [5] is the end.
 void noalloc_offsets(const Layout& L, int64_t cols, size_t off[6]) {
     const bool red = L.precision != GWAS_FP64;
     const int xt = prod_xt_of(L.precision, L.x_dtype);
