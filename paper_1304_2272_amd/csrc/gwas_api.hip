@@ -1662,7 +1662,7 @@ int gwas_autotune(gwas_ctx* c, const void* XR, int64_t ldx, int64_t cols, int32_
             xptr = c->xbuf[0];
             xld = Y.n_pad;
         }
-        // bfloat16-slice mode with float64 dosages: the slices the products read
+        // float64 dosages of the bfloat16 products: the cut dosages the products read
         HIPCHK(c, cut_dosages(c, xptr, xld, cols, c->xsl, c->s_comp));
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
