@@ -274,7 +274,8 @@ int gwas_stream_wait(gwas_ctx* ctx);
  * aligned, ldx * element size a multiple of 16 and at most 4 MiB), b,
  * var_snp and info must all be device memory (GWAS_E_INVALID otherwise).
  * The per-SNP scratch of each sub-block (the product's partial sums, their
- * chunk totals and, in the reduced modes, the cross products x^T W) lives in
+ * chunk totals, in the reduced modes the cross products x^T W and, in the
+ * bfloat16 modes with float64 dosages, their cut bfloat16 copy) lives in
  * one static device buffer of 256 MiB that every GPU the library runs on
  * holds until the process ends; sub-blocks are as wide as fits it (at most
  * dev_block columns).  Every entry of it a call reads, that call writes
