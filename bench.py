@@ -437,8 +437,8 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
     n = 50,000, p = 8: for each half-bandwidth w, int8 dosages in pinned host
     memory queued as in the main legs.  The algorithmic work of a banded
     forward substitution is 2 n w flops per SNP; with blocks of W = w rounded
-    up to 256 rows the kernels run 3.125 n_pad W (int8 dosages with W up to
-    1,024: one launch per sub-block, each wave's triangular part stopping at
+    up to 256 rows the kernels run 3.125 n_pad W (int8 dosages with W of 256
+    or 512: one launch per sub-block, each wave's triangular part stopping at
     its own rows) or n_pad (3 W + 128) (one launch per block row)."""
     import torch
     from paper_1304_2272_amd import binding, synth
@@ -474,7 +474,7 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
         W = -(-w // 256) * 256
         # the library's choice of kernel for int8 dosages (GWAS_BAND_STEP=1
         # forces the launch per block row)
-        walk = W <= 1024 and int(os.environ.get("GWAS_BAND_STEP", "0") or 0) == 0
+        walk = W <= 512 and int(os.environ.get("GWAS_BAND_STEP", "0") or 0) == 0
         alg = 2.0 * n * w * kcols / (kms * 1e-3) / 1e12
         exe = float(n_pad) * (3.125 * W if walk else 3 * W + 128) * kcols / (kms * 1e-3) / 1e12
         rate = steps * step / el

@@ -157,7 +157,7 @@ typedef struct gwas_desc {
                                 (block bidiagonal) and each streamed block is
                                 solved by block forward substitution, about
                                 3 n W flops per SNP instead of n^2.  With
-                                int8 dosages and W <= 1,024 a sub-block walks
+                                int8 dosages and W <= 512 a sub-block walks
                                 all block rows in one launch, Z on chip; else
                                 (or with the environment variable
                                 GWAS_BAND_STEP=1 at gwas_init, a measurement

@@ -227,8 +227,243 @@ __global__ __launch_bounds__(BT_NT) void band_step_kernel(BandArgs a) {
     }
 }
 
+// The block-row step for int8 dosages with its operands loaded straight from
+// global memory into two LDS buffers (the loads of stage s + 1 issued at the
+// top of stage s, explicit waits and a bare barrier at its end), so no
+// staging registers or LDS writes are spent on them and two workgroups
+// share a CU.  Rows of U_ii^T and Gt_i^T sit unpadded in 8-row groups of
+// 128-byte stage rows, chunk c (16 bytes) of row r8 of a group in slot
+// 16 (c / 2) + 8 ((c % 2) xor (group parity)) + r8, so a fragment read (16
+// rows, one chunk) hits distinct banks whether the LDS serves 8 or 16 lanes
+// of a 16-byte read per cycle; the block row's dosages sit as bytes (16 per column and stage,
+// widened per fragment), Z_{i-1} in the layout of the rows.  Dosage bytes
+// past n belong to the next column: they meet zeros of U_ii^T in every row
+// below n, and the rows at or past n (only in the last block row, whose Z no
+// block row reads) are zeroed before the sums.  The tile, the instructions
+// per accumulator, their K order and the partial sums are band_step_kernel's.
+__global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
+    constexpr int WTM = BT_WTM, WTN = BT_WTN, NW = 8;
+    constexpr int AB = BT_M * BT_BK * 8;          // bytes of U_ii^T or Gt_i^T per stage
+    constexpr int ZB = BT_N * BT_BK * 8;          // bytes of Z_{i-1} per stage (dosages: the first 2 KB)
+    constexpr int WAIT_ALL = 7 << 4;              // vmcnt(0) lgkmcnt(0)
+    const int b = blockIdx.x;
+    const int rtiles = (int)(a.W / BT_M);
+    const int q0 = b >> 3;
+    const int64_t ct = (b & 7) + 8 * (int64_t)(q0 / rtiles);
+    const int rt = q0 % rtiles;
+    const int64_t c0 = ct * BT_N;
+    if (c0 >= a.cols) return;
+    const int64_t r0 = (int64_t)rt * BT_M;
+    const int64_t g0 = a.blk * a.W;
+
+    __shared__ __attribute__((aligned(1024))) char Abuf[2][AB];
+    __shared__ __attribute__((aligned(1024))) char Bbuf[2][ZB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / BT_WGN, wc = wave % BT_WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    const int nA = (int)(std::min<int64_t>(r0 + BT_M, a.W) / BT_BK);
+    const int nst = nA + (a.blk > 0 ? (int)(a.W / BT_BK) : 0);
+    const int64_t row_bytes = a.W * 8;
+    const u4_t rsU = buffer_words(a.Ut + r0 * a.W, (uint32_t)(BT_M * row_bytes));
+    const u4_t rsG = a.blk > 0 ? buffer_words(a.Gt + r0 * a.W, (uint32_t)(BT_M * row_bytes)) : rsU;
+    const int64_t xcols = std::min<int64_t>(BT_N, a.cols - c0);
+    const u4_t rsX = buffer_words(static_cast<const int8_t*>(a.X) + c0 * a.ldx,
+                                  (uint32_t)(((xcols - 1) * a.ldx + a.n + 15) / 16 * 16));
+    const u4_t rsZ = a.blk > 0 ? buffer_words(a.Zprev + c0 * a.ldz, (uint32_t)(xcols * a.ldz * 8)) : rsX;
+    // lane l of a load of 8 rows fetches the chunk that belongs in slot l;
+    // lane l of a dosage load, column l of its 64
+    const int lr8 = lane & 7;
+    const int lc_even = 2 * (lane >> 4) + ((lane >> 3) & 1);
+    const int lc_odd = 2 * (lane >> 4) + (((lane >> 3) & 1) ^ 1);
+    auto load = [&](int s, char* Ab, char* Bb) {
+        const bool pu = s < nA;
+        const int k0 = (pu ? s : s - nA) * BT_BK;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int q = wave + c * NW;
+            const int ch = (q & 1) ? lc_odd : lc_even;
+            load_lds16(pu ? rsU : rsG, lds_address(Ab + q * 1024),
+                       (uint32_t)((q * 8 + lr8) * row_bytes + k0 * 8 + ch * 16));
+        }
+        if (pu) {
+            if (wave < 2)
+                load_lds16(rsX, lds_address(Bb + wave * 1024),
+                           (uint32_t)((wave * 64 + lane) * a.ldx + g0 + k0));
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = wave + c * NW;
+                const int ch = (q & 1) ? lc_odd : lc_even;
+                load_lds16(rsZ, lds_address(Bb + q * 1024), (uint32_t)((q * 8 + lr8) * a.ldz * 8 + k0 * 8 + ch * 16));
+            }
+        }
+    };
+
+    d4_t acc[WTM][WTN];
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    // this lane's fragment offsets in a stage buffer: rows wr*32 + i*16 + li,
+    // chunks 2 lg + h, in the slots above; the group parity is that of li / 8
+    // for every i, so
+    // fragment i (column block j of Z_{i-1}) sits 2048 i (2048 j) bytes on
+    // from fragment 0
+    const int p8 = (li >> 3) & 1;
+    const int lbase = (li >> 3) * 1024 + lg * 256 + (li & 7) * 16;
+    const int abase = wr * WTM * 16 / 8 * 1024 + lbase;
+    const int zbase = wc * WTN * 16 / 8 * 1024 + lbase;
+    auto aoff = [&](int i, int h) { return abase + i * 2048 + ((h ^ p8) << 7); };
+    auto zoff = [&](int j, int h) { return zbase + j * 2048 + ((h ^ p8) << 7); };
+    const int xoff = (wc * WTN * 16 + li) * BT_BK + lg * 4;
+
+    // the end of every stage: its matrix instructions stay ahead of the
+    // barrier; this wave's loads of the next stage have landed, and after
+    // the barrier every wave's have, and every wave is done with this one
+    auto stage_end = [&]() {
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+        compiler_fence();
+        __builtin_amdgcn_s_barrier();
+        compiler_fence();
+    };
+    auto read_a = [&](const char* Ar, u4_t (&fa)[WTM][2]) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) fa[i][h] = *reinterpret_cast<const u4_t*>(Ar + aoff(i, h));
+    };
+    auto a_val = [&](const u4_t (&fa)[WTM][2], int i, int e) {
+        const u2_t w2 = (e & 1) ? u2_t{fa[i][e >> 1][2], fa[i][e >> 1][3]} : u2_t{fa[i][e >> 1][0], fa[i][e >> 1][1]};
+        return __builtin_bit_cast(double, w2);
+    };
+    // a stage of the U_ii^T part: dosage bytes widened per fragment
+    auto stage_u = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
+        if (s + 1 < nst) load(s + 1, An, Bn);
+        u4_t fa[WTM][2];
+        read_a(Ar, fa);
+        uint32_t fb[WTN];
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + xoff + j * 16 * BT_BK);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double xb[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * e));
+#pragma unroll
+            for (int i = 0; i < WTM; ++i) {
+                const double av = a_val(fa, i, e);
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        stage_end();
+    };
+    // a stage of the Gt_i^T part: Z_{i-1} in the layout of the rows, one
+    // 16-byte piece (two K) of each fragment at a time
+    auto stage_g = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
+        if (s + 1 < nst) load(s + 1, An, Bn);
+        u4_t fa[WTM][2];
+        read_a(Ar, fa);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            u4_t fz[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) fz[j] = *reinterpret_cast<const u4_t*>(Br + zoff(j, h));
+#pragma unroll
+            for (int e2 = 0; e2 < 2; ++e2) {
+                const int e = 2 * h + e2;
+                double zb[WTN];
+#pragma unroll
+                for (int j = 0; j < WTN; ++j)
+                    zb[j] = __builtin_bit_cast(double, e2 ? u2_t{fz[j][2], fz[j][3]} : u2_t{fz[j][0], fz[j][1]});
+#pragma unroll
+                for (int i = 0; i < WTM; ++i) {
+                    const double av = a_val(fa, i, e);
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, zb[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        stage_end();
+    };
+
+    load(0, Abuf[0], Bbuf[0]);
+    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    compiler_fence();
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
+    // both parts have an even number of stages (nA a multiple of 8, W / 16
+    // even), so each starts in buffer 0
+    for (int s = 0; s < nA; s += 2) {
+        stage_u(s, Abuf[0], Bbuf[0], Abuf[1], Bbuf[1]);
+        stage_u(s + 1, Abuf[1], Bbuf[1], Abuf[0], Bbuf[0]);
+    }
+    for (int s = nA; s < nst; s += 2) {
+        stage_g(s, Abuf[0], Bbuf[0], Abuf[1], Bbuf[1]);
+        stage_g(s + 1, Abuf[1], Bbuf[1], Abuf[0], Bbuf[0]);
+    }
+
+    // Epilogue (as band_step_kernel); rows at or past n are zeroed first
+    const int64_t rw = r0 + wr * BT_ROWS;
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (g0 + rw + i * 16 + lg + 4 * v >= a.n)
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j][v] = 0.0;
+    const int64_t pb = (g0 + rw) / BT_ROWS;
+    const int64_t cbase = c0 + wc * BT_WTN * 16 + li;
+    const int Q = a.Qc + 1;
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        const int64_t col = cbase + j * 16;
+        if (col < a.cols) {
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a.Zcur[col * a.ldz + rw + i * 16 + lg + 4 * v] = acc[i][j][v];
+        }
+    }
+    for (int qq = 0; qq < a.Qc; ++qq) {
+        const double* Cq = a.C + qq * a.ldc + g0 + rw + lg;
+        double cv[WTM][4];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + 4 * v];
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * cv[i][v];
+            sum = wave_sum16(sum);
+            const int64_t col = cbase + j * 16;
+            if (lg == 0 && col < a.cols) a.part[(pb * Q + qq) * a.ldp + col] = sum;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * acc[i][j][v];
+        sum = wave_sum16(sum);
+        const int64_t col = cbase + j * 16;
+        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
+    }
+}
+
 // The whole block forward substitution of a sub-block in one launch, for
-// int8 dosages and blocks of W = 128 WTM rows (256 to 1,024).  Workgroup b
+// int8 dosages and blocks of W = 128 WTM rows (256 or 512).  Workgroup b
 // owns SNP columns [b TN, (b + 1) TN) and walks every block row; Z_{i-1} of
 // its columns stays in LDS as float64 from one block row to the next, and
 // the dosages of the block row sit there as bytes.  Wave w holds 16 WTM rows
@@ -486,14 +721,25 @@ hipError_t band_step(const BandArgs& a, hipStream_t s) {
     const int64_t ctiles = (a.cols + BT_N - 1) / BT_N;
     const int64_t grid = 8 * (a.W / BT_M) * ((ctiles + 7) / 8);
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    if (a.xt == X_I8)
-        hipLaunchKernelGGL(band_step_kernel<int8_t>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
-    else
+    if (a.xt == X_I8) {
+        // 32-bit buffer offsets: a tile's dosage columns up to the block
+        // row's last stage, its rows of U_ii^T and Gt_i^T, its Z columns
+        if ((BT_N - 1) * a.ldx + (a.blk + 1) * a.W > INT32_MAX || (int64_t)BT_M * a.W * 8 > INT32_MAX ||
+            (int64_t)BT_N * a.ldz * 8 > INT32_MAX || (reinterpret_cast<uintptr_t>(a.Zcur) % 16))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(band_lds_kernel, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    } else {
         hipLaunchKernelGGL(band_step_kernel<double>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 
-bool band_walk_fits(int xt, int64_t W) { return xt == X_I8 && W >= 256 && W <= 1024; }
+// The walk beats one launch per block row (band_lds_kernel) up to W = 512:
+// 10.98 against 16.96 ms per 16,384 columns at W = 256 and 20.3 against
+// 24.9 at 512 (n = 50,000); from 768 on the launch per block row is faster
+// (34.8 against 45.2 ms at 768, 42.1 against 58.1 at 1,024), since 16
+// columns per workgroup double the walk's L2 reads per instruction.
+bool band_walk_fits(int xt, int64_t W) { return xt == X_I8 && (W == 256 || W == 512); }
 
 hipError_t band_walk(const BandArgs& a, hipStream_t s) {
     if (a.cols <= 0) return hipSuccess;
@@ -507,9 +753,8 @@ hipError_t band_walk(const BandArgs& a, hipStream_t s) {
         (reinterpret_cast<uintptr_t>(a.Gt) % 16))
         return hipErrorInvalidValue;
     // columns per workgroup: 32 once a sub-block fills the chip with them,
-    // else 16; 16 always for W of 768 and 1,024, whose Z columns fill the
-    // LDS.  W = 256: two workgroups per CU (75 KB of LDS, at most 128 VGPRs
-    // each); larger W keeps 64 to 128 rows per wave in more registers, one
+    // else 16.  W = 256: two workgroups per CU (75 KB of LDS, at most 128
+    // VGPRs each); W = 512 keeps 64 rows per wave in more registers, one
     // workgroup per CU.
     const bool wide = a.cols > 8192;
     const int tn = wide ? 32 : 16;
@@ -520,17 +765,11 @@ hipError_t band_walk(const BandArgs& a, hipStream_t s) {
             hipLaunchKernelGGL((band_walk_kernel<2, 2, 4>), dim3((unsigned)grid), dim3(512), 0, s, a);
         else
             hipLaunchKernelGGL((band_walk_kernel<2, 1, 4>), dim3((unsigned)grid), dim3(512), 0, s, a);
-    } else if (a.W == 512) {
+    } else {
         if (wide)
             hipLaunchKernelGGL((band_walk_kernel<4, 2, 2>), dim3((unsigned)grid), dim3(512), 0, s, a);
         else
             hipLaunchKernelGGL((band_walk_kernel<4, 1, 2>), dim3((unsigned)grid), dim3(512), 0, s, a);
-    } else if (a.W == 768) {
-        const int64_t g16 = (a.cols + 15) / 16;
-        hipLaunchKernelGGL((band_walk_kernel<6, 1, 2>), dim3((unsigned)g16), dim3(512), 0, s, a);
-    } else {
-        const int64_t g16 = (a.cols + 15) / 16;
-        hipLaunchKernelGGL((band_walk_kernel<8, 1, 2>), dim3((unsigned)g16), dim3(512), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -237,8 +237,8 @@ struct BandArgs {
 };
 hipError_t band_step(const BandArgs& a, hipStream_t s);
 int band_part_rows();   // rows per partial-sum slice of band_step and band_walk (32)
-// All nb block rows of a sub-block in one launch (int8 dosages, W of 256 to
-// 1,024: band_walk_fits): Ut and Gt point at block row 0's U_00 and Gt_0, Z
+// All nb block rows of a sub-block in one launch (int8 dosages, W of 256 or
+// 512: band_walk_fits): Ut and Gt point at block row 0's U_00 and Gt_0, Z
 // stays on chip (Zprev, Zcur unused); the same partial sums as nb calls of
 // band_step.
 bool band_walk_fits(int xt, int64_t W);

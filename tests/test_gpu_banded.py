@@ -30,6 +30,8 @@ def normwise(b, bref):
     (5000, 1000, 3, 1, 900, "i8", 0),       # W = 1024, 5 block rows
     (1290, 256, 5, 1, 333, "f64", 128),     # w = W exactly
     (1800, 400, 4, 3, 500, "i8", 0),        # W = 512 in one launch, three traits
+    (6000, 1500, 4, 1, 700, "i8", 0),       # W = 1,536: one launch per block row, loaded straight into LDS
+    (4000, 1300, 3, 2, 300, "i8", 128),     # W = 1,536, ragged last block row, two traits
 ])
 def test_banded_vs_oracle(n, w, p, t, m, x_dtype, dev_block):
     seed = 5100 + n + w
@@ -109,12 +111,11 @@ def test_banded_calls_that_need_the_dense_factor_are_refused():
     (3000, 200, 5, 9000),      # W = 256, 12 block rows; 32 columns per workgroup, ragged last workgroup
     (2600, 400, 4, 9000),      # W = 512, 6 block rows (the last one partly past n)
     (1100, 256, 3, 700),       # W = 256, 5 block rows; 16 columns per workgroup
-    (2000, 700, 3, 600),       # W = 768, 3 block rows
-    (2500, 1000, 4, 300),      # W = 1,024, 3 block rows
+    (1500, 450, 3, 600),       # W = 512, 3 block rows; 16 columns per workgroup
 ])
 def test_banded_one_launch_equals_block_row_launches(n, w, p, m, monkeypatch):
-    # int8 dosages with W of 256 to 1,024 run every block row of a sub-block
-    # in one launch, Z kept on chip; the launch per block row (GWAS_BAND_STEP=1)
+    # int8 dosages with W of 256 or 512 run every block row of a sub-block in
+    # one launch, Z kept on chip; the launch per block row (GWAS_BAND_STEP=1)
     # gives the same bits, a SNP's result does not depend on the call it
     # comes in, and a sample of SNPs agrees with the oracle on the dense M
     seed = 5500 + n + w
