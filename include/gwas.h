@@ -156,7 +156,9 @@ typedef struct gwas_desc {
                                 W = w rounded up to a multiple of 256 rows
                                 (block bidiagonal) and each streamed block is
                                 solved by block forward substitution, about
-                                3 n W flops per SNP instead of n^2.  With
+                                3 n W flops per SNP instead of n^2, for
+                                n <= 2,000,000 with float64 dosages and
+                                n <= 16,000,000 with int8.  With
                                 int8 dosages and W <= 512 a sub-block walks
                                 all block rows in one launch, Z on chip; else
                                 (or with the environment variable

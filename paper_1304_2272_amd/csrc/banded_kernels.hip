@@ -5,7 +5,7 @@
 // Forward substitution then runs block row by block row,
 //     Z_i = L_ii^-1 (X_i - E_i Z_{i-1}) = U_ii^T X_i + Gt_i^T Z_{i-1},
 // with U_ii = L_ii^-T and Gt_i = -E_i^T U_ii formed at set-up.  One launch
-// of band_step_kernel is one block row for every SNP column of a sub-block:
+// of band_lds_kernel is one block row for every SNP column of a sub-block:
 // a float64 matrix-core product with K = [the triangular part of U_ii^T |
 // all of Gt_i^T] against [X_i | Z_{i-1}], which stores Z_i for the next
 // block row and writes the same partial sums as the dense product (S_BL,
@@ -24,224 +24,29 @@ constexpr int BT_WGN = 2;                             // waves along the columns
 constexpr int BT_BK = 16;                             // K per stage (one 128-byte row of doubles)
 constexpr int BT_ROWS = BT_WTM * 16;                  // rows of a partial-sum slice
 
-// One BT_M x BT_N tile of Z_i per workgroup.  Stages of 16 K go global ->
-// registers -> LDS (double buffered); within a stage lane group g = lane/16
+// One BT_M x BT_N tile of Z_i per workgroup, stages of 16 K, its operands
+// loaded straight from global memory into two LDS buffers (the loads of
+// stage s + 1 issued at the top of stage s, explicit waits and a bare
+// barrier at its end), so no staging registers or LDS writes are spent on
+// them and two workgroups share a CU.  Within a stage lane group g = lane/16
 // supplies the contiguous K slice [4g, 4g + 4) to both operands, one K per
 // instruction (the 16x16x4 float64 instruction sums its K in any order the
 // two operands agree on).  Workgroup b runs on XCD b % 8: the row tiles of a
 // column tile run on one XCD, so its dosage and Z panels stay in that L2.
-template <typename XT>
-__global__ __launch_bounds__(BT_NT) void band_step_kernel(BandArgs a) {
-    constexpr int EPC = 16 / (int)sizeof(XT);          // dosage elements per 16-byte chunk
-    const int b = blockIdx.x;
-    const int rtiles = (int)(a.W / BT_M);
-    const int q = b >> 3;
-    const int64_t ct = (b & 7) + 8 * (int64_t)(q / rtiles);
-    const int rt = q % rtiles;
-    const int64_t c0 = ct * BT_N;
-    if (c0 >= a.cols) return;
-    const int64_t r0 = (int64_t)rt * BT_M;               // first row of the tile inside the block
-    const int64_t g0 = a.blk * a.W;                      // first global row of the block
-
-    __shared__ __attribute__((aligned(16))) char As[2][BT_M * ROW_STRIDE];
-    __shared__ __attribute__((aligned(16))) char Bs[2][BT_N * ROW_STRIDE];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / BT_WGN, wc = wave % BT_WGN;
-    const int li = lane & 15, lg = lane >> 4;
-
-    // stages: the U_ii^T part runs K up to the tile's last row (U_ii^T is
-    // lower triangular), the Gt_i^T part all W (none in block row 0)
-    const int nA = (int)(std::min<int64_t>(r0 + BT_M, a.W) / BT_BK);
-    const int nst = nA + (a.blk > 0 ? (int)(a.W / BT_BK) : 0);
-    const XT* X = reinterpret_cast<const XT*>(a.X);
-
-    d4_t acc[BT_WTM][BT_WTN];
-#pragma unroll
-    for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-        for (int j = 0; j < BT_WTN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-
-    // staged operands of one stage: two 16-byte chunks of A and of B per thread
-    u4_t ra[2], rb[2];
-    auto load = [&](int s) {
-        const bool pa = s < nA;
-        const int64_t k0 = (int64_t)(pa ? s : s - nA) * BT_BK;
-        const double* Ab = pa ? a.Ut : a.Gt;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int idx = tid + c * BT_NT;
-            const int row = idx >> 3, ch = idx & 7;
-            ra[c] = *reinterpret_cast<const u4_t*>(Ab + (r0 + row) * a.W + k0 + 2 * ch);
-        }
-        if (!pa) {
-            // Z_{i-1}: float64, rows 0..W-1 of every column of the sub-block
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int idx = tid + c * BT_NT;
-                const int64_t col = c0 + (idx >> 3);
-                rb[c] = col < a.cols ? *reinterpret_cast<const u4_t*>(a.Zprev + col * a.ldz + k0 + 2 * ((idx & 7)))
-                                     : u4_t{0u, 0u, 0u, 0u};
-            }
-            return;
-        }
-        // X_i: rows g0 + k0 .. of the dosages, zero past n and past the block
-        if constexpr (sizeof(XT) == 8) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int idx = tid + c * BT_NT;
-                const int64_t col = c0 + (idx >> 3);
-                const int64_t g = g0 + k0 + 2 * (idx & 7);
-                const XT* src = X + col * a.ldx + g;
-                if (col < a.cols && g + 2 <= a.n) {
-                    rb[c] = *reinterpret_cast<const u4_t*>(src);
-                } else {
-                    double t2[2] __attribute__((aligned(16)));
-                    t2[0] = (col < a.cols && g < a.n) ? (double)src[0] : 0.0;
-                    t2[1] = 0.0;
-                    rb[c] = *reinterpret_cast<const u4_t*>(t2);
-                }
-            }
-        } else {
-            // one 16-byte chunk (16 K of one column) for each of the first
-            // BT_N threads
-            if (tid < BT_N) {
-                const int64_t col = c0 + tid;
-                const int64_t g = g0 + k0;
-                const XT* src = X + col * a.ldx + g;
-                if (col < a.cols && g + EPC <= a.n) {
-                    rb[0] = *reinterpret_cast<const u4_t*>(src);
-                } else {
-                    XT tmp[EPC] __attribute__((aligned(16)));
-#pragma unroll
-                    for (int e = 0; e < EPC; ++e) tmp[e] = (col < a.cols && g + e < a.n) ? src[e] : (XT)0;
-                    rb[0] = *reinterpret_cast<const u4_t*>(tmp);
-                }
-            }
-        }
-    };
-    auto store = [&](int buf, int s) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int idx = tid + c * BT_NT;
-            *reinterpret_cast<u4_t*>(As[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = ra[c];
-        }
-        if (sizeof(XT) == 8 || s >= nA) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int idx = tid + c * BT_NT;
-                *reinterpret_cast<u4_t*>(Bs[buf] + (idx >> 3) * ROW_STRIDE + (idx & 7) * 16) = rb[c];
-            }
-        } else if (tid < BT_N) {
-            // int8 dosages of one column, expanded to float64
-            const int8_t* x8 = reinterpret_cast<const int8_t*>(&rb[0]);
-            double* dst = reinterpret_cast<double*>(Bs[buf] + tid * ROW_STRIDE);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) dst[e] = (double)x8[e];
-        }
-    };
-
-    load(0);
-    store(0, 0);
-    __syncthreads();
-    for (int s = 0; s < nst; ++s) {
-        const int buf = s & 1;
-        const bool more = s + 1 < nst;
-        if (more) load(s + 1);
-        double fa[BT_WTM][4], fb[BT_WTN][4];
-        // a lane's 32 bytes of K of one row of A or column of B, as two
-        // 16-byte reads
-        auto frag4 = [&](const char* p, double (&f)[4]) {
-            const u4_t lo = *reinterpret_cast<const u4_t*>(p);
-            const u4_t hi = *reinterpret_cast<const u4_t*>(p + 16);
-            f[0] = __builtin_bit_cast(double, u2_t{lo[0], lo[1]});
-            f[1] = __builtin_bit_cast(double, u2_t{lo[2], lo[3]});
-            f[2] = __builtin_bit_cast(double, u2_t{hi[0], hi[1]});
-            f[3] = __builtin_bit_cast(double, u2_t{hi[2], hi[3]});
-        };
-#pragma unroll
-        for (int i = 0; i < BT_WTM; ++i)
-            frag4(As[buf] + (wr * BT_ROWS + i * 16 + li) * ROW_STRIDE + lg * 32, fa[i]);
-#pragma unroll
-        for (int j = 0; j < BT_WTN; ++j)
-            frag4(Bs[buf] + (wc * BT_WTN * 16 + j * 16 + li) * ROW_STRIDE + lg * 32, fb[j]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-                for (int j = 0; j < BT_WTN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][e], fb[j][e], acc[i][j], 0, 0, 0);
-        // the other buffer held stage s - 1, which every wave finished
-        // reading before the previous barrier
-        if (more) store(buf ^ 1, s + 1);
-        __syncthreads();
-    }
-
-    // Epilogue.  Element v of accumulator (i, j) holds row
-    // r0 + wr*32 + i*16 + lg + 4v and column c0 + wc*64 + j*16 + li.
-    const int64_t rw = r0 + wr * BT_ROWS;
-    const int64_t pb = (g0 + rw) / BT_ROWS;
-    const int64_t cbase = c0 + wc * BT_WTN * 16 + li;
-    const int Q = a.Qc + 1;
-#pragma unroll
-    for (int j = 0; j < BT_WTN; ++j) {
-        const int64_t col = cbase + j * 16;
-        if (col < a.cols) {
-#pragma unroll
-            for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) a.Zcur[col * a.ldz + rw + i * 16 + lg + 4 * v] = acc[i][j][v];
-        }
-    }
-    for (int qq = 0; qq < a.Qc; ++qq) {
-        const double* Cq = a.C + qq * a.ldc + g0 + rw + lg;
-        double cv[BT_WTM][4];
-#pragma unroll
-        for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) cv[i][v] = Cq[i * 16 + 4 * v];
-#pragma unroll
-        for (int j = 0; j < BT_WTN; ++j) {
-            double sum = 0.0;
-#pragma unroll
-            for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * cv[i][v];
-            sum = wave_sum16(sum);
-            const int64_t col = cbase + j * 16;
-            if (lg == 0 && col < a.cols) a.part[(pb * Q + qq) * a.ldp + col] = sum;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < BT_WTN; ++j) {
-        double sum = 0.0;
-#pragma unroll
-        for (int i = 0; i < BT_WTM; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sum += acc[i][j][v] * acc[i][j][v];
-        sum = wave_sum16(sum);
-        const int64_t col = cbase + j * 16;
-        if (lg == 0 && col < a.cols) a.part[(pb * Q + Q - 1) * a.ldp + col] = sum;
-    }
-}
-
-// The block-row step for int8 dosages with its operands loaded straight from
-// global memory into two LDS buffers (the loads of stage s + 1 issued at the
-// top of stage s, explicit waits and a bare barrier at its end), so no
-// staging registers or LDS writes are spent on them and two workgroups
-// share a CU.  Rows of U_ii^T and Gt_i^T sit unpadded in 8-row groups of
-// 128-byte stage rows, chunk c (16 bytes) of row r8 of a group in slot
+// Rows of U_ii^T and Gt_i^T sit unpadded in 8-row groups of 128-byte stage
+// rows, chunk c (16 bytes) of row r8 of a group in slot
 // 16 (c / 2) + 8 ((c % 2) xor (group parity)) + r8, so a fragment read (16
 // rows, one chunk) hits distinct banks whether the LDS serves 8 or 16 lanes
-// of a 16-byte read per cycle; the block row's dosages sit as bytes (16 per column and stage,
-// widened per fragment), Z_{i-1} in the layout of the rows.  Dosage bytes
-// past n belong to the next column: they meet zeros of U_ii^T in every row
-// below n, and the rows at or past n (only in the last block row, whose Z no
-// block row reads) are zeroed before the sums.  The tile, the instructions
-// per accumulator, their K order and the partial sums are band_step_kernel's.
+// of a 16-byte read per cycle; Z_{i-1} and float64 dosages sit in the same
+// layout, int8 dosages as bytes (16 per column and stage, widened per
+// fragment).  Int8 dosage bytes past n belong to the next column: they meet
+// zeros of U_ii^T in every row below n, and the rows at or past n (only in
+// the last block row, whose Z no block row reads) are zeroed before the
+// sums; float64 dosages at or past n are read as zero, since the stride's
+// padding may hold anything (NaN included).
+template <typename XT>
 __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
+    constexpr bool XD = sizeof(XT) == 8;          // float64 dosages: laid out as the rows
     constexpr int WTM = BT_WTM, WTN = BT_WTN, NW = 8;
     constexpr int AB = BT_M * BT_BK * 8;          // bytes of U_ii^T or Gt_i^T per stage
     constexpr int ZB = BT_N * BT_BK * 8;          // bytes of Z_{i-1} per stage (dosages: the first 2 KB)
@@ -270,8 +75,8 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
     const u4_t rsU = buffer_words(a.Ut + r0 * a.W, (uint32_t)(BT_M * row_bytes));
     const u4_t rsG = a.blk > 0 ? buffer_words(a.Gt + r0 * a.W, (uint32_t)(BT_M * row_bytes)) : rsU;
     const int64_t xcols = std::min<int64_t>(BT_N, a.cols - c0);
-    const u4_t rsX = buffer_words(static_cast<const int8_t*>(a.X) + c0 * a.ldx,
-                                  (uint32_t)(((xcols - 1) * a.ldx + a.n + 15) / 16 * 16));
+    const u4_t rsX = buffer_words(static_cast<const char*>(a.X) + c0 * a.ldx * (int64_t)sizeof(XT),
+                                  (uint32_t)((((xcols - 1) * a.ldx + a.n) * (int64_t)sizeof(XT) + 15) / 16 * 16));
     const u4_t rsZ = a.blk > 0 ? buffer_words(a.Zprev + c0 * a.ldz, (uint32_t)(xcols * a.ldz * 8)) : rsX;
     // lane l of a load of 8 rows fetches the chunk that belongs in slot l;
     // lane l of a dosage load, column l of its 64
@@ -288,10 +93,18 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
             load_lds16(pu ? rsU : rsG, lds_address(Ab + q * 1024),
                        (uint32_t)((q * 8 + lr8) * row_bytes + k0 * 8 + ch * 16));
         }
-        if (pu) {
+        if (pu && !XD) {
             if (wave < 2)
                 load_lds16(rsX, lds_address(Bb + wave * 1024),
                            (uint32_t)((wave * 64 + lane) * a.ldx + g0 + k0));
+        } else if (pu) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = wave + c * NW;
+                const int ch = (q & 1) ? lc_odd : lc_even;
+                load_lds16(rsX, lds_address(Bb + q * 1024),
+                           (uint32_t)((q * 8 + lr8) * a.ldx * 8 + (g0 + k0) * 8 + ch * 16));
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -340,34 +153,10 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
         const u2_t w2 = (e & 1) ? u2_t{fa[i][e >> 1][2], fa[i][e >> 1][3]} : u2_t{fa[i][e >> 1][0], fa[i][e >> 1][1]};
         return __builtin_bit_cast(double, w2);
     };
-    // a stage of the U_ii^T part: dosage bytes widened per fragment
-    auto stage_u = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
-        if (s + 1 < nst) load(s + 1, An, Bn);
-        u4_t fa[WTM][2];
-        read_a(Ar, fa);
-        uint32_t fb[WTN];
-#pragma unroll
-        for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + xoff + j * 16 * BT_BK);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            double xb[WTN];
-#pragma unroll
-            for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * e));
-#pragma unroll
-            for (int i = 0; i < WTM; ++i) {
-                const double av = a_val(fa, i, e);
-#pragma unroll
-                for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[j], acc[i][j], 0, 0, 0);
-            }
-        }
-        stage_end();
-    };
-    // a stage of the Gt_i^T part: Z_{i-1} in the layout of the rows, one
-    // 16-byte piece (two K) of each fragment at a time
-    auto stage_g = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
-        if (s + 1 < nst) load(s + 1, An, Bn);
-        u4_t fa[WTM][2];
-        read_a(Ar, fa);
+    // the products of a stage whose B side holds float64 values in the
+    // layout of the rows (Z_{i-1}, or float64 dosages), one 16-byte piece
+    // (two K) of each fragment at a time
+    auto stage_b64 = [&](const u4_t (&fa)[WTM][2], const char* Br) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             u4_t fz[WTN];
@@ -389,6 +178,59 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
                 }
             }
         }
+    };
+    // a stage of the U_ii^T part: dosage bytes widened per fragment, or
+    // float64 dosages in the layout of the rows with K at or past n read as
+    // zero (the bytes past a column's n belong to whatever follows it)
+    auto stage_u = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
+        if (s + 1 < nst) load(s + 1, An, Bn);
+        u4_t fa[WTM][2];
+        read_a(Ar, fa);
+        if constexpr (XD) {
+            // 8 bytes of a fragment at a time, K at or past n read as zero
+            const int kl = (int)std::min<int64_t>(a.n - (g0 + s * BT_BK), BT_BK) - 4 * lg;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double xb[WTN];
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) {
+                    const double v = *reinterpret_cast<const double*>(Br + zoff(j, e >> 1) + (e & 1) * 8);
+                    xb[j] = e < kl ? v : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < WTM; ++i) {
+                    const double av = a_val(fa, i, e);
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            stage_end();
+            return;
+        }
+        uint32_t fb[WTN];
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) fb[j] = *reinterpret_cast<const uint32_t*>(Br + xoff + j * 16 * BT_BK);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double xb[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) xb[j] = (double)(int)(int8_t)(fb[j] >> (8 * e));
+#pragma unroll
+            for (int i = 0; i < WTM; ++i) {
+                const double av = a_val(fa, i, e);
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        stage_end();
+    };
+    // a stage of the Gt_i^T part: Z_{i-1} in the layout of the rows
+    auto stage_g = [&](int s, const char* Ar, const char* Br, char* An, char* Bn) {
+        if (s + 1 < nst) load(s + 1, An, Bn);
+        u4_t fa[WTM][2];
+        read_a(Ar, fa);
+        stage_b64(fa, Br);
         stage_end();
     };
 
@@ -408,7 +250,9 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
         stage_g(s + 1, Abuf[1], Bbuf[1], Abuf[0], Bbuf[0]);
     }
 
-    // Epilogue (as band_step_kernel); rows at or past n are zeroed first
+    // Epilogue.  Element v of accumulator (i, j) holds row
+    // r0 + wr*32 + i*16 + lg + 4v and column c0 + wc*64 + j*16 + li; rows at
+    // or past n are zeroed first
     const int64_t rw = r0 + wr * BT_ROWS;
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
@@ -476,7 +320,7 @@ __global__ __launch_bounds__(BT_NT, 4) void band_lds_kernel(BandArgs a) {
 // each SIMD gets the same share of the triangular U_ii^T part.
 // Per accumulator the matrix instructions, their K order (the triangular
 // part up to the wave's last row, then all of Gt_i^T) and the partial sums
-// per 32-row slice are those of band_step_kernel; the stages it runs past a
+// per 32-row slice are those of band_lds_kernel; the stages it runs past a
 // wave's last row multiply zeros of U_ii^T, so both kernels give the same
 // values.  MINW waves per SIMD: 4 for two workgroups per CU.
 template <int WTM, int WTN, int MINW>
@@ -721,16 +565,15 @@ hipError_t band_step(const BandArgs& a, hipStream_t s) {
     const int64_t ctiles = (a.cols + BT_N - 1) / BT_N;
     const int64_t grid = 8 * (a.W / BT_M) * ((ctiles + 7) / 8);
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    if (a.xt == X_I8) {
-        // 32-bit buffer offsets: a tile's dosage columns up to the block
-        // row's last stage, its rows of U_ii^T and Gt_i^T, its Z columns
-        if ((BT_N - 1) * a.ldx + (a.blk + 1) * a.W > INT32_MAX || (int64_t)BT_M * a.W * 8 > INT32_MAX ||
-            (int64_t)BT_N * a.ldz * 8 > INT32_MAX || (reinterpret_cast<uintptr_t>(a.Zcur) % 16))
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL(band_lds_kernel, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
-    } else {
-        hipLaunchKernelGGL(band_step_kernel<double>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
-    }
+    // 32-bit buffer offsets: a tile's dosage columns up to the block row's
+    // last stage, its rows of U_ii^T and Gt_i^T, its Z columns
+    if (((BT_N - 1) * a.ldx + (a.blk + 1) * a.W) * (int64_t)xs > INT32_MAX || (int64_t)BT_M * a.W * 8 > INT32_MAX ||
+        (int64_t)BT_N * a.ldz * 8 > INT32_MAX || (reinterpret_cast<uintptr_t>(a.Zcur) % 16))
+        return hipErrorInvalidValue;
+    if (a.xt == X_I8)
+        hipLaunchKernelGGL(band_lds_kernel<int8_t>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(band_lds_kernel<double>, dim3((unsigned)grid), dim3(BT_NT), 0, s, a);
     return hipGetLastError();
 }
 

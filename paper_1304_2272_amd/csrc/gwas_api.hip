@@ -90,6 +90,8 @@ void noalloc_offsets(const Layout& L, int64_t cols, size_t off[6]) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+constexpr int64_t BAND_MAX_N_F64 = 2000000, BAND_MAX_N_I8 = 16000000;
+
 bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
                  int32_t x_dtype, int64_t band = 0) {
     if (band < 0 || (band > 0 && precision != GWAS_FP64)) return false;
@@ -102,6 +104,9 @@ bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t pre
     // exact int32 sums of the paired digits (|127 A_hi + A_lo| <= 8,192 per
     // element) need n_pad < 2^18
     if (precision == GWAS_INT8_SLICED && n > ((int64_t)1 << 18) - NPAD_ALIGN) return false;
+    // the banded product addresses 128 dosage columns of a tile with 32-bit
+    // offsets: 128 n_pad bytes of int8, 1,024 n_pad of float64, below 2^31
+    if (band > 0 && n > (x_dtype == GWAS_X_F64 ? BAND_MAX_N_F64 : BAND_MAX_N_I8)) return false;
     return true;
 }
 

@@ -100,6 +100,12 @@ def test_banded_descriptor_validated_before_device(lib):
     assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 100, 101, 0) > 0
     assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 100, 100, 0) == 0     # ldm < band + 1
     assert lib.gwas_workspace_bytes_band(1000, 4, 1, 0, 0, 1, 0) == 0         # band < 1
+    # the banded product's 32-bit dosage offsets: n up to 2,000,000 with
+    # float64 dosages, 16,000,000 with int8
+    assert lib.gwas_workspace_bytes_band(2000000, 4, 1, 0, 100, 101, 0) > 0
+    assert lib.gwas_workspace_bytes_band(2000001, 4, 1, 0, 100, 101, 0) == 0
+    assert lib.gwas_workspace_bytes_band(16000000, 4, 1, 0, 100, 101, 1) > 0
+    assert lib.gwas_workspace_bytes_band(16000001, 4, 1, 0, 100, 101, 1) == 0
     # far smaller than the dense factor at n = 20,000 with w = 500
     assert lib.gwas_workspace_bytes_band(20000, 4, 1, 0, 500, 501, 1) < lib.gwas_workspace_bytes(20000, 4, 1, 0, 0, 1) / 4
     for precision, ldm in ((1, 17), (0, 5)):     # float32 arithmetic; ldm < band + 1

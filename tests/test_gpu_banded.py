@@ -141,3 +141,33 @@ def test_banded_one_launch_equals_block_row_launches(n, w, p, m, monkeypatch):
     verr = float(np.max(np.abs(v1[pick] - vo) / vo))
     _say(f"  bit-equal to the per-block-row launches; oracle sample normwise {err:.3e}, var {verr:.3e}")
     assert err < TOL and verr < TOL
+
+
+@pytest.mark.parametrize("n,w,p,m", [
+    (1291, 200, 4, 700),       # W = 256, n odd: the last stage ends one K into a 16-byte piece
+    (2999, 700, 3, 500),       # W = 768, 4 block rows, the last one mostly past n
+])
+def test_banded_float64_dosages_strided_nan_padding(n, w, p, m):
+    # float64 dosages in device memory with a stride past n whose padding
+    # holds NaN: every K at or past n is read as zero, so the padding (and
+    # the next column's first values) never reach b or var
+    import torch
+    seed = 5600 + n + w
+    _say(f"banded float64 strided dosages n={n} w={w} p={p} m={m}")
+    prob = synth.banded_problem(n, p, seed, w)
+    XR = synth.snp_block(n, seed, 0, m)
+    ld = n + 7 if n % 2 else n + 6
+    dev = torch.device("cuda:0")
+    Xp = torch.full((m, ld), float("nan"), dtype=torch.float64, device=dev)
+    Xp[:, :n] = torch.from_numpy(XR).to(dev)
+    with binding.GwasContext(prob["M_band"], prob["XL"], prob["Y"], band=w) as ctx:
+        b, var, info = ctx.stream_block(Xp[:, :n])
+        bh, vh, _ = ctx.stream_block(XR)
+    b, var, info = b.cpu().numpy(), var.cpu().numpy(), info.cpu().numpy()
+    bo, vo, io = GLSOracle(synth.band_to_dense(prob["M_band"]), prob["XL"], prob["Y"]).solve(XR)
+    err = normwise(b, bo)
+    verr = float(np.max(np.abs(var - vo) / vo))
+    _say(f"  normwise {err:.3e}, var {verr:.3e}")
+    assert np.array_equal(info, io) and (io == 0).all()
+    assert err < TOL and verr < TOL
+    assert np.array_equal(b, bh) and np.array_equal(var, vh)
