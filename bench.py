@@ -432,18 +432,21 @@ def compact_c5(seed, m=100_000, step=50_000):
             "inputs": "float64 dosages device-resident"}
 
 
-def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
+def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2, x_dtype="i8"):
     """Banded M (relatives grouped near the diagonal, Section 5.1) at
-    n = 50,000, p = 8: for each half-bandwidth w, int8 dosages in pinned host
-    memory queued as in the main legs.  The algorithmic work of a banded
-    forward substitution is 2 n w flops per SNP; with blocks of W = w rounded
-    up to 256 rows the kernels run 3.125 n_pad W (int8 dosages with W of 256
-    or 512: one launch per sub-block, each wave's triangular part stopping at
-    its own rows) or n_pad (3 W + 128) (one launch per block row)."""
+    n = 50,000, p = 8: for each half-bandwidth w, dosages in pinned host
+    memory queued as in the main legs (int8 by default; float64 dosages in
+    blocks of 16,384 SNPs).  The algorithmic work of a banded forward
+    substitution is 2 n w flops per SNP; with blocks of W = w rounded up to
+    256 rows the kernels run 3.125 n_pad W (int8 dosages with W of 256 or
+    512: one launch per sub-block, each wave's triangular part stopping at its
+    own rows) or n_pad (3 W + 128) (one launch per block row)."""
     import torch
     from paper_1304_2272_amd import binding, synth
     dev = torch.device("cuda:0")
-    blocks = host_blocks(n, seed, step, steps, torch.int8, dev)
+    if x_dtype == "f64":
+        step = min(step, 16_384)
+    blocks = host_blocks(n, seed, step, steps, torch.int8 if x_dtype == "i8" else torch.float64, dev)
     X = [torch.from_numpy(blocks.array[i]) for i in range(steps)]
     out_b = PinnedHost((step * steps, 1, p), np.float64)
     out_v = PinnedHost((step * steps,), np.float64)
@@ -456,7 +459,7 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
         XL, Y = torch.from_numpy(pr["XL"]).to(dev), torch.from_numpy(pr["Y"]).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx = binding.GwasContext(Mb, XL, Y, x_dtype="i8", band=w)
+        ctx = binding.GwasContext(Mb, XL, Y, x_dtype=x_dtype, band=w)
         torch.cuda.synchronize()
         init_s = time.perf_counter() - t0
         ctx.stream_block_async(X[0], (ob[:step], ov[:step], oi[:step]))     # warm-up
@@ -474,7 +477,7 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
         W = -(-w // 256) * 256
         # the library's choice of kernel for int8 dosages (GWAS_BAND_STEP=1
         # forces the launch per block row)
-        walk = W <= 512 and int(os.environ.get("GWAS_BAND_STEP", "0") or 0) == 0
+        walk = x_dtype == "i8" and W <= 512 and int(os.environ.get("GWAS_BAND_STEP", "0") or 0) == 0
         alg = 2.0 * n * w * kcols / (kms * 1e-3) / 1e12
         exe = float(n_pad) * (3.125 * W if walk else 3 * W + 128) * kcols / (kms * 1e-3) / 1e12
         rate = steps * step / el
@@ -486,14 +489,15 @@ def compact_banded(seed, widths, n=50_000, p=8, step=50_000, steps=2):
                        "executed_tflops": exe, "executed_frac": exe / PEAK_TFLOPS["fp64"],
                        "kernel": "one launch per sub-block" if walk else "one launch per block row",
                        "rank_flags": int((oi.numpy()[:steps * step] != 0).sum())}
-        log(f"[banded w={w}] init {init_s:.2f} s, {rate:.1f} SNP/s; product {alg:.2f} TFLOP/s algorithmic "
+        log(f"[banded w={w}{'' if x_dtype == 'i8' else ' f64'}] init {init_s:.2f} s, {rate:.1f} SNP/s; product {alg:.2f} TFLOP/s algorithmic "
             f"(2nw), {exe:.2f} executed ({exe / PEAK_TFLOPS['fp64']:.3f} of peak)")
         del Mb, XL, Y, pr
         torch.cuda.empty_cache()
     for x in (out_b, out_v, out_i, blocks):
         x.close()
-    return {"n": n, "p": p, "m_per_w": steps * step, "x_dtype": "int8", "precision": "fp64",
-            "inputs": "int8 dosages in pinned host memory, queued blocks", "by_half_bandwidth": res}
+    xname = "int8" if x_dtype == "i8" else "float64"
+    return {"n": n, "p": p, "m_per_w": steps * step, "x_dtype": xname, "precision": "fp64",
+            "inputs": f"{xname} dosages in pinned host memory, queued blocks", "by_half_bandwidth": res}
 
 
 def run_main(args):
@@ -568,7 +572,8 @@ def run_main(args):
             others["n10000_p4_grad"] = compact_c5(args.seed + 4)
         if "banded_n50000_p8" in pick:
             others["banded_n50000_p8"] = compact_banded(args.seed + 5,
-                                                        [int(x) for x in args.band_widths.split(",") if x])
+                                                        [int(x) for x in args.band_widths.split(",") if x],
+                                                        x_dtype=args.band_x_dtype)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -635,6 +640,7 @@ def main():
     ap.add_argument("--c2-blocks", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--band-widths", default="256,1024,4096", help="half-bandwidths of the banded-M leg")
+    ap.add_argument("--band-x-dtype", choices=["i8", "f64"], default="i8", help="dosage type of the banded-M leg")
     ap.add_argument("--slices", type=int, default=SLICES, help="int8 digits per entry of L^-1 in the int8 leg (4..6)")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--cpu-snps", type=int, default=512)
