@@ -91,11 +91,11 @@ extern "C" {
                                   exact int32 sums and one float64
                                   combination; cross products and the p x p
                                   solve as in GWAS_FP32_REFINE.  Needs
-                                  x_dtype = GWAS_X_I8 and n <= 261,888.
+                                  x_dtype = GWAS_X_I8 and n <= 260,096.
                                   The default tile shape adds both digits of
-                                  a pair into one sum against centred
-                                  dosages x - 1, which needs dosages 0, 1 or
-                                  2: a SNP with any other value gets NaN in
+                                  a pair into one sum (the hi digit against
+                                  127 (x - 1), in int8 only for dosages 0, 1
+                                  or 2; the lo digit against x): a SNP with any other value gets NaN in
                                   b and var_snp (tile shape 0, through
                                   GWAS_TRMM_CFG or gwas_autotune, takes any
                                   int8 value).                            */

@@ -91,6 +91,7 @@ void noalloc_offsets(const Layout& L, int64_t cols, size_t off[6]) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int64_t BAND_MAX_N_F64 = 2000000, BAND_MAX_N_I8 = 16000000;
+constexpr int64_t INT8_SLICED_MAX_N = 260096;     // a multiple of 256
 
 bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t precision,
                  int32_t x_dtype, int64_t band = 0) {
@@ -101,9 +102,10 @@ bool sizes_valid(int64_t n, int32_t p, int32_t t, int64_t dev_block, int32_t pre
     if (precision < GWAS_FP64 || precision > GWAS_BF16X3_REFINE) return false;
     if (x_dtype != GWAS_X_F64 && x_dtype != GWAS_X_I8) return false;
     if (precision == GWAS_INT8_SLICED && x_dtype != GWAS_X_I8) return false;
-    // exact int32 sums of the paired digits (|127 A_hi + A_lo| <= 8,192 per
-    // element) need n_pad < 2^18
-    if (precision == GWAS_INT8_SLICED && n > ((int64_t)1 << 18) - NPAD_ALIGN) return false;
+    // exact int32 sums of the paired digits against the dosages
+    // (|127 A_hi (x - 1) + A_lo x| <= 8,256 per element) need
+    // 8,256 n_pad < 2^31
+    if (precision == GWAS_INT8_SLICED && n > INT8_SLICED_MAX_N) return false;
     // the banded product addresses 128 dosage columns of a tile with 32-bit
     // offsets: 128 n_pad bytes of int8, 1,024 n_pad of float64, below 2^31
     if (band > 0 && n > (x_dtype == GWAS_X_F64 ? BAND_MAX_N_F64 : BAND_MAX_N_I8)) return false;

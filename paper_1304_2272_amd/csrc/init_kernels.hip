@@ -333,8 +333,8 @@ __global__ void convert_x_bf16_kernel(const double* __restrict__ X, int64_t ldx,
 // it leave, scaled by 127 inside a pair and by 128 from one pair to the
 // next (a subtraction of a nearby integer is exact; the scaling by 127
 // rounds at 2^-53 of the digit, far below the last digit's half unit).
-// The row sums of the paired digits over k < n are exact int32 sums
-// (|127 A_hi + A_lo| <= 8,192, n < 2^18).
+// The row sums 127 sum_{k<n} A_hi of the hi digits of each pair are exact
+// int32 sums (|127 A_hi| <= 8,128, n < 2^18).
 __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ U, int64_t ld,
                                                          int64_t n_pad, int64_t n, int S,
                                                          int8_t* __restrict__ A, int64_t lda,
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
             for (int sl = 0; sl < S; ++sl) {
                 const double q = rint(t);
                 A[(base + sl * 16) * lda + k] = (int8_t)q;
-                if (k < n && sl / 2 < SLICE_PAIRS_MAX) dsum[sl / 2] += (sl & 1) ? (int)q : 127 * (int)q;
+                if (k < n && !(sl & 1) && sl / 2 < SLICE_PAIRS_MAX) dsum[sl / 2] += 127 * (int)q;
                 t = (t - q) * ((sl & 1) ? 128.0 : 127.0);
             }
         }

@@ -107,8 +107,8 @@ struct TrmmArgs {
                                 // bfloat16-slice product (row r holds its slices one after
                                 // another, n_pad elements each), else 0
     const double* rscale;       // A_I8S: power-of-two scale of each row of L^-1
-    const int* rsum;            // A_I8S: rsum[p * n_pad + r] = sum over k < n of the
-                                // paired digits 127 A_2p(r, k) + A_2p+1(r, k)
+    const int* rsum;            // A_I8S: rsum[p * n_pad + r] = sum over k < n of
+                                // 127 A_2p(r, k), the hi digit of pair p
     const void* Ut; int64_t ldu; int64_t n_pad;
     const void* X; int64_t ldx; int64_t n; int64_t cols;
     const void* Xd; int64_t ldxd;  // the dosages as handed over (float64 or int8): X and ldx,
@@ -169,7 +169,7 @@ hipError_t convert_x_bf16(const double* X, int64_t ldx, int64_t n, int64_t n_pad
 // (hi A_2p, lo A_2p+1) with a radix of 127 inside a pair and 128 between
 // pairs:  L^-1(r,k)/rscale[r] = sum_p D_p(r,k) w_p up to half a unit of the
 // last digit, D_p = 127 A_2p + A_2p+1 (A_S = 0 for odd S) and
-// w_p = 2^(-6-7p) / 127^(2p+1).  rsum[p * n_pad + r] = sum_{k < n} D_p(r,k).
+// w_p = 2^(-6-7p) / 127^(2p+1).  rsum[p * n_pad + r] = 127 sum_{k < n} A_2p(r,k).
 constexpr int SLICE_PAIRS_MAX = 3;
 hipError_t slice_rows(const double* U, int64_t ld, int64_t n_pad, int64_t n, int S, int8_t* A,
                       int64_t lda, double* rscale, int* rsum, hipStream_t s);

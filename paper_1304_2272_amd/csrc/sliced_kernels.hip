@@ -374,27 +374,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_sliced_lds_kernel(TrmmArg
     }
 }
 
-// Centred dosages of the paired-digit product: bytes x in {0, 1, 2} map to
-// x - 1 (lo) and 127 (x - 1) (hi), both in int8, by a byte permute with the
-// dosage bytes as selectors into a constant table (the same table in both
-// halves of the permute's source pair).
-__device__ __forceinline__ uint32_t centred_lo(uint32_t x) {
-    return __builtin_amdgcn_perm(0x000100ffu, 0x000100ffu, x);
-}
+// The hi operand of the paired-digit product: bytes x in {0, 1, 2} map to
+// 127 (x - 1) in int8 by a byte permute with the dosage bytes as selectors
+// into a constant table (the same table in both halves of the permute's
+// source pair).
 __device__ __forceinline__ uint32_t centred_hi(uint32_t x) {
     return __builtin_amdgcn_perm(0x007f0081u, 0x007f0081u, x);
 }
 
 // The product with each pair of digits in one int32 accumulator: the
 // instruction for the hi digit A_2p meets 127 (x - 1) and the one for the lo
-// digit A_2p+1 meets x - 1, both adding to acc_p = sum_k D_p(r, k) (x_k - 1)
-// (|acc_p| <= 8,192 n_pad < 2^31); the epilogue adds the exact row sums
-// sum_{k<n} D_p(r, k) to recover sum_k D_p(r, k) x_k, the same integers the
-// other shapes form.  Half the accumulators let a wave hold 16 real rows x
-// WTN * 16 columns with all S digits, so each fragment read from LDS feeds
-// more matrix instructions.  A stage is 64 bytes of K; staged dosage
-// elements past n or past the block read as 1 (centred 0).  Dosages must be
-// 0, 1 or 2.
+// digit A_2p+1 meets the dosage bytes themselves, both adding to
+// acc_p = sum_k D_p(r, k) x_k - 127 sum_k A_2p(r, k), D_p = 127 A_2p + A_2p+1
+// (|127 A_2p (x - 1) + A_2p+1 x| <= 8,256 per k, so |acc_p| < 2^31 for
+// n_pad <= 260,096); the epilogue adds the exact row sums
+// 127 sum_{k<n} A_2p(r, k) to recover sum_k D_p(r, k) x_k, the same integers
+// the other shapes form.  Only the hi operand takes a byte permute.  Half
+// the accumulators let a wave hold 16 real rows x WTN * 16 columns with all
+// S digits, so each fragment read from LDS feeds more matrix instructions.
+// A stage is 64 bytes of K; staged dosage elements past n or past the block
+// read as 1 (they meet zero digits).  Dosages must be 0, 1 or 2.
 template <int S, int WGM, int WGN, int WTN, bool GROUPED>
 __global__ __launch_bounds__(64 * WGM * WGN) void trmm_paired_kernel(TrmmArgs la) {
     constexpr int NP = (S + 1) / 2;
@@ -502,7 +501,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_paired_kernel(TrmmArgs la
 #pragma unroll
         for (int j = 0; j < WTN; ++j)
             fb[j] = *reinterpret_cast<const u4_t*>(Bs[buf] + (wc * WTN * 16 + j * 16 + li) * RS + lg * 16);
-        // hi digits against 127 (x - 1), then lo digits against x - 1: the two
+        // hi digits against 127 (x - 1), then lo digits against x: the two
         // instructions into one accumulator are WTN * NP instructions apart
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -510,7 +509,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void trmm_paired_kernel(TrmmArgs la
 #pragma unroll
             for (int j = 0; j < WTN; ++j)
 #pragma unroll
-                for (int w = 0; w < 4; ++w) xb[j][w] = h == 0 ? centred_hi(fb[j][w]) : centred_lo(fb[j][w]);
+                for (int w = 0; w < 4; ++w) xb[j][w] = h == 0 ? centred_hi(fb[j][w]) : fb[j][w];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 if (2 * p + h >= S) continue;
@@ -678,8 +677,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
 #pragma unroll
             for (int j = 0; j < WTN; ++j)
                 fb[j] = *reinterpret_cast<const u4_t*>(Br + (wc * WTN * 16 + j * 16 + li) * BK + slot);
-            // hi digits against 127 (x - 1), then lo digits against x - 1,
-            // one dosage fragment at a time (its byte maps just before its
+            // hi digits against 127 (x - 1), then lo digits against x, one
+            // dosage fragment at a time (its byte map just before its
             // instructions); the two instructions into one accumulator are
             // WTN * NP instructions apart
 #pragma unroll
@@ -688,7 +687,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void trmm_paired_lds_kernel(Trmm
                 for (int j = 0; j < WTN; ++j) {
                     u4_t xb;
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) xb[w] = h == 0 ? centred_hi(fb[j][w]) : centred_lo(fb[j][w]);
+                    for (int w = 0; w < 4; ++w) xb[w] = h == 0 ? centred_hi(fb[j][w]) : fb[j][w];
 #pragma unroll
                     for (int p = 0; p < NP; ++p) {
                         if (2 * p + h >= S) continue;

@@ -51,10 +51,12 @@ def test_workspace_bytes(lib):
                  (100, 4, 0, 0, 0, 0), (100, 4, 1, -1, 0, 0), (100, 4, 1, 0, 7, 0),
                  (100, 4, 1, 0, 0, 5), (100, 4, 257, 0, 0, 0)]:
         assert lib.gwas_workspace_bytes(*args) == 0, args
-    # int8 slices: the paired digits' exact int32 sums need n_pad < 2^18
-    # (|127 A_hi + A_lo| <= 8,192 per element)
-    assert lib.gwas_workspace_bytes(2 ** 18 - 256, 4, 1, 0, 3, 1) > 0
-    assert lib.gwas_workspace_bytes(2 ** 18 - 255, 4, 1, 0, 3, 1) == 0
+    # int8 slices: the paired digits' exact int32 sums need 8,256 n_pad < 2^31
+    # (|127 A_hi (x - 1) + A_lo x| <= 127 * 64 + 64 * 2 per element): n up
+    # to 260,096, the largest multiple of 256 that keeps them
+    assert 8256 * 260096 < 2 ** 31 <= 8256 * (260096 + 256)
+    assert lib.gwas_workspace_bytes(260096, 4, 1, 0, 3, 1) > 0
+    assert lib.gwas_workspace_bytes(260097, 4, 1, 0, 3, 1) == 0
     assert lib.gwas_workspace_bytes(2 ** 18, 4, 1, 0, 0, 1) > 0          # float64 has no such limit
 
 
